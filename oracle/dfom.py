@@ -1,0 +1,381 @@
+"""Algorithm DFOM (Sec. 3) with the inner Algorithm FOM (Sec. 2.1), FP64 NumPy.
+
+TEST INFRASTRUCTURE ONLY: see the package docstring.  Plain and slow on
+purpose: every product is taken directly from its definition, with no
+blocking, fusion or reuse beyond what the algorithms state.
+
+QP class: Sec. 2, eq. original_primal, with K = R^p_- (G u + g <= 0) and
+the box U = [lb, ub].
+
+Readings of points the paper leaves open (each is listed again in the
+design notes):
+  * Inner stopping test (Step 1, eq. duquad_in).  The criterion needs the
+    unknown d_rho(mu).  It is replaced by a computable certificate that is
+    a rigorous upper bound on L_rho(x, mu) - d_rho(mu):
+      - at a point x of the box with the exact gradient g = grad phi(x):
+        min(FW gap  sum_i max(g_i (x_i - lb_i), g_i (x_i - ub_i)),
+            ||pi||^2 / (2 sigma))       [second term only when sigma > 0]
+        with pi the minimum-norm element of g + N_U(x);
+      - after a projected step x = [y - grad phi(y)/L]_U, with the gradient
+        mapping G_L = L (y - x):
+        min(sum_i max(G_i (y_i - lb_i), G_i (y_i - ub_i)) - ||G_L||^2/(2L),
+            ||G_L||^2 (1/sigma - 1/L) / 2)  [second term only when sigma > 0].
+    With rho = 0 the exact-gradient form is used at every inner iterate.
+    With rho > 0 the exact form is used for the warm start x^0 and the
+    gradient-mapping form after each step (it needs no extra product).
+    The loop also stops at the iteration count k_in of Sec. 5 (natural log,
+    rounded up), which by Lemma lemma_sublin_dfg already implies the
+    criterion when the constants are exact.
+  * Inner variant: FGM_sigma when sigma_in > 0, FGM otherwise (Sec. 2.1);
+    sigma_in = lambda_min(Q) (the strong convexity of L_rho(., mu) that
+    survives the [.]_+ term).  Inner momentum restarts every outer
+    iteration; only x is warm-started (Sec. 3, warm start).
+  * First inner start: the projection of the origin onto U.
+  * lambda^0 = 0 unless given (Sec. 4), lambda^{-1} = lambda^0, theta_1 = 1.
+  * Primal average over j = 1..k with weights theta_j (eq. average_primal).
+  * Outer test (the paper's experiments use the unknown F*): on the
+    candidate x (last or averaged iterate)
+        ||[Gx+g]_+|| <= eps_out max(1, ||g||),
+        F(x) - LB   <= eps_out max(1, |F(x)|),
+        ||lambda^k|| ||[Gx+g]_+|| <= eps_out max(1, |F(x)|),
+    with LB = max_j (dbar_j - gap_j) over multipliers where weak duality
+    holds (mu^j >= 0 when rho = 0, every mu^j when rho > 0).
+  * Last iterate of DFGM is u(lambda^k) (eq. last_primal): when ubar^k
+    passes the test, one more inner solve at lambda^k, warm-started from
+    ubar^k, is tested and returned if it passes; otherwise the iteration
+    continues from ubar^k unchanged (the extra solve only raises LB).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+DGM, DFGM = 0, 1
+LAST, AVG = 0, 1
+CERT, FIXED = 0, 1
+INNER_AUTO, INNER_GM, INNER_FGM, INNER_FGM_SIGMA = 0, 1, 2, 3
+
+STATUS_OK = 0
+STATUS_MAXITER = 1
+
+
+@dataclass
+class Options:
+    method: int = DFGM
+    output: int = LAST
+    inner_rule: int = CERT
+    inner_variant: int = INNER_AUTO
+    eps_out: float = 1e-4
+    eps_in: float = 1e-6
+    rho: float = 0.0
+    max_outer: int = 10000
+    max_inner: int = 0            # 0: use the k_in count of Sec. 5
+    lam_min: Optional[float] = None
+    lam_max: Optional[float] = None
+    G_norm2: Optional[float] = None
+    log_vectors: int = 0          # outer iterations whose vectors are logged
+
+
+@dataclass
+class Constants:
+    lam_min: float
+    lam_max: float
+    G_norm2: float
+    Ld: float
+    alpha: float
+    L_in: float
+    sigma_in: float
+    beta_in: float
+    D_U: float
+    k_in_max: int
+    Kd_nonneg: bool
+
+
+@dataclass
+class Result:
+    x: np.ndarray
+    lam: np.ndarray
+    F: float
+    LB: float
+    feas: float
+    status: int
+    outer_iters: int
+    inner_iters: int
+    consts: Constants
+    log: List[dict] = field(default_factory=list)
+
+
+# ----------------------------------------------------------------------------
+# Constants (Sec. 2 eq. Ld, Sec. 3 Step 1, Sec. 5 k_in)
+# ----------------------------------------------------------------------------
+
+def problem_constants(Q, G, lb, ub, rho: float, eps_in: float,
+                      lam_min=None, lam_max=None, G_norm2=None,
+                      max_inner: int = 0) -> Constants:
+    """L_d, the outer step 1/(2 L_d), the inner L and sigma, beta, D_U, k_in.
+
+    Spectral quantities default to exact dense eigen/singular values."""
+    if lam_min is None or lam_max is None:
+        ev = np.linalg.eigvalsh(Q)
+        lam_min = float(ev[0]) if lam_min is None else lam_min
+        lam_max = float(ev[-1]) if lam_max is None else lam_max
+    if G_norm2 is None:
+        G_norm2 = float(np.linalg.norm(G, 2) ** 2) if G.shape[0] > 0 else 0.0
+    denom = lam_min + rho * G_norm2
+    if G_norm2 == 0.0:
+        Ld = 0.0
+    elif denom <= 0.0:
+        raise ValueError("lambda_min(Q) = 0 needs rho > 0 (Sec. 2, Case 2)")
+    else:
+        Ld = G_norm2 / denom                       # eq. Ld
+    alpha = 0.0 if Ld == 0.0 else 1.0 / (2.0 * Ld)  # Algorithm DFOM step 2
+    L_in = lam_max + rho * G_norm2                  # Sec. 3, Step 1
+    sigma_in = max(lam_min, 0.0)
+    sqL, sqs = math.sqrt(L_in), math.sqrt(sigma_in)
+    beta_in = (sqL - sqs) / (sqL + sqs)             # FGM_sigma, Sec. 2.1
+    D_U = float(np.linalg.norm(ub - lb))
+    if max_inner > 0:
+        k_in = int(max_inner)
+    elif sigma_in > 0.0:                            # Sec. 5, k_in
+        arg = L_in * D_U * D_U / eps_in
+        k_in = int(math.ceil(math.sqrt(L_in / sigma_in) * math.log(arg))) + 1 if arg > 1.0 else 1
+    else:
+        k_in = int(math.ceil(math.sqrt(2.0 * L_in * D_U * D_U / eps_in)))
+    k_in = max(k_in, 1)
+    return Constants(lam_min, lam_max, G_norm2, Ld, alpha, L_in, sigma_in,
+                     beta_in, D_U, k_in, lam_min > 0.0)
+
+
+# ----------------------------------------------------------------------------
+# Objective, (augmented) Lagrangian, dual gradient (Sec. 2, Sec. 3)
+# ----------------------------------------------------------------------------
+
+def objective(Q, q, u) -> float:
+    """F(u) = 1/2 u^T Q u + q^T u (eq. original_primal)."""
+    return float(0.5 * u @ (Q @ u) + q @ u)
+
+
+def slack(G, g, u, lam, rho: float) -> np.ndarray:
+    """s(u, lambda): [G u + g + lambda/rho]_K for rho > 0, 0 for rho = 0 (Sec. 2)."""
+    if rho > 0.0:
+        return np.minimum(G @ u + g + lam / rho, 0.0)   # projection onto R^p_-
+    return np.zeros(G.shape[0])
+
+
+def lagrangian(Q, q, G, g, u, lam, rho: float) -> float:
+    """L_rho(u, lambda) of eq. auglag1 with K = R^p_- (dist_K(v) = ||[v]_+||)."""
+    r = G @ u + g
+    if rho > 0.0:
+        v = np.maximum(r + lam / rho, 0.0)
+        return objective(Q, q, u) + 0.5 * rho * float(v @ v) - float(lam @ lam) / (2.0 * rho)
+    return objective(Q, q, u) + float(lam @ r)
+
+
+def dual_gradient(G, g, u, lam, rho: float) -> np.ndarray:
+    """bar-nabla d_rho(lambda) = G u + g - s(u, lambda) (eq. inexact_framework)."""
+    return G @ u + g - slack(G, g, u, lam, rho)
+
+
+def inner_gradient(Q, q, G, g, u, mu, rho: float) -> np.ndarray:
+    """Gradient in u of L_rho(u, mu).
+
+    rho = 0: Q u + q + G^T mu.  rho > 0: Q u + q + G^T [mu + rho (G u + g)]_+
+    (derivative of (rho/2) ||[G u + g + mu/rho]_+||^2)."""
+    if rho > 0.0:
+        return Q @ u + q + G.T @ np.maximum(mu + rho * (G @ u + g), 0.0)
+    return Q @ u + q + G.T @ mu
+
+
+# ----------------------------------------------------------------------------
+# Inner certificates
+# ----------------------------------------------------------------------------
+
+def inner_certificate(x, grad, lb, ub, sigma: float) -> float:
+    """Upper bound on phi(x) - min_U phi at a box point x with gradient grad."""
+    fw = float(np.sum(np.maximum(grad * (x - lb), grad * (x - ub))))
+    if sigma <= 0.0:
+        return fw
+    pi = grad.copy()
+    at_lb = x <= lb
+    at_ub = x >= ub
+    pi[at_lb] = np.minimum(grad[at_lb], 0.0)
+    pi[at_ub] = np.maximum(grad[at_ub], 0.0)
+    pi[at_lb & at_ub] = 0.0
+    return min(fw, float(pi @ pi) / (2.0 * sigma))
+
+
+def gradmap_certificate(y, x, L: float, lb, ub, sigma: float) -> float:
+    """Upper bound on phi(x) - min_U phi for x = [y - grad phi(y)/L]_U.
+
+    With G_L = L (y - x): phi(x) - phi(z) <= <G_L, y - z> - ||G_L||^2/(2L)
+    - (sigma/2) ||z - y||^2 for every z in U; maximise over z."""
+    gm = L * (y - x)
+    gg = float(gm @ gm)
+    fw = float(np.sum(np.maximum(gm * (y - lb), gm * (y - ub)))) - gg / (2.0 * L)
+    if sigma <= 0.0:
+        return fw
+    return min(fw, 0.5 * gg * (1.0 / sigma - 1.0 / L))
+
+
+# ----------------------------------------------------------------------------
+# Algorithm FOM on the inner problem (Sec. 2.1)
+# ----------------------------------------------------------------------------
+
+def _inner_beta_schedule(variant: int, sigma: float, beta_in: float):
+    """Yields beta_1, beta_2, ... of Algorithm FOM for the chosen variant."""
+    if variant == INNER_AUTO:
+        variant = INNER_FGM_SIGMA if sigma > 0.0 else INNER_FGM
+    if variant == INNER_GM:
+        while True:
+            yield 0.0
+    elif variant == INNER_FGM_SIGMA:
+        while True:
+            yield beta_in
+    else:  # FGM: theta_1 = 1, theta_{k+1} = (1 + sqrt(1 + 4 theta_k^2)) / 2
+        th = 1.0
+        while True:
+            th_next = 0.5 * (1.0 + math.sqrt(1.0 + 4.0 * th * th))
+            yield (th - 1.0) / th_next
+            th = th_next
+
+
+def fom_inner(Q, q, G, g, lb, ub, mu, rho: float, c: Constants, x0,
+              eps_in: float, rule: int = CERT, variant: int = INNER_AUTO):
+    """Approximate u(mu) by Algorithm FOM(L_rho(., mu), U) from x^0 = y^1 = x0.
+
+    Returns (x, steps, gap) with gap the certificate value of x."""
+    L, sigma, k_max = c.L_in, c.sigma_in, c.k_in_max
+    betas = _inner_beta_schedule(variant, sigma, c.beta_in)
+
+    def grad(u):
+        return inner_gradient(Q, q, G, g, u, mu, rho)
+
+    def done(gap, t):
+        return (rule == CERT and gap <= eps_in) or t >= k_max
+
+    if rho == 0.0:
+        x_prev = x = x0.copy()
+        t = 0
+        while True:
+            gap = inner_certificate(x, grad(x), lb, ub, sigma)
+            if done(gap, t):
+                return x, t, gap
+            if t == 0:
+                y = x                                   # y^1 = x^0
+            else:
+                y = x + next(betas) * (x - x_prev)      # y^{t+1}
+            x_prev = x
+            x = np.clip(y - grad(y) / L, lb, ub)        # x^{t+1}
+            t += 1
+    # rho > 0: gradient at y only; exact certificate at x^0, gradient-mapping after
+    x_prev = x0.copy()
+    y = x0.copy()
+    t = 0
+    while True:
+        gy = grad(y)
+        if t == 0:
+            gap = inner_certificate(x0, gy, lb, ub, sigma)
+            if rule == CERT and gap <= eps_in:
+                return x0.copy(), 0, gap
+        x = np.clip(y - gy / L, lb, ub)
+        t += 1
+        gap = gradmap_certificate(y, x, L, lb, ub, sigma)
+        if done(gap, t):
+            return x, t, gap
+        y = x + next(betas) * (x - x_prev)
+        x_prev = x
+
+
+# ----------------------------------------------------------------------------
+# Algorithm DFOM (Sec. 3) with last / averaged primal output (Sec. 4)
+# ----------------------------------------------------------------------------
+
+def _outer_test(Q, q, G, g, x, lam, LB, eps, gnorm):
+    Fx = objective(Q, q, x)
+    feas = float(np.linalg.norm(np.maximum(G @ x + g, 0.0)))
+    scale = max(1.0, abs(Fx))
+    ok = (feas <= eps * max(1.0, gnorm) and Fx - LB <= eps * scale
+          and float(np.linalg.norm(lam)) * feas <= eps * scale)
+    return ok, Fx, feas
+
+
+def dfom_solve(qp, opts: Options, consts: Optional[Constants] = None,
+               x_start=None, lam_start=None) -> Result:
+    """Inexact (augmented) dual first-order method DFOM(d_rho, K_d)."""
+    Q, q, G, g, lb, ub = qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub
+    rho = float(opts.rho)
+    c = consts or problem_constants(Q, G, lb, ub, rho, opts.eps_in,
+                                    opts.lam_min, opts.lam_max, opts.G_norm2,
+                                    opts.max_inner)
+    p = G.shape[0]
+    gnorm = float(np.linalg.norm(g))
+
+    def proj_Kd(v):
+        return np.maximum(v, 0.0) if c.Kd_nonneg else v
+
+    lam = proj_Kd(np.zeros(p) if lam_start is None else np.asarray(lam_start, float))
+    lam_prev = lam.copy()                          # lambda^{-1} = lambda^0
+    mu = lam.copy()                                # mu^1 = lambda^0
+    theta = 1.0                                    # theta_1
+    S = 0.0
+    u_sum = np.zeros_like(q)
+    x_warm = np.clip(np.zeros_like(q), lb, ub) if x_start is None else np.asarray(x_start, float).copy()
+    LB = -math.inf
+    inner_total = 0
+    log: List[dict] = []
+    last = None
+
+    for k in range(1, opts.max_outer + 1):
+        # Step 1: ubar^k approximately minimises L_rho(., mu^k) over U
+        u, t, gap = fom_inner(Q, q, G, g, lb, ub, mu, rho, c, x_warm,
+                              opts.eps_in, opts.inner_rule, opts.inner_variant)
+        inner_total += t
+        dg = dual_gradient(G, g, u, mu, rho)
+        dbar = lagrangian(Q, q, G, g, u, mu, rho)
+        if rho > 0.0 or np.all(mu >= 0.0):         # weak duality holds at mu^k
+            LB = max(LB, dbar - gap)
+        # Step 2: projected inexact dual gradient step
+        lam_k = proj_Kd(mu + c.alpha * dg)
+        # Step 3: momentum (DGM: theta = 1; DFGM: theta rule)
+        if opts.method == DFGM:
+            theta_next = 0.5 * (1.0 + math.sqrt(1.0 + 4.0 * theta * theta))
+        else:
+            theta_next = 1.0
+        beta = (theta - 1.0) / theta_next
+        mu_next = lam_k + beta * (lam_k - lam_prev)
+        # eq. average_primal, weights theta_j, j = 1..k
+        S += theta
+        u_sum = u_sum + theta * u
+        u_hat = u_sum / S
+        cand = u if opts.output == LAST else u_hat
+        ok, Fx, feas = _outer_test(Q, q, G, g, cand, lam_k, LB, opts.eps_out, gnorm)
+        entry = dict(k=k, t=t, gap=gap, dbar=dbar, LB=LB, theta=theta, S=S,
+                     F=Fx, feas=feas, lam_norm=float(np.linalg.norm(lam_k)), passed=ok)
+        if k <= opts.log_vectors:
+            entry.update(mu=mu.copy(), u=u.copy(), lam=lam_k.copy())
+        result_x = cand
+        if ok and opts.output == LAST and opts.method == DFGM:
+            # last primal iterate u(lambda^k), eq. last_primal
+            u2, t2, gap2 = fom_inner(Q, q, G, g, lb, ub, lam_k, rho, c, u,
+                                     opts.eps_in, opts.inner_rule, opts.inner_variant)
+            inner_total += t2
+            if rho > 0.0 or np.all(lam_k >= 0.0):
+                LB = max(LB, lagrangian(Q, q, G, g, u2, lam_k, rho) - gap2)
+            ok, Fx, feas = _outer_test(Q, q, G, g, u2, lam_k, LB, opts.eps_out, gnorm)
+            entry.update(extra_t=t2, extra_gap=gap2, LB=LB, F2=Fx, feas2=feas, passed2=ok)
+            result_x = u2
+        log.append(entry)
+        last = (result_x, lam_k, Fx, feas)
+        if ok:
+            return Result(result_x.copy(), lam_k.copy(), Fx, LB, feas, STATUS_OK,
+                          k, inner_total, c, log)
+        lam_prev = lam_k
+        mu = mu_next
+        theta = theta_next
+        x_warm = u
+    x, lam_k, Fx, feas = last
+    return Result(x.copy(), lam_k.copy(), Fx, LB, feas, STATUS_MAXITER,
+                  opts.max_outer, inner_total, c, log)

@@ -1,0 +1,269 @@
+"""Seeded synthetic QP generators.
+
+This module only draws problem data; it holds none of the solver's
+arithmetic.  Both the CPU oracle tests and the HIP path take their inputs
+from here, so the two sides always see the same bits.
+
+Problem class (Sec. 2, eq. original_primal):
+    min 1/2 u^T Q u + q^T u   s.t.  G u + g <= 0,  lb <= u <= ub.
+
+The paper's experiments use "random QPs" without a published generator
+(Sec. 6.2, 6.3) and motivate the method with linear MPC (Sec. 1, Sec. 2).
+The recipes below stand in for those workloads:
+
+* random_dense_qp: Q = A^T A / n + reg*I with A (2n x n) i.i.d. N(0,1),
+  q ~ N(0,1), G (p x n) i.i.d. N(0,1), g = -(G x0) - s with
+  x0 ~ U(-.5,.5)^n and s ~ U(.1,1)^p so that x0 is strictly feasible,
+  box [-1, 1].  Draw order A, q, G, x0, s from numpy's PCG64.
+* mpc_system / mpc_instance: condensed linear MPC with nx states, nu
+  inputs, horizon N; input box |u| <= 1 and state bounds |x_k| <= 5 as
+  2*N*nx rows of G; the Hessian and G are shared, q and g depend on x0.
+* uneven_batch: many independent random_dense_qp instances of uneven n.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+
+@dataclass
+class QP:
+    """One QP in the form of Sec. 2 with inequality constraints."""
+    Q: np.ndarray          # (n, n) float64, symmetric
+    q: np.ndarray          # (n,)
+    G: np.ndarray          # (p, n)
+    g: np.ndarray          # (p,)
+    lb: np.ndarray         # (n,)
+    ub: np.ndarray         # (n,)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.Q.shape[0])
+
+    @property
+    def p(self) -> int:
+        return int(self.G.shape[0])
+
+    def rounded(self, dtype) -> "QP":
+        """Same QP with Q and G rounded (RNE) to `dtype` and promoted back.
+
+        The FP32 storage path solves exactly this problem."""
+        Q = self.Q.astype(dtype).astype(np.float64)
+        G = self.G.astype(dtype).astype(np.float64)
+        return QP(Q, self.q.copy(), G, self.g.copy(), self.lb.copy(),
+                  self.ub.copy(), dict(self.meta, storage=np.dtype(dtype).name))
+
+
+def _rng(seed) -> np.random.Generator:
+    if isinstance(seed, np.random.Generator):
+        return seed
+    return np.random.default_rng(seed)
+
+
+def random_dense_qp(n: int, p: int, seed=0, reg: float = 0.1,
+                    box: float = 1.0, s_lo: float = 0.1,
+                    s_hi: float = 1.0) -> QP:
+    """Random dense strongly convex QP with a strictly feasible point."""
+    rng = _rng(seed)
+    A = rng.standard_normal((2 * n, n))
+    Q = (A.T @ A) / n
+    del A
+    Q = 0.5 * (Q + Q.T)
+    Q[np.diag_indices(n)] += reg
+    q = rng.standard_normal(n)
+    G = rng.standard_normal((p, n))
+    x0 = rng.uniform(-0.5, 0.5, n)
+    s = rng.uniform(s_lo, s_hi, p)
+    g = -(G @ x0) - s
+    lb = np.full(n, -box)
+    ub = np.full(n, box)
+    return QP(Q, q, G, g, lb, ub,
+              dict(kind="random_dense", n=n, p=p, reg=reg,
+                   seed=seed if not isinstance(seed, np.random.Generator) else None))
+
+
+def config0() -> QP:
+    """Small dense QP: n=50, p=25, reg 0.1, seed 0."""
+    return random_dense_qp(50, 25, seed=0, reg=0.1)
+
+
+def config1(n: int = 8192, p: int = 4096, seed: int = 1) -> QP:
+    """Large dense QP: n=8192, p=4096, reg 0.01, seed 1 (smaller n for tests)."""
+    return random_dense_qp(n, p, seed=seed, reg=0.01)
+
+
+# ----------------------------------------------------------------------------
+# Condensed linear MPC (shared Hessian, per-instance linear terms)
+# ----------------------------------------------------------------------------
+
+@dataclass
+class MPCSystem:
+    Ad: np.ndarray        # (nx, nx)
+    Bd: np.ndarray        # (nx, nu)
+    Gamma: np.ndarray     # (N*nx, N*nu)  stacked input-to-state map
+    Phi: np.ndarray       # (N*nx, nx)    stacked free response
+    H: np.ndarray         # (n, n) shared Hessian
+    G: np.ndarray         # (2*N*nx, n) shared constraint matrix
+    lb: np.ndarray
+    ub: np.ndarray
+    xmax: float
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.H.shape[0])
+
+    @property
+    def p(self) -> int:
+        return int(self.G.shape[0])
+
+
+def mpc_system(seed=2, nx: int = 12, nu: int = 4, N: int = 30,
+               rho_spec: float = 0.95, xmax: float = 5.0, umax: float = 1.0,
+               r_weight: float = 0.1, max_tries: int = 100000) -> MPCSystem:
+    """Random condensed MPC system.
+
+    A_d ~ N(0,1) scaled to spectral radius `rho_spec`, resampled until
+    max_{k<=N} ||A_d^k||_inf < xmax so that u = 0 is strictly feasible
+    for every |x0|_inf <= 1.  B_d ~ N(0,1)/2.  Stage cost x^T x and
+    r_weight*u^T u, terminal cost x^T x (constant term dropped).
+    """
+    rng = _rng(seed)
+    for _ in range(max_tries):
+        Ad = rng.standard_normal((nx, nx))
+        Ad *= rho_spec / np.max(np.abs(np.linalg.eigvals(Ad)))
+        P = np.eye(nx)
+        ok = True
+        for _k in range(N):
+            P = Ad @ P
+            if np.max(np.sum(np.abs(P), axis=1)) >= xmax:
+                ok = False
+                break
+        if ok:
+            break
+    else:  # pragma: no cover - the recipe accepts quickly in practice
+        raise RuntimeError("mpc_system: no admissible A_d found")
+    Bd = rng.standard_normal((nx, nu)) / 2.0
+    n = N * nu
+    Gamma = np.zeros((N * nx, n))
+    Phi = np.zeros((N * nx, nx))
+    Apow = [np.eye(nx)]
+    for _k in range(N):
+        Apow.append(Ad @ Apow[-1])
+    for k in range(1, N + 1):          # state x_k, rows (k-1)*nx
+        Phi[(k - 1) * nx:k * nx, :] = Apow[k]
+        for j in range(k):             # input u_j, cols j*nu
+            Gamma[(k - 1) * nx:k * nx, j * nu:(j + 1) * nu] = Apow[k - 1 - j] @ Bd
+    H = Gamma.T @ Gamma
+    H = 0.5 * (H + H.T)
+    H[np.diag_indices(n)] += r_weight
+    G = np.vstack([Gamma, -Gamma])
+    lb = np.full(n, -umax)
+    ub = np.full(n, umax)
+    return MPCSystem(Ad, Bd, Gamma, Phi, H, G, lb, ub, xmax,
+                     dict(kind="mpc", nx=nx, nu=nu, N=N,
+                          seed=seed if not isinstance(seed, np.random.Generator) else None))
+
+
+def mpc_linear_terms(sys: MPCSystem, x0: np.ndarray):
+    """q and g of one MPC instance with initial state x0."""
+    fx = sys.Phi @ x0
+    q = sys.Gamma.T @ fx
+    g = np.concatenate([fx - sys.xmax, -fx - sys.xmax])
+    return q, g
+
+
+def mpc_batch(sys: MPCSystem, B: int, seed=20):
+    """B initial states x0 ~ U(-1,1)^nx and their (q, g); returns (X0, Qlin, Glin)."""
+    rng = _rng(seed)
+    nx = sys.Ad.shape[0]
+    X0 = rng.uniform(-1.0, 1.0, (B, nx))
+    FX = X0 @ sys.Phi.T                                  # (B, N*nx)
+    Qlin = FX @ sys.Gamma                                # (B, n)
+    Glin = np.concatenate([FX - sys.xmax, -FX - sys.xmax], axis=1)
+    return X0, Qlin, Glin
+
+
+def mpc_instance(sys: MPCSystem, x0: np.ndarray) -> QP:
+    q, g = mpc_linear_terms(sys, x0)
+    return QP(sys.H.copy(), q, sys.G.copy(), g, sys.lb.copy(), sys.ub.copy(),
+              dict(kind="mpc_instance"))
+
+
+# ----------------------------------------------------------------------------
+# Uneven independent batch
+# ----------------------------------------------------------------------------
+
+@dataclass
+class UnevenBatch:
+    """Packed batch of independent QPs of different sizes.
+
+    Q of instance i is rows [qoff[i], qoff[i]+n_i*n_i) of the flat array
+    `Q` (row-major n_i x n_i), G likewise at goff[i] (p_i x n_i), vectors
+    q/lb/ub at voff[i] (n_i) and g at coff[i] (p_i)."""
+    n: np.ndarray
+    p: np.ndarray
+    Q: np.ndarray
+    G: np.ndarray
+    q: np.ndarray
+    g: np.ndarray
+    lb: np.ndarray
+    ub: np.ndarray
+    qoff: np.ndarray
+    goff: np.ndarray
+    voff: np.ndarray
+    coff: np.ndarray
+
+    @property
+    def B(self) -> int:
+        return int(self.n.shape[0])
+
+    def instance(self, i: int) -> QP:
+        n, p = int(self.n[i]), int(self.p[i])
+        Q = self.Q[self.qoff[i]:self.qoff[i] + n * n].reshape(n, n).astype(np.float64)
+        G = self.G[self.goff[i]:self.goff[i] + p * n].reshape(p, n).astype(np.float64)
+        sl = slice(self.voff[i], self.voff[i] + n)
+        sc = slice(self.coff[i], self.coff[i] + p)
+        return QP(Q, self.q[sl].copy(), G, self.g[sc].copy(),
+                  self.lb[sl].copy(), self.ub[sl].copy(), dict(kind="uneven", index=i))
+
+
+def uneven_batch(B: int = 10000, seed: int = 3, n_lo: int = 20, n_hi: int = 512,
+                 reg: float = 0.1, dtype=np.float32) -> UnevenBatch:
+    """B random_dense_qp instances with n ~ U{n_lo..n_hi}, p = n // 2.
+
+    Instance i draws from SeedSequence(seed).spawn(B)[i]; sizes come from a
+    separate stream of the same seed."""
+    ss = np.random.SeedSequence(seed)
+    children = ss.spawn(B + 1)
+    size_rng = np.random.default_rng(children[0])
+    ns = size_rng.integers(n_lo, n_hi + 1, size=B).astype(np.int64)
+    ps = ns // 2
+    qoff = np.zeros(B, np.int64)
+    goff = np.zeros(B, np.int64)
+    voff = np.zeros(B, np.int64)
+    coff = np.zeros(B, np.int64)
+    qoff[1:] = np.cumsum(ns * ns)[:-1]
+    goff[1:] = np.cumsum(ps * ns)[:-1]
+    voff[1:] = np.cumsum(ns)[:-1]
+    coff[1:] = np.cumsum(ps)[:-1]
+    Qf = np.empty(int((ns * ns).sum()), dtype)
+    Gf = np.empty(int((ps * ns).sum()), dtype)
+    qf = np.empty(int(ns.sum()))
+    gf = np.empty(int(ps.sum()))
+    lbf = np.empty(int(ns.sum()))
+    ubf = np.empty(int(ns.sum()))
+    for i in range(B):
+        qp = random_dense_qp(int(ns[i]), int(ps[i]), seed=np.random.default_rng(children[i + 1]),
+                             reg=reg)
+        n, p = qp.n, qp.p
+        Qf[qoff[i]:qoff[i] + n * n] = qp.Q.ravel()
+        Gf[goff[i]:goff[i] + p * n] = qp.G.ravel()
+        qf[voff[i]:voff[i] + n] = qp.q
+        lbf[voff[i]:voff[i] + n] = qp.lb
+        ubf[voff[i]:voff[i] + n] = qp.ub
+        gf[coff[i]:coff[i] + p] = qp.g
+    return UnevenBatch(ns, ps, Qf, Gf, qf, gf, lbf, ubf, qoff, goff, voff, coff)

@@ -1,0 +1,576 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: exact
+optima from brute-force active-set enumeration, an independent interior-
+point solver, closed forms, KKT conditions, weak duality, the inexact
+descent lemma of Sec. 3, the theta identities and the feasibility
+identities used in the proofs of Sec. 4.2, and the rate bounds of
+Lemma lemma_sublin_dfg and Theorem lemma_sublin_dfg_inexact.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import minimize
+
+from oracle import dfom
+from oracle.dfom import (DFGM, DGM, LAST, AVG, CERT, FIXED, Options,
+                         problem_constants, dfom_solve, fom_inner, lagrangian,
+                         dual_gradient, inner_gradient, inner_certificate,
+                         objective)
+from oracle.exact import brute_force_qp, box_qp_exact
+from oracle.ipm import ipm_qp
+from paper_1504_05708_amd import gen
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def tiny_qp(n, p, seed, reg=0.3):
+    return gen.random_dense_qp(n, p, seed=seed, reg=reg)
+
+
+def tight(method=DFGM, output=LAST, rho=0.0, eps_out=1e-9, eps_in=1e-13, max_outer=400000):
+    return Options(method=method, output=output, rho=rho, eps_out=eps_out,
+                   eps_in=eps_in, max_outer=max_outer)
+
+
+# ----------------------------------------------------------------------------
+# P1: exact optimum by brute-force enumeration (n <= 6)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,p,seed", [(3, 2, 0), (4, 3, 1), (5, 4, 2), (4, 4, 3), (6, 3, 4)])
+def test_ipm_matches_bruteforce(n, p, seed):
+    qp = tiny_qp(n, p, seed)
+    xs, fs, _ = brute_force_qp(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub)
+    x, f, _ = ipm_qp(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub)
+    assert abs(f - fs) <= 1e-9 * max(1.0, abs(fs))
+    assert np.max(np.abs(x - xs)) <= 1e-6
+
+
+@pytest.mark.parametrize("method", [DGM, DFGM])
+@pytest.mark.parametrize("n,p,seed", [(3, 2, 0), (4, 3, 1), (5, 4, 2), (4, 4, 3)])
+def test_dfom_reaches_bruteforce_optimum(method, n, p, seed):
+    qp = tiny_qp(n, p, seed)
+    xs, fs, lam_s = brute_force_qp(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub)
+    r = dfom_solve(qp, tight(method=method, eps_out=1e-8, eps_in=1e-14, max_outer=100000))
+    assert r.status == dfom.STATUS_OK
+    assert abs(r.F - fs) <= 1e-7 * max(1.0, abs(fs))
+    assert np.max(np.abs(r.x - xs)) <= 1e-5
+    np.testing.assert_allclose(r.lam, lam_s, atol=1e-5)
+
+
+@pytest.mark.parametrize("rho", [0.5, 2.0])
+def test_augmented_dfom_reaches_bruteforce_optimum(rho):
+    qp = tiny_qp(4, 3, 7)
+    xs, fs, _ = brute_force_qp(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub)
+    r = dfom_solve(qp, tight(method=DFGM, rho=rho, eps_out=1e-8, eps_in=1e-14, max_outer=100000))
+    assert r.status == dfom.STATUS_OK
+    assert abs(r.F - fs) <= 1e-7 * max(1.0, abs(fs))
+    assert np.max(np.abs(r.x - xs)) <= 1e-5
+
+
+def test_square_nonsymmetric_G_reaches_optimum():
+    # p = n with a non-symmetric G: a transposed G anywhere changes the answer
+    qp = tiny_qp(4, 4, 11)
+    assert np.max(np.abs(qp.G - qp.G.T)) > 0.1
+    xs, fs, _ = brute_force_qp(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub)
+    for rho in (0.0, 1.0):
+        r = dfom_solve(qp, tight(method=DGM, rho=rho, eps_out=1e-8, eps_in=1e-14, max_outer=100000))
+        assert r.status == dfom.STATUS_OK
+        assert abs(r.F - fs) <= 1e-7 * max(1.0, abs(fs))
+
+
+# ----------------------------------------------------------------------------
+# P2: closed forms
+# ----------------------------------------------------------------------------
+
+def test_box_only_diagonal_closed_form():
+    rng = np.random.default_rng(5)
+    n = 12
+    d = rng.uniform(0.5, 3.0, n)
+    qp = gen.QP(np.diag(d), rng.standard_normal(n) * 3, np.zeros((0, n)), np.zeros(0),
+                -np.ones(n), np.ones(n))
+    r = dfom_solve(qp, Options(eps_out=1e-8, eps_in=1e-14))
+    assert r.status == dfom.STATUS_OK
+    np.testing.assert_allclose(r.x, np.clip(-qp.q / d, -1, 1), atol=1e-6)
+
+
+def test_interior_unconstrained_closed_form():
+    rng = np.random.default_rng(6)
+    n, p = 10, 5
+    A = rng.standard_normal((n, n))
+    Q = A.T @ A / n + np.eye(n)
+    xstar = rng.uniform(-0.3, 0.3, n)
+    q = -Q @ xstar
+    G = rng.standard_normal((p, n))
+    g = -(G @ xstar) - 1.0                  # all rows slack by 1 at x*
+    qp = gen.QP(Q, q, G, g, -np.ones(n), np.ones(n))
+    for method in (DGM, DFGM):
+        r = dfom_solve(qp, Options(method=method, eps_out=1e-8, eps_in=1e-14, max_outer=10000))
+        np.testing.assert_allclose(r.x, np.linalg.solve(Q, -q), atol=1e-6)
+        assert np.max(r.lam) <= 1e-8
+
+
+def test_single_active_row_closed_form():
+    # one active row, box inactive: 2-block KKT solve
+    rng = np.random.default_rng(8)
+    n = 6
+    A = rng.standard_normal((n, n))
+    Q = A.T @ A / n + np.eye(n)
+    q = rng.standard_normal(n) * 0.1
+    a = rng.standard_normal(n)
+    x_unc = np.linalg.solve(Q, -q)
+    b = -(a @ x_unc) + 0.05                 # row a x + b <= 0 violated at x_unc
+    K = np.block([[Q, a[:, None]], [a[None, :], np.zeros((1, 1))]])
+    sol = np.linalg.solve(K, np.concatenate([-q, [-b]]))
+    assert sol[n] > 0 and np.max(np.abs(sol[:n])) < 1
+    qp = gen.QP(Q, q, a[None, :], np.array([b]), -np.ones(n), np.ones(n))
+    r = dfom_solve(qp, Options(method=DFGM, eps_out=1e-9, eps_in=1e-15, max_outer=100000))
+    np.testing.assert_allclose(r.x, sol[:n], atol=1e-6)
+    np.testing.assert_allclose(r.lam, sol[n:], rtol=1e-4)
+
+
+# ----------------------------------------------------------------------------
+# P3: KKT and an independent solver at the config-0 size
+# ----------------------------------------------------------------------------
+
+def test_config0_kkt_and_ipm_value():
+    qp = gen.config0()
+    _, f_ipm, _ = ipm_qp(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub)
+    r = dfom_solve(qp, Options(method=DGM, output=LAST, eps_out=1e-8, eps_in=1e-12, max_outer=300000))
+    assert r.status == dfom.STATUS_OK
+    assert abs(r.F - f_ipm) <= 5e-8 * abs(f_ipm)
+    x, lam = r.x, r.lam
+    grad = qp.Q @ x + qp.q + qp.G.T @ lam
+    assert np.max(np.abs(x - np.clip(x - grad, qp.lb, qp.ub))) <= 1e-4
+    assert np.min(lam) >= 0.0
+    assert abs(lam @ (qp.G @ x + qp.g)) <= 1e-4
+
+
+# ----------------------------------------------------------------------------
+# P4 / P5: weak duality along the run, DGM monotone ascent
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("method", [DGM, DFGM])
+def test_weak_duality_along_run(method):
+    qp = gen.config0()
+    _, fstar, _ = ipm_qp(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub)
+    r = dfom_solve(qp, Options(method=method, eps_out=1e-6, eps_in=1e-9, max_outer=3000, log_vectors=3000))
+    for e in r.log:
+        assert e["LB"] <= fstar + 1e-9 * abs(fstar)
+        if np.all(e["mu"] >= 0):
+            assert e["dbar"] - e["gap"] <= fstar + 1e-9 * abs(fstar)
+    # a feasible candidate is never below F*
+    for e in r.log:
+        if e["feas"] == 0.0:
+            assert e["F"] >= fstar - 1e-9 * abs(fstar)
+
+
+def test_dgm_monotone_ascent():
+    qp = gen.config0()
+    r = dfom_solve(qp, Options(method=DGM, eps_out=1e-12, eps_in=1e-8, max_outer=400, log_vectors=400))
+    Ld = r.consts.Ld
+    for a, b in zip(r.log[:-1], r.log[1:]):
+        step = float(np.sum((a["lam"] - a["mu"]) ** 2))
+        assert b["dbar"] >= a["dbar"] + Ld * step - 2 * a["gap"] - 1e-9 * abs(a["dbar"])
+
+
+# ----------------------------------------------------------------------------
+# P6: theta identities (Sec. 4.2, eq. fg_step)
+# ----------------------------------------------------------------------------
+
+def test_theta_identities():
+    qp = gen.config0()
+    r = dfom_solve(qp, Options(method=DFGM, eps_out=1e-12, max_outer=500))
+    for e in r.log:
+        k, th, S = e["k"], e["theta"], e["S"]
+        assert abs(S - th * th) <= 1e-12 * th * th
+        assert (k + 1) / 2 - 1e-12 <= th <= k + 1e-12
+    rg = dfom_solve(qp, Options(method=DGM, eps_out=1e-12, max_outer=50))
+    assert all(e["theta"] == 1.0 and e["S"] == e["k"] for e in rg.log)
+
+
+# ----------------------------------------------------------------------------
+# P7: identity_lag
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("rho", [0.0, 0.3, 5.0])
+def test_identity_lag(rho):
+    qp = gen.random_dense_qp(20, 12, seed=3)
+    rng = np.random.default_rng(9)
+    for _ in range(5):
+        u = rng.uniform(-1, 1, 20)
+        lam = rng.standard_normal(12) * 2
+        if rho == 0.0:
+            lam = np.abs(lam)
+        dg = dual_gradient(qp.G, qp.g, u, lam, rho)
+        lhs = lagrangian(qp.Q, qp.q, qp.G, qp.g, u, lam, rho) - dg @ lam
+        rhs = objective(qp.Q, qp.q, u) + 0.5 * rho * dg @ dg
+        assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(rhs))
+
+
+# ----------------------------------------------------------------------------
+# P8: inner certificate validity and the inexact dual gradient bound
+# ----------------------------------------------------------------------------
+
+def exact_dual(qp, mu, rho):
+    """d_rho(mu) and u(mu): exact box QP for rho = 0, L-BFGS-B to 1e-13 for rho > 0."""
+    if rho == 0.0:
+        u, _ = box_qp_exact(qp.Q, qp.q + qp.G.T @ mu, qp.lb, qp.ub)
+        return lagrangian(qp.Q, qp.q, qp.G, qp.g, u, mu, 0.0), u
+    fun = lambda u: lagrangian(qp.Q, qp.q, qp.G, qp.g, u, mu, rho)
+    jac = lambda u: inner_gradient(qp.Q, qp.q, qp.G, qp.g, u, mu, rho)
+    best = None
+    for x0 in (np.zeros(qp.n), qp.lb, qp.ub):
+        res = minimize(fun, x0, jac=jac, method="L-BFGS-B", bounds=list(zip(qp.lb, qp.ub)),
+                       options=dict(ftol=1e-15, gtol=1e-13, maxiter=10000))
+        if best is None or res.fun < best.fun:
+            best = res
+    return float(best.fun), best.x
+
+
+@pytest.mark.parametrize("rho", [0.0, 0.7])
+@pytest.mark.parametrize("eps_in", [1e-2, 1e-4, 1e-7])
+def test_inner_certificate_bounds_true_gap(rho, eps_in):
+    qp = tiny_qp(6, 4, 21, reg=0.2)
+    c = problem_constants(qp.Q, qp.G, qp.lb, qp.ub, rho, eps_in)
+    rng = np.random.default_rng(22)
+    for trial in range(6):
+        mu = np.abs(rng.standard_normal(4)) * 2
+        x0 = rng.uniform(-1, 1, 6)
+        u, t, gap = fom_inner(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub, mu, rho, c, x0, eps_in)
+        d_true, u_true = exact_dual(qp, mu, rho)
+        true_gap = lagrangian(qp.Q, qp.q, qp.G, qp.g, u, mu, rho) - d_true
+        assert -1e-11 <= true_gap <= gap + 1e-11
+        if t < c.k_in_max:
+            assert gap <= eps_in
+        # eq. inexact_gradient_rel with the certificate as the inner accuracy
+        err = np.linalg.norm(dual_gradient(qp.G, qp.g, u, mu, rho)
+                             - dual_gradient(qp.G, qp.g, u_true, mu, rho))
+        assert err <= math.sqrt(2 * c.Ld * max(gap, 0.0)) + 1e-7
+
+
+def test_descent_lemma_inexact():
+    # eq. descentlemmainexact: 0 <= dbar(mu) + <gbar, lam - mu> - d(lam) <= Ld||mu-lam||^2 + 2 eps
+    qp = tiny_qp(5, 3, 31)
+    eps_in = 1e-5
+    c = problem_constants(qp.Q, qp.G, qp.lb, qp.ub, 0.0, eps_in)
+    rng = np.random.default_rng(32)
+    for _ in range(8):
+        mu = np.abs(rng.standard_normal(3))
+        lam = np.abs(rng.standard_normal(3))
+        u, t, gap = fom_inner(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub, mu, 0.0, c,
+                              np.zeros(5), eps_in)
+        dbar = lagrangian(qp.Q, qp.q, qp.G, qp.g, u, mu, 0.0)
+        gbar = dual_gradient(qp.G, qp.g, u, mu, 0.0)
+        d_lam, _ = exact_dual(qp, lam, 0.0)
+        val = dbar + gbar @ (lam - mu) - d_lam
+        assert -1e-10 <= val <= c.Ld * np.sum((mu - lam) ** 2) + 2 * gap + 1e-10
+
+
+# ----------------------------------------------------------------------------
+# P9: rate bounds
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", [dfom.INNER_GM, dfom.INNER_FGM, dfom.INNER_FGM_SIGMA])
+def test_inner_fom_rate_bound(variant):
+    # Lemma lemma_sublin_dfg on a box QP: phi(x^k) - phi* <= min((1-sqrt(s/L))^(k-1) L R^2, 2LR^2/(k+1)^p)
+    qp = tiny_qp(6, 0, 41, reg=0.05)
+    mu = np.zeros(0)
+    phistar_x, phistar = box_qp_exact(qp.Q, qp.q, qp.lb, qp.ub)
+    x0 = np.zeros(6)
+    R2 = float(np.sum((x0 - phistar_x) ** 2))
+    for k in (1, 2, 5, 10, 20, 40):
+        c = problem_constants(qp.Q, qp.G, qp.lb, qp.ub, 0.0, 1e-300, max_inner=k)
+        x, t, _ = fom_inner(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub, mu, 0.0, c, x0, 1e-300,
+                            rule=FIXED, variant=variant)
+        assert t == k
+        err = objective(qp.Q, qp.q, x) - phistar
+        L, s = c.L_in, c.sigma_in
+        pb = 1 if variant == dfom.INNER_GM else 2
+        bound = 2 * L * R2 / (k + 1) ** pb
+        if variant == dfom.INNER_FGM_SIGMA:
+            bound = min(bound, (1 - math.sqrt(s / L)) ** (k - 1) * L * R2)
+        assert err <= bound * (1 + 1e-9) + 1e-13
+
+
+@pytest.mark.parametrize("method", [DGM, DFGM])
+def test_outer_rate_bound(method):
+    # Theorem lemma_sublin_dfg_inexact: F* - d(lam^k) <= 4 Ld Rd^2/(k+1)^p + 2 (k+1)^(p-1) eps_in
+    qp = tiny_qp(5, 3, 51)
+    _, fstar, lam_star = brute_force_qp(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub)
+    eps_in = 1e-9
+    r = dfom_solve(qp, Options(method=method, eps_out=1e-14, eps_in=eps_in, max_outer=60, log_vectors=60))
+    Rd2 = float(lam_star @ lam_star)
+    pb = 1 if method == DGM else 2
+    eps_eff = max(e["gap"] for e in r.log)
+    for e in r.log[::5]:
+        k = e["k"]
+        d_lam, _ = exact_dual(qp, e["lam"], 0.0)
+        bound = 4 * r.consts.Ld * Rd2 / (k + 1) ** pb + 2 * (k + 1) ** (pb - 1) * eps_eff
+        assert fstar - d_lam <= bound + 1e-9
+
+
+def test_lambda_distance_bound():
+    # eq. bound_seq_dgm: ||lam^k - lam*|| <= Rd + sqrt(k eps_in / Ld), lam^0 = 0
+    qp = tiny_qp(5, 3, 61)
+    _, _, lam_star = brute_force_qp(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub)
+    for method in (DGM, DFGM):
+        r = dfom_solve(qp, Options(method=method, eps_out=1e-14, eps_in=1e-8, max_outer=200, log_vectors=200))
+        Rd = float(np.linalg.norm(lam_star))
+        eps_eff = max(e["gap"] for e in r.log)
+        for e in r.log:
+            assert np.linalg.norm(e["lam"] - lam_star) <= Rd + math.sqrt(e["k"] * eps_eff / r.consts.Ld) + 1e-7
+
+
+# ----------------------------------------------------------------------------
+# P10: feasibility identities of the averaged iterate (Sec. 4.2)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("method", [DGM, DFGM])
+@pytest.mark.parametrize("rho", [0.0, 1.0])
+def test_average_feasibility_identity(method, rho):
+    """DGM: ||[G uhat^k + g]_+|| <= 2 Ld ||lam^k - lam^0|| / k.
+    DFGM: ||[G uhat^k + g]_+|| <= 2 Ld ||l^k - l^0|| / S_k with
+    l^k = lam^{k-1} + theta_k (lam^k - lam^{k-1}), l^0 = lam^0 (eq. feasibility_aux1).
+    Both follow from the telescoping of the multiplier steps alone, so they
+    hold to rounding for any inner accuracy."""
+    qp = gen.random_dense_qp(30, 18, seed=71)
+    r = dfom_solve(qp, Options(method=method, rho=rho, eps_out=1e-14, eps_in=1e-6,
+                               max_outer=300, log_vectors=300))
+    Ld = r.consts.Ld
+    u_sum = np.zeros(qp.n)
+    lam_prev = np.zeros(qp.p)
+    for e in r.log:
+        k, th, S = e["k"], e["theta"], e["S"]
+        u_sum += th * e["u"]
+        u_hat = u_sum / S
+        lhs = np.linalg.norm(np.maximum(qp.G @ u_hat + qp.g, 0.0))
+        lk = lam_prev + th * (e["lam"] - lam_prev)
+        rhs = 2 * Ld * np.linalg.norm(lk) / S
+        assert lhs <= rhs * (1 + 1e-9) + 1e-12
+        lam_prev = e["lam"]
+
+
+# ----------------------------------------------------------------------------
+# Misc semantics
+# ----------------------------------------------------------------------------
+
+def test_constants_formulas():
+    qp = gen.random_dense_qp(40, 20, seed=81)
+    ev = np.linalg.eigvalsh(qp.Q)
+    s = np.linalg.svd(qp.G, compute_uv=False)
+    for rho in (0.0, 2.0):
+        c = problem_constants(qp.Q, qp.G, qp.lb, qp.ub, rho, 1e-6)
+        assert math.isclose(c.Ld, s[0] ** 2 / (ev[0] + rho * s[0] ** 2), rel_tol=1e-12)
+        assert math.isclose(c.L_in, ev[-1] + rho * s[0] ** 2, rel_tol=1e-12)
+        assert math.isclose(c.alpha * 2 * c.Ld, 1.0, rel_tol=1e-15)
+        assert math.isclose(c.D_U, 2 * math.sqrt(40), rel_tol=1e-15)
+        kin = math.ceil(math.sqrt(c.L_in / c.sigma_in) * math.log(c.L_in * c.D_U ** 2 / 1e-6)) + 1
+        assert c.k_in_max == kin
+
+
+def test_inner_zero_steps_when_warm_start_is_optimal():
+    qp = tiny_qp(5, 0, 91)
+    xs, _ = box_qp_exact(qp.Q, qp.q, qp.lb, qp.ub)
+    c = problem_constants(qp.Q, qp.G, qp.lb, qp.ub, 0.0, 1e-8)
+    x, t, gap = fom_inner(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub, np.zeros(0), 0.0, c, xs, 1e-8)
+    assert t == 0 and gap <= 1e-8
+
+
+def test_last_dfgm_returns_inner_solution_at_lambda():
+    # eq. last_primal: the DFGM last iterate is an eps_in-solution of the inner problem at lambda^k
+    qp = gen.config0()
+    r = dfom_solve(qp, Options(method=DFGM, output=LAST, eps_out=1e-4, eps_in=1e-8))
+    assert r.status == dfom.STATUS_OK
+    g_x = inner_gradient(qp.Q, qp.q, qp.G, qp.g, r.x, r.lam, 0.0)
+    assert inner_certificate(r.x, g_x, qp.lb, qp.ub, r.consts.sigma_in) <= 1e-8 * (1 + 1e-9)
+    assert r.log[-1]["passed2"]
+
+
+@pytest.mark.parametrize("method,output", [(DGM, LAST), (DFGM, LAST), (DFGM, AVG)])
+def test_config0_accuracy_vs_ipm(method, output):
+    qp = gen.config0()
+    _, fstar, _ = ipm_qp(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub)
+    eps_in = 1e-6 if method == DGM else 1e-8
+    r = dfom_solve(qp, Options(method=method, output=output, eps_out=1e-4, eps_in=eps_in, max_outer=100000))
+    assert r.status == dfom.STATUS_OK
+    assert abs(r.F - fstar) / abs(fstar) <= 1e-4
+    assert r.feas / max(1.0, np.linalg.norm(qp.g)) <= 1e-4
+    assert r.LB <= fstar + 1e-9 * abs(fstar)
+
+
+def test_generators_strictly_feasible():
+    qp = gen.random_dense_qp(60, 30, seed=1)
+    assert np.min(np.linalg.eigvalsh(qp.Q)) > 0
+    assert np.allclose(qp.Q, qp.Q.T, rtol=0, atol=0)
+    sysm = gen.mpc_system(seed=2, N=10)
+    X0, Qlin, Glin = gen.mpc_batch(sysm, 16, seed=3)
+    assert np.all(Glin < 0)                  # u = 0 strictly feasible
+    assert sysm.G.shape == (2 * 10 * 12, 10 * 4)
+
+
+# ----------------------------------------------------------------------------
+# Sharper pins of the momentum, averaging, certificates and lower bound
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("method", [DGM, DFGM])
+def test_momentum_identity_feasibility_aux1(method):
+    """Sec. 4.2, eq. feasibility_aux1: theta_k (lam^k - mu^k) = l^k - l^{k-1},
+    l^k = lam^{k-1} + theta_k (lam^k - lam^{k-1}), lam^{-1} = lam^0, theta_0 = 0."""
+    qp = gen.random_dense_qp(30, 18, seed=72)
+    r = dfom_solve(qp, Options(method=method, eps_out=1e-14, eps_in=1e-7, max_outer=150, log_vectors=150))
+    lam_prev = np.zeros(qp.p)
+    l_prev = np.zeros(qp.p)
+    for e in r.log:
+        th = e["theta"]
+        l_k = lam_prev + th * (e["lam"] - lam_prev)
+        np.testing.assert_allclose(th * (e["lam"] - e["mu"]), l_k - l_prev,
+                                   rtol=0, atol=1e-11 * (1 + np.abs(l_k).max()))
+        l_prev, lam_prev = l_k, e["lam"]
+
+
+@pytest.mark.parametrize("method", [DGM, DFGM])
+def test_averaged_residual_vector_identity(method):
+    """sum_j theta_j (G u^j + g) / S_k = (2 Ld / S_k) l^k + (2 Ld / S_k) sum_j theta_j min(z^j, 0)
+    with z^j = mu^j + (G u^j + g) / (2 Ld) (rho = 0, K_d = R^p_+): the telescoping
+    behind the averaged-iterate feasibility bound of Sec. 4.2."""
+    qp = gen.random_dense_qp(30, 18, seed=73)
+    r = dfom_solve(qp, Options(method=method, eps_out=1e-14, eps_in=1e-7, max_outer=150, log_vectors=150))
+    Ld = r.consts.Ld
+    lam_prev = np.zeros(qp.p)
+    acc_r = np.zeros(qp.p)
+    acc_z = np.zeros(qp.p)
+    for e in r.log:
+        th, S = e["theta"], e["S"]
+        rj = qp.G @ e["u"] + qp.g
+        acc_r += th * rj
+        acc_z += th * np.minimum(e["mu"] + rj / (2 * Ld), 0.0)
+        l_k = lam_prev + th * (e["lam"] - lam_prev)
+        np.testing.assert_allclose(acc_r / S, 2 * Ld * (l_k + acc_z) / S,
+                                   rtol=0, atol=1e-9 * (1 + np.abs(acc_r / S).max()))
+        lam_prev = e["lam"]
+
+
+@pytest.mark.parametrize("method", [DGM, DFGM])
+def test_avg_candidate_is_theta_weighted_mean(method):
+    qp = gen.random_dense_qp(30, 18, seed=74)
+    r = dfom_solve(qp, Options(method=method, output=AVG, eps_out=1e-14, eps_in=1e-7,
+                               max_outer=60, log_vectors=60))
+    ths = np.array([e["theta"] for e in r.log])
+    U = np.array([e["u"] for e in r.log])
+    for k, e in enumerate(r.log, start=1):
+        uh = (ths[:k, None] * U[:k]).sum(0) / ths[:k].sum()
+        assert math.isclose(e["F"], objective(qp.Q, qp.q, uh), rel_tol=1e-12, abs_tol=1e-12)
+        assert math.isclose(e["feas"], np.linalg.norm(np.maximum(qp.G @ uh + qp.g, 0)),
+                            rel_tol=1e-9, abs_tol=1e-13)
+
+
+def test_tseng_lemma_dfgm():
+    """Lemma th_tseng_2 at lambda = lambda*: theta_k^2 (F* - d(lam^k)) + sum_j theta_j Delta(lam*, mu^j)
+    + Ld ||l^k - lam*||^2 <= Ld ||lam^0 - lam*||^2 + 2 sum_j theta_j^2 eps_in."""
+    qp = tiny_qp(5, 3, 81)
+    _, fstar, lam_star = brute_force_qp(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub)
+    r = dfom_solve(qp, Options(method=DFGM, eps_out=1e-14, eps_in=1e-9, max_outer=40, log_vectors=40))
+    Ld = r.consts.Ld
+    d_star = fstar                               # strong duality
+    lam_prev = np.zeros(qp.p)
+    sum_delta = 0.0
+    sum_eps = 0.0
+    for e in r.log:
+        th = e["theta"]
+        gbar = dual_gradient(qp.G, qp.g, e["u"], e["mu"], 0.0)
+        sum_delta += th * (e["dbar"] + gbar @ (lam_star - e["mu"]) - d_star)
+        sum_eps += th * th * e["gap"]
+        d_k, _ = exact_dual(qp, e["lam"], 0.0)
+        l_k = lam_prev + th * (e["lam"] - lam_prev)
+        lhs = th * th * (fstar - d_k) + sum_delta + Ld * np.sum((l_k - lam_star) ** 2)
+        rhs = Ld * np.sum(lam_star ** 2) + 2 * sum_eps
+        assert lhs <= rhs * (1 + 1e-9) + 1e-9
+        lam_prev = e["lam"]
+
+
+def test_inner_fgm_lyapunov_decrease():
+    """FGM with the theta rule (Sec. 2.1): E_k = theta_k^2 (phi(x^k) - phi*)
+    + (L/2) ||theta_k x^k - (theta_k - 1) x^{k-1} - x*||^2 is nonincreasing
+    (the potential behind the 2 L R^2/(k+1)^2 rate of Lemma lemma_sublin_dfg)."""
+    qp = tiny_qp(6, 0, 82, reg=0.01)
+    xs, phis = box_qp_exact(qp.Q, qp.q, qp.lb, qp.ub)
+    x0 = np.full(6, 0.9)
+    xs_path = [x0]
+    for k in range(1, 31):
+        c = problem_constants(qp.Q, qp.G, qp.lb, qp.ub, 0.0, 1e-300, max_inner=k)
+        x, t, _ = fom_inner(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub, np.zeros(0), 0.0, c, x0,
+                            1e-300, rule=FIXED, variant=dfom.INNER_FGM)
+        xs_path.append(x)
+    L = c.L_in
+    th = 1.0
+    E_prev = math.inf
+    for k in range(1, 31):
+        xk, xkm1 = xs_path[k], xs_path[k - 1]
+        E = th * th * (objective(qp.Q, qp.q, xk) - phis) + 0.5 * L * np.sum((th * xk - (th - 1) * xkm1 - xs) ** 2)
+        assert E <= E_prev * (1 + 1e-10) + 1e-12
+        E_prev = E
+        th = 0.5 * (1 + math.sqrt(1 + 4 * th * th))
+
+
+@pytest.mark.parametrize("sigma_mode", ["exact", "zero"])
+def test_certificates_valid_at_random_points(sigma_mode):
+    """Both certificates bound phi(x) - phi* from above at arbitrary points,
+    including points on the faces of the box."""
+    qp = tiny_qp(6, 0, 83, reg=0.1)
+    xs, phis = box_qp_exact(qp.Q, qp.q, qp.lb, qp.ub)
+    c = problem_constants(qp.Q, qp.G, qp.lb, qp.ub, 0.0, 1e-6)
+    sigma = c.sigma_in if sigma_mode == "exact" else 0.0
+    rng = np.random.default_rng(84)
+    for _ in range(400):
+        x = rng.uniform(-1, 1, 6)
+        face = rng.integers(0, 3, 6)
+        x[face == 1] = -1.0
+        x[face == 2] = 1.0
+        gx = qp.Q @ x + qp.q
+        cert = inner_certificate(x, gx, qp.lb, qp.ub, sigma)
+        assert objective(qp.Q, qp.q, x) - phis <= cert + 1e-12
+        y = rng.uniform(-1.5, 1.5, 6)
+        xp = np.clip(y - (qp.Q @ y + qp.q) / c.L_in, qp.lb, qp.ub)
+        cert2 = dfom.gradmap_certificate(y, xp, c.L_in, qp.lb, qp.ub, sigma)
+        assert objective(qp.Q, qp.q, xp) - phis <= cert2 + 1e-12
+    # tight at the optimum
+    gs = qp.Q @ xs + qp.q
+    assert inner_certificate(xs, gs, qp.lb, qp.ub, sigma) <= 1e-9
+
+
+def test_lower_bound_skips_multipliers_outside_Kd():
+    """Two parallel rows x1 <= 0.5 and x1 <= 0.6 with the unconstrained optimum
+    at x1 ~ 0.9: DFGM's extrapolated mu_2 turns negative while lambda_2 decays
+    to 0, and a Lagrangian value at such mu can exceed F*.  The lower bound must
+    only use mu in K_d (weak duality, Sec. 2 eq. dual_pr)."""
+    n = 4
+    Q = np.diag([1.0, 2.0, 1.5, 3.0])
+    q = np.array([-0.9, 0.3, -0.2, 0.1])
+    G = np.zeros((2, n))
+    G[0, 0] = G[1, 0] = 1.0
+    g = np.array([-0.5, -0.6])
+    qp = gen.QP(Q, q, G, g, -np.ones(n), np.ones(n))
+    _, fstar, _ = brute_force_qp(Q, q, G, g, qp.lb, qp.ub)
+    r = dfom_solve(qp, Options(method=DFGM, eps_out=1e-14, eps_in=1e-12, max_outer=300, log_vectors=300))
+    assert any(np.any(e["mu"] < 0) and e["dbar"] - e["gap"] > fstar + 1e-9 for e in r.log)
+    assert all(e["LB"] <= fstar + 1e-12 for e in r.log)
+
+
+def test_gradmap_certificate_valid_on_ill_conditioned_instances():
+    """Validity of the gradient-mapping bound where its -||G_L||^2/(2L) term is
+    nearly tight: 2-D box QPs with condition numbers up to 1e4 and steps taken
+    from points outside the box."""
+    rng = np.random.default_rng(85)
+    lb, ub = -np.ones(2), np.ones(2)
+    for _ in range(3000):
+        U, _ = np.linalg.qr(rng.standard_normal((2, 2)))
+        Q = U @ np.diag([1.0, 10 ** rng.uniform(-4, 0)]) @ U.T
+        q = rng.standard_normal(2) * rng.uniform(0.1, 3)
+        xs, phis = box_qp_exact(Q, q, lb, ub)
+        L = float(np.linalg.eigvalsh(Q)[-1])
+        y = rng.uniform(-1.5, 1.5, 2)
+        xp = np.clip(y - (Q @ y + q) / L, lb, ub)
+        cert = dfom.gradmap_certificate(y, xp, L, lb, ub, 0.0)
+        assert objective(Q, q, xp) - phis <= cert + 1e-12
