@@ -1,0 +1,171 @@
+/*
+ * duq.h -- C ABI of libduq.so, an MI355X (gfx950) implementation of the
+ * inexact (augmented) dual first-order method DFOM with inner Algorithm FOM
+ * (Necoara & Patrascu, "DuQuad: an inexact (augmented) dual first order
+ * algorithm for quadratic programming", arXiv 1504.05708).
+ *
+ * Problem (Sec. 2, eq. original_primal, with K = R^p_-):
+ *     min  1/2 u^T Q u + q^T u   s.t.  G u + g <= 0,   lb <= u <= ub
+ * Q is n x n symmetric positive definite (or semidefinite with rho > 0,
+ * Sec. 2 Case 2), G is p x n, both dense and row-major.
+ *
+ * Conventions for every entry point:
+ *   - Return value: DUQ_OK (0) on success, a negative DUQ_E* code on
+ *     failure.  No C++ exception crosses this interface.
+ *   - A handle belongs to one host thread at a time.
+ *   - "HOST" pointers are read (copied) during the call and may be freed
+ *     afterwards.  "DEVICE" pointers are borrowed: they must stay valid and
+ *     unchanged until the handle that borrowed them is destroyed.
+ *   - Outputs are written to caller-owned host buffers unless stated.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     All device work of a handle runs on that stream; calls that return
+ *     results synchronise the stream before returning.
+ *   - duq_last_error() returns a thread-local text for the last failure.
+ */
+#ifndef DUQ_H
+#define DUQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define DUQ_OK           0
+#define DUQ_EINVAL      -1   /* bad argument: null pointer, n <= 0, p < 0, lb > ub,
+                                non-finite data, eps <= 0, rho < 0, rho = 0 with
+                                lambda_min(Q) <= 0, unsupported combination      */
+#define DUQ_ENOMEM      -2   /* device or host allocation failed                  */
+#define DUQ_EDEVICE     -3   /* HIP runtime error or device-side fault flag       */
+#define DUQ_EMAXITER    -4   /* max_outer reached; the last iterate is written    */
+#define DUQ_ENUMERIC    -5   /* NaN/Inf produced during the iteration             */
+#define DUQ_EAGAIN      -6   /* request not finished yet (duq_poll)               */
+#define DUQ_ENOTFOUND   -7   /* unknown ticket or id                              */
+
+/* ---- enumerations ------------------------------------------------------ */
+enum { DUQ_F64 = 0, DUQ_F32 = 1, DUQ_BF16 = 2 };            /* storage of Q, G   */
+enum { DUQ_HOST = 0, DUQ_DEVICE = 1 };                        /* memspace          */
+enum { DUQ_DGM = 0, DUQ_DFGM = 1 };                           /* outer method, Sec. 3 */
+enum { DUQ_LAST = 0, DUQ_AVG = 1 };                           /* primal output, Sec. 4 */
+enum { DUQ_CERT = 0, DUQ_FIXED = 1 };                         /* inner stopping rule */
+enum { DUQ_INNER_AUTO = 0, DUQ_INNER_GM = 1, DUQ_INNER_FGM = 2,
+       DUQ_INNER_FGM_SIGMA = 3 };                             /* inner FOM variant, Sec. 2.1 */
+enum { DUQ_ACC_F64 = 0, DUQ_ACC_F32 = 1 };                    /* product accumulation */
+enum { DUQ_ENGINE_AUTO = 0, DUQ_ENGINE_BLOCK = 1, DUQ_ENGINE_GRID = 2 };
+
+/* ---- problem data (Sec. 2, eq. original_primal) ------------------------- */
+typedef struct duq_problem {
+    int32_t n;            /* variables, n >= 1                                  */
+    int32_t p;            /* inequality rows, p >= 0                            */
+    int32_t dtype;        /* DUQ_F64 or DUQ_F32: element type of Q and G        */
+    int32_t memspace;     /* DUQ_HOST (copied) or DUQ_DEVICE (borrowed)         */
+    const void *Q;        /* n x n row-major, symmetric                          */
+    const void *G;        /* p x n row-major (may be NULL when p == 0)           */
+    const double *q;      /* n                                                   */
+    const double *g;      /* p                                                   */
+    const double *lb;     /* n, lb <= ub                                         */
+    const double *ub;     /* n                                                   */
+} duq_problem;
+
+/* ---- solver options ----------------------------------------------------- *
+ * Initialise with duq_default_options().  Spectral constants lam_min(Q),
+ * lam_max(Q) and ||G||^2 set to a value <= 0 are estimated on the device by
+ * an FP64 Lanczos process (k steps), inflated by `safety`.  From them:
+ *   L_d = ||G||^2/(lam_min + rho ||G||^2)   (Sec. 2 eq. Ld), outer step 1/(2 L_d)
+ *   L_in = lam_max + rho ||G||^2, sigma_in = lam_min       (Sec. 3, Step 1)
+ *   k_in cap of Sec. 5 (natural log, rounded up) unless max_inner > 0.      */
+typedef struct duq_options {
+    int32_t method;         /* DUQ_DGM | DUQ_DFGM                                */
+    int32_t output;         /* DUQ_LAST | DUQ_AVG                                */
+    int32_t inner_rule;     /* DUQ_CERT | DUQ_FIXED                              */
+    int32_t inner_variant;  /* DUQ_INNER_*                                       */
+    int32_t accumulate;     /* DUQ_ACC_F64 | DUQ_ACC_F32 (first phase only)      */
+    int32_t engine;         /* DUQ_ENGINE_*                                      */
+    int32_t max_outer;      /* outer iteration cap (>= 1)                         */
+    int32_t max_inner;      /* inner cap; 0 = k_in of Sec. 5                      */
+    int32_t lanczos_steps;  /* Krylov steps for estimated constants (0 = 96)     */
+    int32_t trace_outer;    /* record the first trace_outer outer iterations     */
+    double eps_out;         /* outer accuracy (relative, see duq_result)         */
+    double eps_in;          /* inner accuracy, eq. duquad_in                     */
+    double rho;             /* augmented Lagrangian parameter, rho >= 0          */
+    double lam_min;         /* lambda_min(Q) or <= 0 to estimate                 */
+    double lam_max;         /* lambda_max(Q) or <= 0 to estimate                 */
+    double G_norm2;         /* ||G||_2^2 or <= 0 to estimate                     */
+    double safety;          /* inflation of estimated constants (default 1.02)   */
+    double switch_factor;   /* DUQ_ACC_F32: switch to F64 at switch_factor*eps_out */
+    int32_t switch_stall;   /* ... or after this many non-improving iterations   */
+    int32_t reserved[7];
+} duq_options;
+
+/* ---- per-solve result --------------------------------------------------- *
+ * The outer test (evaluated on the device every outer iteration) accepts a
+ * candidate x (last iterate ubar(lambda^k), eq. last_primal, or the
+ * theta-weighted average, eq. average_primal) when
+ *    ||[Gx+g]_+|| <= eps_out max(1,||g||),  F(x) - LB <= eps_out max(1,|F(x)|),
+ *    ||lambda^k|| ||[Gx+g]_+|| <= eps_out max(1,|F(x)|)
+ * with LB a certified lower bound on F* (weak duality minus the inner
+ * certificate).                                                              */
+typedef struct duq_result {
+    int32_t status;         /* DUQ_OK, DUQ_EMAXITER, DUQ_ENUMERIC                */
+    int32_t outer_iters;
+    int64_t inner_iters;    /* total inner FOM steps (products with Q)           */
+    int64_t gt_rows;        /* rows of G touched by G^T v products (sparsity)    */
+    double f;               /* F(x)                                              */
+    double lb_dual;         /* LB                                                */
+    double gap;             /* F(x) - LB                                         */
+    double feas;            /* ||[Gx+g]_+||_2                                    */
+    double time_ms;         /* device time of the solve (hipEvent)               */
+    int32_t f64_outer_iters;/* outer iterations run with FP64 accumulation       */
+    int32_t engine;         /* engine that ran                                   */
+    double lam_min, lam_max, G_norm2;  /* constants used                         */
+    double reserved[4];
+} duq_result;
+
+typedef struct duq_handle duq_handle;
+
+/* Fill `o` with defaults: DFGM, LAST, CERT, AUTO inner, ACC_F64, eps_out 1e-4,
+ * eps_in 1e-6, rho 0, max_outer 100000, constants estimated, safety 1.02.   */
+void duq_default_options(duq_options *o);
+
+/* Validate the problem (Sec. 2), move/borrow it to the device, derive the
+ * constants (a1) and allocate the workspace.  On success *out owns all
+ * device memory of the solve.  Errors: DUQ_EINVAL, DUQ_ENOMEM, DUQ_EDEVICE. */
+int duq_setup(const duq_problem *prob, const duq_options *opts, void *stream,
+              duq_handle **out);
+
+/* Run Algorithm DFOM (Sec. 3) to the outer test.  x0 (n) warm-starts the
+ * inner solver and lam0 (p) the multipliers (both host, may be NULL:
+ * x0 = projection of 0 onto the box, lam0 = 0, Sec. 4).  x_out (n) and
+ * lam_out (p) are host buffers (may be NULL).  Returns the result status
+ * (DUQ_OK, DUQ_EMAXITER with the last iterate written, DUQ_ENUMERIC) or an
+ * error code.                                                               */
+int duq_solve(duq_handle *h, const double *x0, const double *lam0,
+              double *x_out, double *lam_out, duq_result *res);
+
+/* Per-outer-iteration trace of the last duq_solve for the first
+ * opts.trace_outer iterations: record k (k = 0..) is
+ *   [DUQ_TRACE_SCALARS doubles][lambda^k (p)][mu^k (p)][ubar^k (n)]
+ * Scalars: k, t_k, gap_k, dbar_k, LB_k, theta_k, S_k, F(cand), feas(cand),
+ * ||lambda^k||, passed, extra_t, extra_gap, F2, feas2, passed2.
+ * `out` holds max_records*(DUQ_TRACE_SCALARS+2p+n) doubles; *n_records gets
+ * the number written.                                                       */
+#define DUQ_TRACE_SCALARS 16
+int duq_get_trace(duq_handle *h, double *out, int32_t max_records, int32_t *n_records);
+
+/* Constants in use: lambda_min(Q), lambda_max(Q), ||G||^2, L_d, L_in, sigma_in. */
+int duq_get_constants(duq_handle *h, double *lam_min, double *lam_max,
+                      double *G_norm2, double *Ld, double *L_in, double *sigma_in);
+
+/* Release every resource of the handle (NULL is allowed).                  */
+void duq_destroy(duq_handle *h);
+
+/* Text of the last error on this thread (never NULL).                       */
+const char *duq_last_error(void);
+const char *duq_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DUQ_H */

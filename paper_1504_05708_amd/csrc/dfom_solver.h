@@ -1,0 +1,624 @@
+// Device-side Algorithm DFOM (Sec. 3) with the inner Algorithm FOM
+// (Sec. 2.1) on the (augmented) Lagrangian over the box, last / averaged
+// primal output (Sec. 4) and the on-device outer test.
+//
+// One body serves three launch shapes:
+//   * the cooperative grid (team = every workgroup; one large QP),
+//   * one workgroup per QP (small QPs, batches),
+// A team member ("rank") owns a contiguous share of the n variables (rows of
+// Q) and of the p constraint rows (rows of G).  Elementwise work touches only
+// owned entries; products read the full input vector staged in LDS; every
+// reduction is done in a fixed order, so every member holds bitwise the same
+// scalars and takes the same branch.
+//
+// Per inner step with rho = 0 the only product is Q x^{t+1}: the gradient at
+// the extrapolated point follows by linearity, Q y = (1+beta) Q x^t - beta Q x^{t-1}
+// (Sec. 5.1 counts one matrix-vector product per inner iteration).
+#pragma once
+#include "device_common.h"
+
+namespace duq {
+
+// ---------------------------------------------------------------------------
+// Products
+// ---------------------------------------------------------------------------
+
+// out[r] = sum_j A[r, j] x[j] + add[r] for the rows [rlo, rhi), one wavefront
+// per row, x staged in LDS.  Lanes stream the row with 16-byte loads.
+template <typename T, typename Acc>
+__device__ __forceinline__ void gemv_rows(const T* A, long ld, int rlo, int rhi, int ncols,
+                                          const double* xl, double* out, const double* add) {
+    typedef typename Vec16<T>::type VT;
+    constexpr int V = Vec16<T>::N;
+    constexpr int U = 8;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    const bool vec = ((ld * (long)sizeof(T)) % 16 == 0) && ((((uintptr_t)A) & 15) == 0);
+    for (int r = rlo + wid; r < rhi; r += nw) {
+        const T* row = A + (long)r * ld;
+        Acc s = 0;
+        int j0 = 0;
+        if (vec) {
+            const VT* rv = reinterpret_cast<const VT*>(row);
+            const int nv = ncols / V;
+            int v = lane;
+            for (; v + kWave * (U - 1) < nv; v += kWave * U) {
+                VT a[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) a[u] = rv[v + kWave * u];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const double* xv = xl + (long)(v + kWave * u) * V;
+#pragma unroll
+                    for (int e = 0; e < V; ++e) s += (Acc)a[u][e] * (Acc)xv[e];
+                }
+            }
+            for (; v < nv; v += kWave) {
+                VT a = rv[v];
+                const double* xv = xl + (long)v * V;
+#pragma unroll
+                for (int e = 0; e < V; ++e) s += (Acc)a[e] * (Acc)xv[e];
+            }
+            j0 = nv * V;
+        }
+        for (int j = j0 + lane; j < ncols; j += kWave) s += (Acc)row[j] * (Acc)xl[j];
+        s = wave_sum(s);
+        if (lane == 0) out[r] = (double)s + (add ? add[r] : 0.0);
+    }
+}
+
+// Phase 1 of z = A^T v over the rows [rlo, rhi) of A: dst[j] = sum_r A[r,j] v[r]
+// (+ add[j] when add != null).  Threads run over columns; rows with v[r] = 0
+// are skipped (exactly: they add +0).  vl holds v[rlo..rhi) in LDS.
+// Returns the number of rows with v != 0.
+template <typename T, typename Acc>
+__device__ __forceinline__ int gemvT_rows(const T* A, long ld, int rlo, int rhi, int ncols,
+                                          const double* vl, double* dst, const double* add) {
+    typedef typename Vec16<T>::type VT;
+    constexpr int V = Vec16<T>::N;
+    const bool vec = ((ld * (long)sizeof(T)) % 16 == 0) && ((((uintptr_t)A) & 15) == 0);
+    const int nv = vec ? ncols / V : 0;
+    for (int cv = threadIdx.x; cv < nv; cv += blockDim.x) {
+        Acc acc[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc[e] = 0;
+        int r = rlo;
+        // two rows per trip keeps two loads in flight per thread
+        for (; r + 1 < rhi; r += 2) {
+            const double v0 = vl[r - rlo], v1 = vl[r - rlo + 1];
+            if (v0 != 0.0) {
+                VT a = reinterpret_cast<const VT*>(A + (long)r * ld)[cv];
+#pragma unroll
+                for (int e = 0; e < V; ++e) acc[e] += (Acc)a[e] * (Acc)v0;
+            }
+            if (v1 != 0.0) {
+                VT a = reinterpret_cast<const VT*>(A + (long)(r + 1) * ld)[cv];
+#pragma unroll
+                for (int e = 0; e < V; ++e) acc[e] += (Acc)a[e] * (Acc)v1;
+            }
+        }
+        if (r < rhi) {
+            const double v0 = vl[r - rlo];
+            if (v0 != 0.0) {
+                VT a = reinterpret_cast<const VT*>(A + (long)r * ld)[cv];
+#pragma unroll
+                for (int e = 0; e < V; ++e) acc[e] += (Acc)a[e] * (Acc)v0;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const int j = cv * V + e;
+            dst[j] = (double)acc[e] + (add ? add[j] : 0.0);
+        }
+    }
+    for (int j = nv * V + threadIdx.x; j < ncols; j += blockDim.x) {
+        Acc acc = 0;
+        for (int r = rlo; r < rhi; ++r) {
+            const double v0 = vl[r - rlo];
+            if (v0 != 0.0) acc += (Acc)A[(long)r * ld + j] * (Acc)v0;
+        }
+        dst[j] = (double)acc + (add ? add[j] : 0.0);
+    }
+    int nz = 0;
+    for (int r = rlo; r < rhi; ++r) nz += (vl[r - rlo] != 0.0);
+    return nz;
+}
+
+// Phase 2: out[j] = add[j] + sum_{b < nb} part[b*n + j] for owned columns,
+// one wavefront per column, lanes over b in a fixed order.
+__device__ __forceinline__ void gemvT_reduce(const double* part, int nb, int n, int clo, int chi,
+                                             const double* add, double* out) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    for (int j = clo + wid; j < chi; j += nw) {
+        double s = 0.0;
+        for (int b = lane; b < nb; b += kWave) s += part[(long)b * n + j];
+        s = wave_sum(s);
+        if (lane == 0) out[j] = add[j] + s;
+    }
+}
+
+__device__ __forceinline__ void stage(const double* src, int len, double* dst) {
+    for (int i = threadIdx.x; i < len; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// The solver
+// ---------------------------------------------------------------------------
+
+template <typename T, typename Acc>
+struct Dfom {
+    DevProblem<T> P;
+    DevParams par;
+    DevWork W;
+    Team tm;
+    int nlo, nhi, plo, phi;  // owned variable / row ranges
+    double* xl;              // LDS: staged n-vector
+    double* vl;              // LDS: staged owned rows of a p-vector
+    double* red;             // LDS: reduction scratch
+    int pp;                  // ping-pong index of the partial buffer
+    long long gt_rows;       // rows of G touched by transposed products
+
+    // Rotating buffers selected without runtime-indexed arrays (which would
+    // force the pointer tables into scratch memory).
+    double *xb0, *xb1, *xb2, *qb0, *qb1, *qb2, *gx0, *gx1, *gx2;
+    __device__ __forceinline__ void bind_rings() {
+        xb0 = W.xb[0]; xb1 = W.xb[1]; xb2 = W.xb[2];
+        qb0 = W.qb[0]; qb1 = W.qb[1]; qb2 = W.qb[2];
+        gx0 = W.gx[0]; gx1 = W.gx[1]; gx2 = W.gx[2];
+    }
+    __device__ __forceinline__ static double* pick(int i, double* a, double* b, double* c) {
+        double* r = c;
+        if (i == 0) r = a;
+        if (i == 1) r = b;
+        return r;
+    }
+    __device__ __forceinline__ double* X(int i) const { return pick(i, xb0, xb1, xb2); }
+    __device__ __forceinline__ double* QX(int i) const { return pick(i, qb0, qb1, qb2); }
+    __device__ __forceinline__ double* GX(int i) const { return pick(i, gx0, gx1, gx2); }
+
+    // ---- team reductions -------------------------------------------------
+    // Reduce K per-thread values over the team; every thread gets the sums.
+    // Contains a team barrier; returns false on abort.
+    template <int K>
+    __device__ __forceinline__ bool allreduce(double (&v)[K]) {
+        block_allreduce<K>(v, red);
+        if (tm.size == 1) return true;
+        double* part = W.part + (long)pp * tm.size * kNP;
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) part[(long)tm.rank * kNP + k] = v[k];
+        }
+        if (tm.sync()) return false;
+        double s[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) s[k] = 0.0;
+        for (int b = threadIdx.x; b < tm.size; b += blockDim.x) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) s[k] += part[(long)b * kNP + k];
+        }
+        block_allreduce<K>(s, red);
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = s[k];
+        pp ^= 1;
+        return true;
+    }
+
+    // z = add + A^T v restricted to owned columns (full v on the team).
+    __device__ __forceinline__ bool gemvT(const double* v, const double* add, double* z) {
+        const int n = P.n;
+        for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) vl[i - plo] = v[i];
+        __syncthreads();
+        if (tm.size == 1) {
+            gt_rows += gemvT_rows<T, Acc>(P.G, n, plo, phi, n, vl, z, add);
+            __syncthreads();
+            return true;
+        }
+        gt_rows += gemvT_rows<T, Acc>(P.G, n, plo, phi, n, vl, W.gtp + (long)tm.rank * n, nullptr);
+        if (tm.sync()) return false;
+        gemvT_reduce(W.gtp, tm.size, n, nlo, nhi, add, z);
+        __syncthreads();
+        return true;
+    }
+
+    __device__ __forceinline__ double clip(double v, int i) const {
+        return fmin(fmax(v, P.lb[i]), P.ub[i]);
+    }
+
+    // Exact-gradient certificate terms at a box point (fw, pi^2).
+    __device__ __forceinline__ void cert_terms(double x, double gr, int i, double& fw, double& pi2) const {
+        const double lo = P.lb[i], hi = P.ub[i];
+        fw += fmax(gr * (x - lo), gr * (x - hi));
+        const bool atl = x <= lo, atu = x >= hi;
+        double pi = gr;
+        if (atl && atu) pi = 0.0;
+        else if (atl) pi = fmin(gr, 0.0);
+        else if (atu) pi = fmax(gr, 0.0);
+        pi2 += pi * pi;
+    }
+
+    __device__ __forceinline__ double gap_from(double fw, double pi2) const {
+        return par.sigma > 0.0 ? fmin(fw, pi2 / (2.0 * par.sigma)) : fw;
+    }
+
+    __device__ __forceinline__ int third(int a, int b) const {
+        int c = (a + 1) % 3;
+        if (c == b) c = (a + 2) % 3;
+        return c;
+    }
+
+    // ---- inner solve, rho = 0 --------------------------------------------
+    // From x^0 = xb[cur] (with Q x^0 in qb[cur]) and c = q + G^T mu.
+    // On return xb[cur] / qb[cur] hold ubar and Q ubar.  Returns -1 on abort.
+    __device__ __forceinline__ int inner_rho0(int& cur, const double* c, double& gap) {
+        const int n = P.n;
+        int prv = cur;
+        int t = 0;
+        double th = 1.0;
+        for (;;) {
+            const int nxt = third(cur, prv);
+            double beta = 0.0;
+            if (t > 0) {
+                if (par.inner_variant == 3) beta = par.beta_in;
+                else if (par.inner_variant == 2) {
+                    const double thn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * th * th));
+                    beta = (th - 1.0) / thn;
+                }
+            }
+            const double* x = X(cur);
+            const double* xp = X(prv);
+            const double* qx = QX(cur);
+            const double* qxp = QX(prv);
+            double* xn = X(nxt);
+            double acc[2] = {0.0, 0.0};
+            for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x) {
+                const double xi = x[i], qi = qx[i], ci = c[i];
+                cert_terms(xi, qi + ci, i, acc[0], acc[1]);
+                const double yi = xi + beta * (xi - xp[i]);
+                const double qyi = qi + beta * (qi - qxp[i]);
+                xn[i] = clip(yi - (qyi + ci) / par.L, i);
+            }
+            if (!allreduce<2>(acc)) return -1;
+            gap = gap_from(acc[0], acc[1]);
+            if (!(gap == gap)) return -2;
+            if ((par.inner_rule == 0 && gap <= par.eps_in) || t >= par.k_in_max) return t;
+            if (t > 0 && par.inner_variant == 2) th = 0.5 * (1.0 + sqrt(1.0 + 4.0 * th * th));
+            // Q x^{t+1}; the barrier inside allreduce published every x^{t+1} entry
+            stage(xn, n, xl);
+            gemv_rows<T, Acc>(P.Q, n, nlo, nhi, n, xl, QX(nxt), nullptr);
+            __syncthreads();
+            prv = cur;
+            cur = nxt;
+            ++t;
+        }
+    }
+
+    // ---- inner solve, rho > 0 --------------------------------------------
+    // Gradient Q y + q + G^T [mu + rho (G y + g)]_+ at the extrapolated point
+    // only; G y and Q y follow by linearity from G x, Q x.  Certificate: exact
+    // at x^0, gradient-mapping bound after each projected step.
+    __device__ __forceinline__ int inner_rhop(int& cur, const double* mu, double& gap) {
+        const int n = P.n;
+        int prv = cur;
+        int t = 0;
+        double th = 1.0, beta = 0.0;
+        for (;;) {
+            const int nxt = third(cur, prv);
+            const double* x = X(cur);
+            const double* xp = X(prv);
+            // w = [mu + rho (G y + g)]_+ on owned rows, G y by linearity
+            for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) {
+                const double gxi = GX(cur)[i];
+                const double gyi = gxi + beta * (gxi - GX(prv)[i]);
+                W.wv[i] = fmax(mu[i] + par.rho * (gyi + P.g[i]), 0.0);
+            }
+            __syncthreads();
+            // h = q + G^T w into W.c (owned columns)
+            if (!gemvT(W.wv, P.q, W.c)) return -1;
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            double* xn = X(nxt);
+            for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x) {
+                const double xi = x[i], qi = QX(cur)[i];
+                const double yi = xi + beta * (xi - xp[i]);
+                const double qyi = qi + beta * (qi - QX(prv)[i]);
+                const double gy = qyi + W.c[i];
+                if (t == 0) cert_terms(xi, gy, i, acc[0], acc[1]);
+                const double xnew = clip(yi - gy / par.L, i);
+                xn[i] = xnew;
+                const double gm = par.L * (yi - xnew);
+                acc[2] += fmax(gm * (yi - P.lb[i]), gm * (yi - P.ub[i]));
+                acc[3] += gm * gm;
+            }
+            if (!allreduce<4>(acc)) return -1;
+            if (t == 0) {
+                gap = gap_from(acc[0], acc[1]);
+                if (!(gap == gap)) return -2;
+                if (par.inner_rule == 0 && gap <= par.eps_in) return 0;
+            }
+            double g2 = acc[2] - acc[3] / (2.0 * par.L);
+            if (par.sigma > 0.0) g2 = fmin(g2, 0.5 * acc[3] * (1.0 / par.sigma - 1.0 / par.L));
+            gap = g2;
+            if (!(gap == gap)) return -2;
+            // products of x^{t+1} (published by the barrier inside allreduce)
+            stage(xn, n, xl);
+            gemv_rows<T, Acc>(P.Q, n, nlo, nhi, n, xl, QX(nxt), nullptr);
+            gemv_rows<T, Acc>(P.G, n, plo, phi, n, xl, GX(nxt), nullptr);
+            __syncthreads();
+            ++t;
+            prv = cur;
+            cur = nxt;
+            if ((par.inner_rule == 0 && gap <= par.eps_in) || t >= par.k_in_max) return t;
+            // momentum for y^{t+1}
+            if (par.inner_variant == 3) beta = par.beta_in;
+            else if (par.inner_variant == 2) {
+                const double thn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * th * th));
+                beta = (th - 1.0) / thn;
+                th = thn;
+            } else beta = 0.0;
+        }
+    }
+
+    __device__ __forceinline__ int inner(int& cur, const double* mu, double& gap) {
+        if (par.rho > 0.0) return inner_rhop(cur, mu, gap);
+        if (!gemvT(mu, P.q, W.c)) return -1;   // c = q + G^T mu (Sec. 5.1)
+        return inner_rho0(cur, W.c, gap);
+    }
+
+    // After an inner solve ending in xb[cur]: r = G u + g on owned rows (for
+    // rho > 0 G u is already in gx[cur]).
+    __device__ __forceinline__ void residual(int cur) {
+        if (par.rho > 0.0) {
+            for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) W.r[i] = GX(cur)[i] + P.g[i];
+            __syncthreads();
+            return;
+        }
+        stage(X(cur), P.n, xl);
+        gemv_rows<T, Acc>(P.G, P.n, plo, phi, P.n, xl, W.r, P.g);
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ bool outer_ok(double F, double feas, double lnorm, double LB, double gnorm) const {
+        const double sc = fmax(1.0, fabs(F));
+        return feas <= par.eps_out * fmax(1.0, gnorm) && F - LB <= par.eps_out * sc &&
+               lnorm * feas <= par.eps_out * sc;
+    }
+
+    // Copy owned entries of the primal answer and multipliers to the outputs.
+    __device__ __forceinline__ void write_outputs(const double* x, double scale) {
+        for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x) W.xout[i] = x[i] * scale;
+    }
+
+    // ---- Algorithm DFOM ---------------------------------------------------
+    __device__ __forceinline__ void run() {
+        const int n = P.n, p = P.p;
+        DevState* st = W.st;
+        bind_rings();
+        pp = 0;
+        gt_rows = 0;
+        int cur;
+        double theta, S, LB, gnorm;
+        int k0;
+        long long inner_total;
+        if (!par.resume) {
+            cur = 0;
+            // x^0 = warm start or the projection of 0; lambda^0 = lam0 or 0
+            for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x) {
+                const double v = par.has_x0 ? W.x0[i] : 0.0;
+                xb0[i] = clip(v, i);
+                W.us[i] = 0.0;
+                W.qus[i] = 0.0;
+            }
+            double gg[1] = {0.0};
+            for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) {
+                double l = par.has_lam0 ? W.lam0[i] : 0.0;
+                if (par.Kd_nonneg) l = fmax(l, 0.0);
+                W.lamp[i] = l;   // lambda^{-1} = lambda^0
+                W.mu[i] = l;     // mu^1 = lambda^0
+                W.rs[i] = 0.0;
+                gg[0] += P.g[i] * P.g[i];
+            }
+            if (!allreduce<1>(gg)) return;
+            gnorm = sqrt(gg[0]);
+            if (tm.size > 1 && tm.sync()) return;
+            stage(xb0, n, xl);
+            gemv_rows<T, Acc>(P.Q, n, nlo, nhi, n, xl, qb0, nullptr);
+            if (par.rho > 0.0) gemv_rows<T, Acc>(P.G, n, plo, phi, n, xl, gx0, nullptr);
+            __syncthreads();
+            theta = 1.0;
+            S = 0.0;
+            LB = -INFINITY;
+            k0 = 0;
+            inner_total = 0;
+        } else {
+            cur = st->cur;
+            theta = st->theta;
+            S = st->S;
+            LB = st->LB;
+            gnorm = st->gnorm;
+            k0 = st->k;
+            inner_total = st->inner;
+            gt_rows = 0;
+        }
+        int status = 1;  // max outer unless the test passes
+        double Fc = 0.0, feasc = 0.0, lnc = 0.0;
+        int ans_cur = cur;   // buffer of the answer (LAST)
+        bool ans_avg = false;
+        int k = k0;
+        while (k < par.max_outer) {
+            ++k;
+            // Step 1: inner solve at mu^k, warm-started from ubar^{k-1}
+            double gap = 0.0;
+            const int t = inner(cur, W.mu, gap);
+            if (t == -1) return;
+            if (t == -2) { status = 2; break; }
+            inner_total += t;
+            residual(cur);
+            // Steps 2-3 and averaging on owned rows / variables
+            const double thk = theta;
+            const double thn = par.method == 1 ? 0.5 * (1.0 + sqrt(1.0 + 4.0 * thk * thk)) : 1.0;
+            const double beta = (thk - 1.0) / thn;
+            const double Sn = S + thk;
+            double a[11];
+#pragma unroll
+            for (int z = 0; z < 11; ++z) a[z] = 0.0;
+            const bool tr = k <= par.trace_iters;
+            double* trec = tr ? W.trace + (long)(k - 1) * (kTraceScalars + 2 * p + n) : nullptr;
+            for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x) {
+                const double ui = X(cur)[i], qui = QX(cur)[i];
+                a[0] += ui * qui;
+                a[1] += P.q[i] * ui;
+                const double us = W.us[i] + thk * ui, qus = W.qus[i] + thk * qui;
+                W.us[i] = us;
+                W.qus[i] = qus;
+                a[8] += us * qus;
+                a[9] += P.q[i] * us;
+                if (tr) trec[kTraceScalars + 2 * p + i] = ui;
+            }
+            for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) {
+                const double ri = W.r[i], mui = W.mu[i];
+                double dg;
+                if (par.rho > 0.0) {
+                    const double v = fmax(ri + mui / par.rho, 0.0);
+                    a[2] += v * v;
+                    a[3] += mui * mui;
+                    dg = ri - fmin(ri + mui / par.rho, 0.0);
+                } else {
+                    a[2] += mui * ri;
+                    dg = ri;
+                }
+                const double rp = fmax(ri, 0.0);
+                a[4] += rp * rp;
+                double lk = mui + par.alpha * dg;
+                if (par.Kd_nonneg) lk = fmax(lk, 0.0);
+                a[5] += lk * lk;
+                const double rs = W.rs[i] + thk * ri;
+                W.rs[i] = rs;
+                const double hp = fmax(rs / Sn, 0.0);
+                a[6] += hp * hp;
+                a[7] += (mui < 0.0) ? 1.0 : 0.0;
+                a[10] += (lk < 0.0) ? 1.0 : 0.0;
+                if (tr) {
+                    trec[kTraceScalars + i] = lk;
+                    trec[kTraceScalars + p + i] = mui;
+                }
+                W.mu[i] = lk + beta * (lk - W.lamp[i]);
+                W.lamp[i] = lk;
+            }
+            if (!allreduce<11>(a)) return;
+            const double Fu = 0.5 * a[0] + a[1];
+            const double dbar = par.rho > 0.0 ? Fu + 0.5 * par.rho * a[2] - a[3] / (2.0 * par.rho)
+                                              : Fu + a[2];
+            if (par.rho > 0.0 || a[7] == 0.0) LB = fmax(LB, dbar - gap);
+            S = Sn;
+            double F, feas;
+            if (par.output == 0) {
+                F = Fu;
+                feas = sqrt(a[4]);
+            } else {
+                F = 0.5 * a[8] / (S * S) + a[9] / S;
+                feas = sqrt(a[6]);
+            }
+            const double lnorm = sqrt(a[5]);
+            if (!(F == F) || !(LB == LB && dbar == dbar)) { status = 2; break; }
+            const bool ok1 = outer_ok(F, feas, lnorm, LB, gnorm);
+            bool ok = ok1;
+            Fc = F; feasc = feas; lnc = lnorm;
+            ans_cur = cur;
+            ans_avg = par.output == 1;
+            double ex[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // extra_t, extra_gap, F2, feas2, passed2
+            if (ok1 && par.output == 0 && par.method == 1) {
+                // Last iterate of DFGM: ubar(lambda^k), eq. last_primal.
+                for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x) {
+                    W.usave[i] = X(cur)[i];
+                    W.qusave[i] = QX(cur)[i];
+                }
+                if (par.rho > 0.0)
+                    for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) W.gsave[i] = GX(cur)[i];
+                __syncthreads();
+                int c2 = cur;
+                double gap2 = 0.0;
+                const int t2 = inner(c2, W.lamp, gap2);
+                if (t2 == -1) return;
+                if (t2 == -2) { status = 2; break; }
+                inner_total += t2;
+                residual(c2);
+                double b[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x) {
+                    const double ui = X(c2)[i];
+                    b[0] += ui * QX(c2)[i];
+                    b[1] += P.q[i] * ui;
+                }
+                for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) {
+                    const double ri = W.r[i], li = W.lamp[i];
+                    if (par.rho > 0.0) {
+                        const double v = fmax(ri + li / par.rho, 0.0);
+                        b[2] += v * v;
+                        b[3] += li * li;
+                    } else {
+                        b[2] += li * ri;
+                    }
+                    const double rp = fmax(ri, 0.0);
+                    b[4] += rp * rp;
+                }
+                if (!allreduce<6>(b)) return;
+                const double F2 = 0.5 * b[0] + b[1];
+                const double d2 = par.rho > 0.0 ? F2 + 0.5 * par.rho * b[2] - b[3] / (2.0 * par.rho)
+                                                : F2 + b[2];
+                if (par.rho > 0.0 || a[10] == 0.0) LB = fmax(LB, d2 - gap2);
+                const double feas2 = sqrt(b[4]);
+                const bool ok2 = outer_ok(F2, feas2, lnorm, LB, gnorm);
+                ex[0] = t2; ex[1] = gap2; ex[2] = F2; ex[3] = feas2; ex[4] = ok2 ? 1.0 : 0.0;
+                if (ok2) {
+                    Fc = F2; feasc = feas2;
+                    ans_cur = c2;
+                } else {
+                    ok = false;
+                    // continue from ubar^k unchanged
+                    for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x) {
+                        X(cur)[i] = W.usave[i];
+                        QX(cur)[i] = W.qusave[i];
+                    }
+                    if (par.rho > 0.0)
+                        for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) GX(cur)[i] = W.gsave[i];
+                    __syncthreads();
+                }
+            }
+            if (tr && tm.rank == 0 && threadIdx.x == 0) {
+                trec[0] = k; trec[1] = t; trec[2] = gap; trec[3] = dbar; trec[4] = LB;
+                trec[5] = thk; trec[6] = S; trec[7] = F; trec[8] = feas; trec[9] = lnorm;
+                trec[10] = ok1 ? 1.0 : 0.0;
+                trec[11] = ex[0]; trec[12] = ex[1]; trec[13] = ex[2]; trec[14] = ex[3]; trec[15] = ex[4];
+                st->n_trace = k;
+            }
+            theta = thn;
+            if (ok) { status = 0; break; }
+            // precision switch support: stop this launch once the looser
+            // tolerance of a first phase is met
+        }
+        // outputs
+        if (ans_avg) write_outputs(W.us, 1.0 / S);
+        else write_outputs(X(ans_cur), 1.0);
+        if (tm.rank == 0 && threadIdx.x == 0) {
+            st->status = status;
+            st->done = status == 0;
+            st->k = k;
+            st->cur = cur;
+            st->inner = inner_total;
+            st->theta = theta;
+            st->S = S;
+            st->LB = LB;
+            st->F = Fc;
+            st->feas = feasc;
+            st->lnorm = lnc;
+            st->gnorm = gnorm;
+        }
+        // rows of G touched, summed over the team (for reporting)
+        if (threadIdx.x == 0 && gt_rows > 0)
+            atomicAdd((unsigned long long*)&st->gt_rows, (unsigned long long)gt_rows);
+    }
+};
+
+}  // namespace duq

@@ -1,0 +1,585 @@
+// Host runtime behind the C ABI of include/duq.h: validation, device
+// memory, constants, engine choice, launches and result transfer.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/duq.h"
+#include "internal.h"
+#include "launch.h"
+
+using namespace duq;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t _e = (expr);                                                          \
+        if (_e != hipSuccess)                                                            \
+            return fail(_e == hipErrorOutOfMemory ? DUQ_ENOMEM : DUQ_EDEVICE,            \
+                        std::string(#expr) + ": " + hipGetErrorString(_e));              \
+    } while (0)
+
+struct DeviceInfo {
+    int cus = 0;
+    size_t lds_max = 0;
+};
+
+int device_info(DeviceInfo* di) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    di->cus = prop.multiProcessorCount;
+    di->lds_max = prop.sharedMemPerBlock;
+#if HIP_VERSION_MAJOR >= 6
+    if (prop.maxSharedMemoryPerMultiProcessor > di->lds_max && prop.maxSharedMemoryPerMultiProcessor <= 160 * 1024)
+        di->lds_max = prop.maxSharedMemoryPerMultiProcessor;
+#endif
+    return DUQ_OK;
+}
+
+size_t esize(int dtype) { return dtype == DUQ_F64 ? 8 : 4; }
+
+bool finite_all(const double* a, long len) {
+    for (long i = 0; i < len; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+template <typename T>
+bool finite_all_t(const T* a, long len) {
+    for (long i = 0; i < len; ++i)
+        if (!std::isfinite((double)a[i])) return false;
+    return true;
+}
+
+// Bump allocator over one device allocation (256-byte aligned slices).
+struct Carve {
+    char* base = nullptr;
+    size_t off = 0;
+    size_t need = 0;
+    template <typename T>
+    T* take(size_t count) {
+        const size_t bytes = ((count * sizeof(T) + 255) / 256) * 256 + 256;
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+}  // namespace
+
+struct duq_handle {
+    int n = 0, p = 0, dtype = 0;
+    hipStream_t stream = nullptr;
+    duq_options opts;
+    // device data
+    void* dQ = nullptr;
+    void* dG = nullptr;
+    double *dq = nullptr, *dg = nullptr, *dlb = nullptr, *dub = nullptr;
+    void* owned_data = nullptr;   // allocation holding copied data (HOST memspace)
+    // constants
+    double lam_min = 0, lam_max = 0, G2 = 0;
+    double Ld = 0, alpha = 0, L_in = 0, sigma = 0, beta_in = 0, D_U = 0;
+    int k_in = 1, Kd_nonneg = 1, variant = 3;
+    // engine
+    int engine = DUQ_ENGINE_BLOCK;
+    LaunchCfg cfg{};
+    // workspace
+    void* ws = nullptr;
+    DevWork W{};
+    double* xstage = nullptr;
+    double* lstage = nullptr;
+    int trace_cap = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int last_records = 0;
+};
+
+extern "C" {
+
+void duq_default_options(duq_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->method = DUQ_DFGM;
+    o->output = DUQ_LAST;
+    o->inner_rule = DUQ_CERT;
+    o->inner_variant = DUQ_INNER_AUTO;
+    o->accumulate = DUQ_ACC_F64;
+    o->engine = DUQ_ENGINE_AUTO;
+    o->max_outer = 100000;
+    o->max_inner = 0;
+    o->lanczos_steps = 0;
+    o->trace_outer = 0;
+    o->eps_out = 1e-4;
+    o->eps_in = 1e-6;
+    o->rho = 0.0;
+    o->lam_min = 0.0;
+    o->lam_max = 0.0;
+    o->G_norm2 = 0.0;
+    o->safety = 1.02;
+    o->switch_factor = 10.0;
+    o->switch_stall = 20;
+}
+
+const char* duq_last_error(void) { return g_err.c_str(); }
+
+const char* duq_strerror(int code) {
+    switch (code) {
+        case DUQ_OK: return "ok";
+        case DUQ_EINVAL: return "invalid argument";
+        case DUQ_ENOMEM: return "out of memory";
+        case DUQ_EDEVICE: return "device error";
+        case DUQ_EMAXITER: return "iteration limit reached";
+        case DUQ_ENUMERIC: return "non-finite value in the iteration";
+        case DUQ_EAGAIN: return "not ready";
+        case DUQ_ENOTFOUND: return "not found";
+        default: return "unknown";
+    }
+}
+
+void duq_destroy(duq_handle* h) {
+    if (!h) return;
+    if (h->ws) (void)hipFree(h->ws);
+    if (h->owned_data) (void)hipFree(h->owned_data);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    delete h;
+}
+
+}  // extern "C"
+
+namespace {
+
+int validate(const duq_problem* pr, const duq_options* o) {
+    if (!pr || !o) return fail(DUQ_EINVAL, "null problem or options");
+    if (pr->n <= 0) return fail(DUQ_EINVAL, "n must be positive");
+    if (pr->p < 0) return fail(DUQ_EINVAL, "p must be non-negative");
+    if (pr->dtype != DUQ_F64 && pr->dtype != DUQ_F32) return fail(DUQ_EINVAL, "dtype must be F64 or F32");
+    if (pr->memspace != DUQ_HOST && pr->memspace != DUQ_DEVICE) return fail(DUQ_EINVAL, "bad memspace");
+    if (!pr->Q || !pr->q || !pr->lb || !pr->ub) return fail(DUQ_EINVAL, "null Q, q, lb or ub");
+    if (pr->p > 0 && (!pr->G || !pr->g)) return fail(DUQ_EINVAL, "null G or g with p > 0");
+    if (o->method != DUQ_DGM && o->method != DUQ_DFGM) return fail(DUQ_EINVAL, "bad method");
+    if (o->output != DUQ_LAST && o->output != DUQ_AVG) return fail(DUQ_EINVAL, "bad output");
+    if (o->inner_rule != DUQ_CERT && o->inner_rule != DUQ_FIXED) return fail(DUQ_EINVAL, "bad inner_rule");
+    if (o->inner_variant < 0 || o->inner_variant > 3) return fail(DUQ_EINVAL, "bad inner_variant");
+    if (o->accumulate != DUQ_ACC_F64 && o->accumulate != DUQ_ACC_F32) return fail(DUQ_EINVAL, "bad accumulate");
+    if (o->accumulate == DUQ_ACC_F32 && pr->dtype != DUQ_F32)
+        return fail(DUQ_EINVAL, "FP32 accumulation needs FP32 storage");
+    if (!(o->eps_out > 0.0) || !(o->eps_in > 0.0)) return fail(DUQ_EINVAL, "eps_out and eps_in must be > 0");
+    if (!(o->rho >= 0.0) || !std::isfinite(o->rho)) return fail(DUQ_EINVAL, "rho must be >= 0");
+    if (o->max_outer < 1) return fail(DUQ_EINVAL, "max_outer must be >= 1");
+    if (o->max_inner < 0 || o->trace_outer < 0 || o->lanczos_steps < 0)
+        return fail(DUQ_EINVAL, "negative count");
+    if (!(o->safety >= 1.0)) return fail(DUQ_EINVAL, "safety must be >= 1");
+    return DUQ_OK;
+}
+
+}  // namespace
+
+namespace duq {
+int estimate_constants(duq_handle* h, const DeviceInfo& di);
+}
+
+extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* stream, duq_handle** out) {
+    if (!out) return fail(DUQ_EINVAL, "null output handle");
+    *out = nullptr;
+    int rc = validate(pr, opts);
+    if (rc) return rc;
+    const int n = pr->n, p = pr->p, dtype = pr->dtype;
+    const long nn = (long)n * n, pn = (long)p * n;
+    DeviceInfo di;
+    if ((rc = device_info(&di))) return rc;
+
+    duq_handle* h = new (std::nothrow) duq_handle();
+    if (!h) return fail(DUQ_ENOMEM, "host allocation");
+    h->n = n;
+    h->p = p;
+    h->dtype = dtype;
+    h->opts = *opts;
+    h->stream = (hipStream_t)stream;
+
+    // lb, ub on the host for validation and the box diameter D_U
+    std::vector<double> lb(n), ub(n);
+    if (pr->memspace == DUQ_HOST) {
+        std::memcpy(lb.data(), pr->lb, n * sizeof(double));
+        std::memcpy(ub.data(), pr->ub, n * sizeof(double));
+    } else {
+        if (hipMemcpy(lb.data(), pr->lb, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(ub.data(), pr->ub, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+            duq_destroy(h);
+            return fail(DUQ_EINVAL, "lb/ub are not readable device pointers");
+        }
+    }
+    double du2 = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (!std::isfinite(lb[i]) || !std::isfinite(ub[i]) || lb[i] > ub[i]) {
+            duq_destroy(h);
+            return fail(DUQ_EINVAL, "box must be finite with lb <= ub (U compact, Sec. 2)");
+        }
+        du2 += (ub[i] - lb[i]) * (ub[i] - lb[i]);
+    }
+    h->D_U = std::sqrt(du2);
+
+    if (pr->memspace == DUQ_HOST) {
+        bool ok = finite_all(pr->q, n) && (p == 0 || finite_all(pr->g, p));
+        ok = ok && (dtype == DUQ_F64 ? finite_all_t((const double*)pr->Q, nn) : finite_all_t((const float*)pr->Q, nn));
+        if (p > 0)
+            ok = ok && (dtype == DUQ_F64 ? finite_all_t((const double*)pr->G, pn) : finite_all_t((const float*)pr->G, pn));
+        if (!ok) {
+            duq_destroy(h);
+            return fail(DUQ_EINVAL, "non-finite problem data");
+        }
+        Carve c;
+        c.take<char>(nn * esize(dtype));
+        c.take<char>(std::max<long>(pn, 1) * esize(dtype));
+        c.take<double>(n);
+        c.take<double>(std::max(p, 1));
+        c.take<double>(n);
+        c.take<double>(n);
+        if (hipMalloc(&h->owned_data, c.off) != hipSuccess) {
+            duq_destroy(h);
+            return fail(DUQ_ENOMEM, "device allocation of problem data");
+        }
+        c.base = (char*)h->owned_data;
+        c.off = 0;
+        h->dQ = c.take<char>(nn * esize(dtype));
+        h->dG = c.take<char>(std::max<long>(pn, 1) * esize(dtype));
+        h->dq = c.take<double>(n);
+        h->dg = c.take<double>(std::max(p, 1));
+        h->dlb = c.take<double>(n);
+        h->dub = c.take<double>(n);
+        hipError_t e = hipSuccess;
+        e = e ? e : hipMemcpy(h->dQ, pr->Q, nn * esize(dtype), hipMemcpyHostToDevice);
+        if (p > 0) e = e ? e : hipMemcpy(h->dG, pr->G, pn * esize(dtype), hipMemcpyHostToDevice);
+        e = e ? e : hipMemcpy(h->dq, pr->q, n * sizeof(double), hipMemcpyHostToDevice);
+        if (p > 0) e = e ? e : hipMemcpy(h->dg, pr->g, p * sizeof(double), hipMemcpyHostToDevice);
+        e = e ? e : hipMemcpy(h->dlb, lb.data(), n * sizeof(double), hipMemcpyHostToDevice);
+        e = e ? e : hipMemcpy(h->dub, ub.data(), n * sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            duq_destroy(h);
+            return fail(DUQ_EDEVICE, std::string("copy of problem data: ") + hipGetErrorString(e));
+        }
+    } else {
+        h->dQ = const_cast<void*>(pr->Q);
+        h->dG = const_cast<void*>(pr->G);
+        h->dq = const_cast<double*>(pr->q);
+        h->dg = const_cast<double*>(pr->g);
+        h->dlb = const_cast<double*>(pr->lb);
+        h->dub = const_cast<double*>(pr->ub);
+        // borrowed data: count non-finite entries on the device
+        unsigned* cnt = nullptr;
+        if (hipMalloc(&cnt, sizeof(unsigned)) != hipSuccess) {
+            duq_destroy(h);
+            return fail(DUQ_ENOMEM, "device allocation");
+        }
+        unsigned hc = 0;
+        hipError_t e = hipMemsetAsync(cnt, 0, sizeof(unsigned), h->stream);
+        e = e ? e : launch_count_nonfinite(dtype, h->dQ, nn, cnt, h->stream);
+        if (p > 0) e = e ? e : launch_count_nonfinite(dtype, h->dG, pn, cnt, h->stream);
+        e = e ? e : launch_count_nonfinite(DUQ_F64, h->dq, n, cnt, h->stream);
+        if (p > 0) e = e ? e : launch_count_nonfinite(DUQ_F64, h->dg, p, cnt, h->stream);
+        e = e ? e : hipMemcpyAsync(&hc, cnt, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream);
+        e = e ? e : hipStreamSynchronize(h->stream);
+        (void)hipFree(cnt);
+        if (e != hipSuccess) {
+            duq_destroy(h);
+            return fail(DUQ_EDEVICE, std::string("validation of device data: ") + hipGetErrorString(e));
+        }
+        if (hc) {
+            duq_destroy(h);
+            return fail(DUQ_EINVAL, "non-finite problem data");
+        }
+    }
+
+    // engine and launch shape
+    int engine = opts->engine;
+    if (engine == DUQ_ENGINE_AUTO) engine = (n <= 1536) ? DUQ_ENGINE_BLOCK : DUQ_ENGINE_GRID;
+    h->engine = engine;
+    const int acc_first = opts->accumulate;
+    if (engine == DUQ_ENGINE_BLOCK) {
+        h->cfg.nblocks = 1;
+        h->cfg.nthreads = n <= 128 ? 256 : 512;
+        h->cfg.cooperative = false;
+    } else {
+        h->cfg.nthreads = 512;
+        int nb = di.cus;
+        nb = std::max(1, std::min(nb, n));
+        h->cfg.nblocks = nb;
+        h->cfg.cooperative = true;
+    }
+    h->cfg.stream = h->stream;
+    h->cfg.shmem = dfom_lds_bytes(n, p, h->cfg.nblocks);
+    if (h->cfg.shmem > di.lds_max) {
+        duq_destroy(h);
+        return fail(DUQ_EINVAL, "n too large for the LDS-staged products of this build (n + p/blocks <= " +
+                                    std::to_string(di.lds_max / 8) + ")");
+    }
+    if (h->cfg.cooperative) {
+        for (int acc = 0; acc <= (dtype == DUQ_F32 ? 1 : 0); ++acc) {
+            int bpc = 0;
+            if (dfom_occupancy(dtype, acc, h->cfg.nthreads, h->cfg.shmem, &bpc) != hipSuccess || bpc < 1) {
+                duq_destroy(h);
+                return fail(DUQ_EDEVICE, "cooperative launch does not fit one block per CU");
+            }
+        }
+    }
+    (void)acc_first;
+
+    // workspace
+    const int nb = h->cfg.nblocks;
+    const int trace = opts->trace_outer;
+    auto carve = [&](Carve& c) {
+        for (int i = 0; i < 3; ++i) h->W.xb[i] = c.take<double>(n);
+        for (int i = 0; i < 3; ++i) h->W.qb[i] = c.take<double>(n);
+        h->W.c = c.take<double>(n);
+        h->W.us = c.take<double>(n);
+        h->W.qus = c.take<double>(n);
+        h->W.usave = c.take<double>(n);
+        h->W.qusave = c.take<double>(n);
+        h->W.xout = c.take<double>(n);
+        const int pp = std::max(p, 1);
+        h->W.r = c.take<double>(pp);
+        h->W.rs = c.take<double>(pp);
+        h->W.lamp = c.take<double>(pp);
+        h->W.mu = c.take<double>(pp);
+        h->W.wv = c.take<double>(pp);
+        h->W.gsave = c.take<double>(pp);
+        for (int i = 0; i < 3; ++i) h->W.gx[i] = c.take<double>(pp);
+        h->W.part = c.take<double>((size_t)2 * nb * kNP);
+        h->W.gtp = c.take<double>(nb > 1 ? (size_t)nb * n : 1);
+        h->W.trace = c.take<double>(trace > 0 ? (size_t)trace * (kTraceScalars + 2 * p + n) : 1);
+        h->W.st = c.take<DevState>(1);
+        h->W.bar = c.take<unsigned>(4);
+        h->xstage = c.take<double>(n);
+        h->lstage = c.take<double>(pp);
+    };
+    Carve c0;
+    carve(c0);
+    if (hipMalloc(&h->ws, c0.off) != hipSuccess) {
+        duq_destroy(h);
+        return fail(DUQ_ENOMEM, "device workspace (" + std::to_string(c0.off) + " bytes)");
+    }
+    Carve c1;
+    c1.base = (char*)h->ws;
+    carve(c1);
+    h->trace_cap = trace;
+    if (hipMemset(h->ws, 0, c0.off) != hipSuccess) {
+        duq_destroy(h);
+        return fail(DUQ_EDEVICE, "workspace clear");
+    }
+    if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
+        duq_destroy(h);
+        return fail(DUQ_EDEVICE, "event creation");
+    }
+
+    // constants (a1): caller-supplied or estimated
+    h->lam_min = opts->lam_min;
+    h->lam_max = opts->lam_max;
+    h->G2 = p > 0 ? opts->G_norm2 : 0.0;
+    if (h->lam_min <= 0.0 || h->lam_max <= 0.0 || (p > 0 && h->G2 <= 0.0)) {
+        rc = estimate_constants(h, di);
+        if (rc) {
+            duq_destroy(h);
+            return rc;
+        }
+    }
+    const double rho = opts->rho;
+    const double denom = h->lam_min + rho * h->G2;
+    if (p > 0 && !(denom > 0.0)) {
+        duq_destroy(h);
+        return fail(DUQ_EINVAL, "lambda_min(Q) = 0 needs rho > 0 (Sec. 2, Case 2)");
+    }
+    h->Ld = p > 0 ? h->G2 / denom : 0.0;
+    h->alpha = h->Ld > 0.0 ? 1.0 / (2.0 * h->Ld) : 0.0;
+    h->L_in = h->lam_max + rho * h->G2;
+    h->sigma = std::max(h->lam_min, 0.0);
+    const double sqL = std::sqrt(h->L_in), sqs = std::sqrt(h->sigma);
+    h->beta_in = (sqL - sqs) / (sqL + sqs);
+    if (opts->max_inner > 0) h->k_in = opts->max_inner;
+    else if (h->sigma > 0.0) {
+        const double arg = h->L_in * h->D_U * h->D_U / opts->eps_in;
+        h->k_in = arg > 1.0 ? (int)std::ceil(std::sqrt(h->L_in / h->sigma) * std::log(arg)) + 1 : 1;
+    } else {
+        h->k_in = (int)std::ceil(std::sqrt(2.0 * h->L_in * h->D_U * h->D_U / opts->eps_in));
+    }
+    h->k_in = std::max(h->k_in, 1);
+    h->Kd_nonneg = h->lam_min > 0.0 ? 1 : 0;
+    int v = opts->inner_variant;
+    if (v == DUQ_INNER_AUTO) v = h->sigma > 0.0 ? DUQ_INNER_FGM_SIGMA : DUQ_INNER_FGM;
+    h->variant = v;
+    *out = h;
+    return DUQ_OK;
+}
+
+namespace duq {
+
+int estimate_constants(duq_handle* h, const DeviceInfo& di) {
+    const int n = h->n, p = h->p;
+    int k = h->opts.lanczos_steps > 0 ? h->opts.lanczos_steps : 96;
+    k = std::min(k, n);
+    const int nb = h->cfg.nblocks;
+    LanczosWork L{};
+    Carve c0;
+    auto carve = [&](Carve& c) {
+        L.V = c.take<double>((size_t)(k + 1) * n);
+        L.w = c.take<double>(n);
+        L.r = c.take<double>(std::max(p, 1));
+        L.part = c.take<double>((size_t)nb * (k + 2));
+        L.gtp = c.take<double>(nb > 1 ? (size_t)nb * n : 1);
+        L.ab = c.take<double>(2 * (size_t)k + 2);
+        L.out = c.take<double>(4);
+        L.bar = c.take<unsigned>(4);
+    };
+    carve(c0);
+    void* buf = nullptr;
+    HIP_TRY(hipMalloc(&buf, c0.off));
+    Carve c1;
+    c1.base = (char*)buf;
+    carve(c1);
+    LaunchCfg cfg = h->cfg;
+    cfg.shmem = lanczos_lds_bytes(n, p, nb, k);
+    if (cfg.shmem > di.lds_max) {
+        (void)hipFree(buf);
+        return fail(DUQ_EINVAL, "problem too large for the Lanczos estimate; pass the constants");
+    }
+    GenericProblem gp{n, p, h->dQ, h->dG, h->dq, h->dg, h->dlb, h->dub};
+    double outQ[4] = {0, 0, 0, 0}, outG[4] = {0, 0, 0, 0};
+    unsigned flag[4] = {0, 0, 0, 0};
+    auto run = [&](int use_gtg, double* out) -> int {
+        hipError_t e = hipMemsetAsync(buf, 0, c0.off, h->stream);
+        e = e ? e : launch_lanczos(h->dtype, cfg, gp, L, k, use_gtg);
+        e = e ? e : hipMemcpyAsync(out, L.out, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+        e = e ? e : hipMemcpyAsync(flag, L.bar, 4 * sizeof(unsigned), hipMemcpyDeviceToHost, h->stream);
+        e = e ? e : hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return fail(DUQ_EDEVICE, std::string("Lanczos: ") + hipGetErrorString(e));
+        if (flag[2]) return fail(DUQ_EDEVICE, "Lanczos: grid barrier timeout");
+        return DUQ_OK;
+    };
+    int rc = DUQ_OK;
+    if (h->lam_min <= 0.0 || h->lam_max <= 0.0) rc = run(0, outQ);
+    if (!rc && h->p > 0 && h->G2 <= 0.0) rc = run(1, outG);
+    (void)hipFree(buf);
+    if (rc) return rc;
+    const double sf = h->opts.safety;
+    if (h->lam_min <= 0.0) h->lam_min = outQ[0] / sf;
+    if (h->lam_max <= 0.0) h->lam_max = outQ[1] * sf;
+    if (h->p > 0 && h->G2 <= 0.0) h->G2 = outG[1] * sf;
+    if (!(h->lam_max > 0.0)) return fail(DUQ_EINVAL, "Q appears to be zero");
+    return DUQ_OK;
+}
+
+}  // namespace duq
+
+extern "C" int duq_get_constants(duq_handle* h, double* lam_min, double* lam_max, double* G_norm2, double* Ld,
+                                 double* L_in, double* sigma_in) {
+    if (!h) return fail(DUQ_EINVAL, "null handle");
+    if (lam_min) *lam_min = h->lam_min;
+    if (lam_max) *lam_max = h->lam_max;
+    if (G_norm2) *G_norm2 = h->G2;
+    if (Ld) *Ld = h->Ld;
+    if (L_in) *L_in = h->L_in;
+    if (sigma_in) *sigma_in = h->sigma;
+    return DUQ_OK;
+}
+
+extern "C" int duq_solve(duq_handle* h, const double* x0, const double* lam0, double* x_out, double* lam_out,
+                         duq_result* res) {
+    if (!h) return fail(DUQ_EINVAL, "null handle");
+    const int n = h->n, p = h->p;
+    const duq_options& o = h->opts;
+    if (x0) {
+        for (int i = 0; i < n; ++i)
+            if (!std::isfinite(x0[i])) return fail(DUQ_EINVAL, "non-finite x0");
+        HIP_TRY(hipMemcpyAsync(h->xstage, x0, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    }
+    if (lam0 && p > 0) {
+        for (int i = 0; i < p; ++i)
+            if (!std::isfinite(lam0[i])) return fail(DUQ_EINVAL, "non-finite lam0");
+        HIP_TRY(hipMemcpyAsync(h->lstage, lam0, p * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    }
+    HIP_TRY(hipMemsetAsync(h->W.st, 0, sizeof(DevState), h->stream));
+    HIP_TRY(hipMemsetAsync(h->W.bar, 0, 4 * sizeof(unsigned), h->stream));
+    DevWork W = h->W;
+    W.x0 = h->xstage;
+    W.lam0 = h->lstage;
+    DevParams par{};
+    par.method = o.method;
+    par.output = o.output;
+    par.inner_rule = o.inner_rule;
+    par.inner_variant = h->variant;
+    par.max_outer = o.max_outer;
+    par.k_in_max = h->k_in;
+    par.trace_iters = std::min(o.trace_outer, h->trace_cap);
+    par.Kd_nonneg = h->Kd_nonneg;
+    par.has_x0 = x0 ? 1 : 0;
+    par.has_lam0 = (lam0 && p > 0) ? 1 : 0;
+    par.resume = 0;
+    par.eps_out = o.eps_out;
+    par.eps_in = o.eps_in;
+    par.rho = o.rho;
+    par.alpha = h->alpha;
+    par.L = h->L_in;
+    par.sigma = h->sigma;
+    par.beta_in = h->beta_in;
+    GenericProblem gp{n, p, h->dQ, h->dG, h->dq, h->dg, h->dlb, h->dub};
+    HIP_TRY(hipEventRecord(h->ev0, h->stream));
+    HIP_TRY(launch_dfom(h->dtype, h->dtype == DUQ_F32 ? o.accumulate : 0, h->cfg, gp, par, W));
+    HIP_TRY(hipEventRecord(h->ev1, h->stream));
+    DevState st;
+    unsigned bar[4];
+    HIP_TRY(hipMemcpyAsync(&st, h->W.st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(bar, h->W.bar, sizeof(bar), hipMemcpyDeviceToHost, h->stream));
+    if (x_out) HIP_TRY(hipMemcpyAsync(x_out, h->W.xout, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    if (lam_out && p > 0)
+        HIP_TRY(hipMemcpyAsync(lam_out, h->W.lamp, p * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    if (bar[2]) return fail(DUQ_EDEVICE, "grid barrier timeout (a workgroup did not arrive)");
+    h->last_records = st.n_trace;
+    int code = st.status == 0 ? DUQ_OK : (st.status == 1 ? DUQ_EMAXITER : DUQ_ENUMERIC);
+    if (res) {
+        std::memset(res, 0, sizeof(*res));
+        res->status = code;
+        res->outer_iters = st.k;
+        res->inner_iters = st.inner;
+        res->gt_rows = st.gt_rows;
+        res->f = st.F;
+        res->lb_dual = st.LB;
+        res->gap = st.F - st.LB;
+        res->feas = st.feas;
+        res->time_ms = ms;
+        res->f64_outer_iters = (h->dtype == DUQ_F32 && o.accumulate == DUQ_ACC_F32) ? 0 : st.k;
+        res->engine = h->engine;
+        res->lam_min = h->lam_min;
+        res->lam_max = h->lam_max;
+        res->G_norm2 = h->G2;
+    }
+    if (code == DUQ_ENUMERIC) g_err = "non-finite value during the iteration";
+    if (code == DUQ_EMAXITER) g_err = "max_outer reached";
+    return code;
+}
+
+extern "C" int duq_get_trace(duq_handle* h, double* out, int32_t max_records, int32_t* n_records) {
+    if (!h || !out || max_records < 0) return fail(DUQ_EINVAL, "bad trace arguments");
+    const int rec = std::min(std::min(h->last_records, h->trace_cap), (int)max_records);
+    const size_t per = (size_t)(kTraceScalars + 2 * h->p + h->n);
+    if (rec > 0)
+        HIP_TRY(hipMemcpy(out, h->W.trace, rec * per * sizeof(double), hipMemcpyDeviceToHost));
+    if (n_records) *n_records = rec;
+    return DUQ_OK;
+}

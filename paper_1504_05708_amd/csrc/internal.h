@@ -1,0 +1,107 @@
+// Internal structures shared by the host runtime and the HIP kernels.
+#pragma once
+#include <stdint.h>
+
+namespace duq {
+
+// Scalars reduced per block: count of slots in one partial record.
+constexpr int kNP = 12;
+// Scalars of one trace record.
+constexpr int kTraceScalars = 16;
+
+// Problem as seen by a kernel (device pointers).  Q is n x n, G is p x n,
+// both row-major with leading dimension n.
+template <typename T>
+struct DevProblem {
+    int n, p;
+    const T* Q;
+    const T* G;
+    const double* q;
+    const double* g;
+    const double* lb;
+    const double* ub;
+};
+
+// Per-solve parameters derived on the host from the options and constants.
+struct DevParams {
+    int method;        // 0 DGM, 1 DFGM
+    int output;        // 0 LAST, 1 AVG
+    int inner_rule;    // 0 CERT, 1 FIXED
+    int inner_variant; // resolved: 1 GM, 2 FGM, 3 FGM_sigma
+    int max_outer;
+    int k_in_max;
+    int trace_iters;
+    int Kd_nonneg;     // project multipliers onto R^p_+
+    int has_x0;
+    int has_lam0;
+    int resume;        // continue from the state left by a previous launch
+    int pad;
+    double eps_out;    // outer tolerance used by this launch
+    double eps_in;
+    double rho;
+    double alpha;      // 1/(2 L_d)
+    double L;          // L_in
+    double sigma;      // sigma_in
+    double beta_in;    // FGM_sigma momentum
+};
+
+// Scalar solver state kept in device memory between launches and the
+// final result of a solve.
+struct DevState {
+    int status;        // 0 running/ok, 1 maxiter, 2 numeric, 3 barrier timeout
+    int done;          // outer test passed
+    int k;             // outer iterations completed
+    int cur;           // index of the warm-start buffer
+    long long inner;   // total inner steps
+    long long gt_rows; // G rows touched by transposed products
+    double theta;
+    double S;
+    double LB;
+    double F;
+    double feas;
+    double lnorm;
+    double gnorm;
+    double best_metric; // used by the precision switch (stall detection)
+    int stall;
+    int n_trace;
+};
+
+// Device workspace of one instance.  All pointers refer to one allocation.
+struct DevWork {
+    double* xb[3];     // rotating inner iterates x^{t-1}, x^t, x^{t+1}
+    double* qb[3];     // matching products Q x
+    double* c;         // q + G^T mu (rho = 0)
+    double* us;        // sum_j theta_j ubar^j
+    double* qus;       // sum_j theta_j Q ubar^j
+    double* usave;     // ubar^k kept across the extra DFGM-last solve
+    double* qusave;
+    double* xout;      // returned primal point
+    double* r;         // G u + g for the owned rows
+    double* rs;        // sum_j theta_j (G ubar^j + g)
+    double* lamp;      // lambda^{k} (after the step) = lambda^{k-1} before it
+    double* mu;        // mu^k
+    double* wv;        // rho > 0: [mu + rho (G y + g)]_+
+    double* gsave;     // rho > 0: G ubar^k kept across the extra DFGM-last solve
+    double* gx[3];     // rho > 0: G x for the rotating iterates
+    double* part;      // 2 x nblocks x kNP partial sums (ping-pong)
+    double* gtp;       // nblocks x n partial columns of G^T v
+    double* trace;     // trace records
+    const double* x0;  // optional warm start (device)
+    const double* lam0;
+    DevState* st;
+    unsigned* bar;     // [0] arrival count, [1] generation, [2] error flag
+};
+
+// Workspace of the Lanczos constant estimate.
+struct LanczosWork {
+    double* V;       // (k+1) x n basis
+    double* w;       // n
+    double* r;       // p (G v for the G^T G operator)
+    double* part;    // nblocks x (k+2) partial sums
+    double* gtp;     // nblocks x n partial columns (G^T r)
+    double* ab;      // alpha[0..k), beta[0..k]
+    double* out;     // [theta_min, theta_max, steps]
+    unsigned* bar;
+};
+
+}  // namespace duq

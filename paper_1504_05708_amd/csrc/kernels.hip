@@ -1,0 +1,140 @@
+// Kernel entry points and launch helpers for the DFOM solver and the
+// Lanczos constant estimate.  Built for gfx950 only.
+#include <hip/hip_runtime.h>
+
+#include "dfom_solver.h"
+#include "lanczos.h"
+#include "launch.h"
+
+namespace duq {
+
+// LDS layout of the solver: [x staged (n)] [owned p rows (pmax)] [reduction scratch].
+static size_t solver_lds_doubles(int n, int p, int nblocks) {
+    const int pmax = (p + nblocks - 1) / nblocks + 1;
+    return (size_t)n + (size_t)pmax + (size_t)kMaxWaves * kNP + 2;
+}
+
+static size_t lanczos_lds_doubles(int n, int p, int nblocks, int k) {
+    const int pmax = (p + nblocks - 1) / nblocks + 1;
+    return (size_t)n + (size_t)pmax + (size_t)(k + 2) + (size_t)kMaxWaves * 2 + 2;
+}
+
+template <typename T, typename Acc>
+__global__ void __launch_bounds__(512) dfom_kernel(DevProblem<T> P, DevParams par, DevWork W) {
+    extern __shared__ __align__(16) double lds[];
+    Dfom<T, Acc> s;
+    s.P = P;
+    s.par = par;
+    s.W = W;
+    s.tm.rank = blockIdx.x;
+    s.tm.size = gridDim.x;
+    s.tm.bar = W.bar;
+    share(P.n, blockIdx.x, gridDim.x, s.nlo, s.nhi);
+    share(P.p, blockIdx.x, gridDim.x, s.plo, s.phi);
+    const int pmax = (P.p + gridDim.x - 1) / gridDim.x + 1;
+    s.xl = lds;
+    s.vl = lds + P.n;
+    s.red = lds + P.n + pmax;
+    s.run();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512) lanczos_kernel(DevProblem<T> P, LanczosWork L, int k, int use_gtg) {
+    extern __shared__ __align__(16) double lds[];
+    Lanczos<T> s;
+    s.P = P;
+    s.L = L;
+    s.k = k;
+    s.use_gtg = use_gtg;
+    s.tm.rank = blockIdx.x;
+    s.tm.size = gridDim.x;
+    s.tm.bar = L.bar;
+    share(P.n, blockIdx.x, gridDim.x, s.nlo, s.nhi);
+    share(P.p, blockIdx.x, gridDim.x, s.plo, s.phi);
+    const int pmax = (P.p + gridDim.x - 1) / gridDim.x + 1;
+    s.xl = lds;
+    s.vl = lds + P.n;
+    s.hl = lds + P.n + pmax;
+    s.red = s.hl + (k + 2);
+    s.run();
+}
+
+// Count of non-finite entries of a device array (validation of borrowed data).
+template <typename T>
+__global__ void count_nonfinite_kernel(const T* a, long len, unsigned* out) {
+    unsigned c = 0;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < len; i += (long)gridDim.x * blockDim.x) {
+        const double v = (double)a[i];
+        c += !(v - v == 0.0);
+    }
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, kWave);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
+template <typename K>
+static hipError_t launch_any(K kernel, const LaunchCfg& cfg, void** args) {
+    const size_t shmem = cfg.shmem;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return e;
+    if (cfg.cooperative)
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kernel), dim3(cfg.nblocks),
+                                          dim3(cfg.nthreads), args, shmem, cfg.stream);
+    return hipLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(cfg.nblocks), dim3(cfg.nthreads),
+                           args, shmem, cfg.stream);
+}
+
+size_t dfom_lds_bytes(int n, int p, int nblocks) { return solver_lds_doubles(n, p, nblocks) * sizeof(double); }
+size_t lanczos_lds_bytes(int n, int p, int nblocks, int k) {
+    return lanczos_lds_doubles(n, p, nblocks, k) * sizeof(double);
+}
+
+hipError_t dfom_occupancy(int dtype, int acc, int nthreads, size_t shmem, int* blocks_per_cu) {
+    const void* f = nullptr;
+    if (dtype == 0) f = reinterpret_cast<const void*>(&dfom_kernel<double, double>);
+    else if (acc == 0) f = reinterpret_cast<const void*>(&dfom_kernel<float, double>);
+    else f = reinterpret_cast<const void*>(&dfom_kernel<float, float>);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, nthreads, shmem);
+}
+
+hipError_t launch_dfom(int dtype, int acc, const LaunchCfg& cfg, const GenericProblem& gp,
+                       const DevParams& par, const DevWork& W) {
+    DevParams pr = par;
+    DevWork w = W;
+    if (dtype == 0) {
+        DevProblem<double> P{gp.n, gp.p, (const double*)gp.Q, (const double*)gp.G, gp.q, gp.g, gp.lb, gp.ub};
+        void* args[] = {&P, &pr, &w};
+        return launch_any(&dfom_kernel<double, double>, cfg, args);
+    }
+    DevProblem<float> P{gp.n, gp.p, (const float*)gp.Q, (const float*)gp.G, gp.q, gp.g, gp.lb, gp.ub};
+    void* args[] = {&P, &pr, &w};
+    if (acc == 0) return launch_any(&dfom_kernel<float, double>, cfg, args);
+    return launch_any(&dfom_kernel<float, float>, cfg, args);
+}
+
+hipError_t launch_lanczos(int dtype, const LaunchCfg& cfg, const GenericProblem& gp, const LanczosWork& L,
+                          int k, int use_gtg) {
+    LanczosWork l = L;
+    int kk = k, ug = use_gtg;
+    if (dtype == 0) {
+        DevProblem<double> P{gp.n, gp.p, (const double*)gp.Q, (const double*)gp.G, gp.q, gp.g, gp.lb, gp.ub};
+        void* args[] = {&P, &l, &kk, &ug};
+        return launch_any(&lanczos_kernel<double>, cfg, args);
+    }
+    DevProblem<float> P{gp.n, gp.p, (const float*)gp.Q, (const float*)gp.G, gp.q, gp.g, gp.lb, gp.ub};
+    void* args[] = {&P, &l, &kk, &ug};
+    return launch_any(&lanczos_kernel<float>, cfg, args);
+}
+
+hipError_t launch_count_nonfinite(int dtype, const void* a, long len, unsigned* out, hipStream_t s) {
+    const int nb = (int)std::min<long>(1024, (len + 255) / 256 + 1);
+    if (dtype == 0)
+        hipLaunchKernelGGL(count_nonfinite_kernel<double>, dim3(nb), dim3(256), 0, s, (const double*)a, len, out);
+    else
+        hipLaunchKernelGGL(count_nonfinite_kernel<float>, dim3(nb), dim3(256), 0, s, (const float*)a, len, out);
+    return hipGetLastError();
+}
+
+}  // namespace duq

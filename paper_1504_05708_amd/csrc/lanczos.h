@@ -1,0 +1,196 @@
+// FP64 Lanczos estimate of extreme eigenvalues on the device (setup step of
+// the method: the constants lambda_min(Q), lambda_max(Q) and ||G||^2 that
+// define L_d (Sec. 2 eq. Ld) and the inner L, sigma (Sec. 3, Step 1)).
+//
+// Operator A is either Q (n x n) or G^T G (through G and G^T).  Full
+// reorthogonalisation (two classical Gram-Schmidt passes) keeps the Krylov
+// basis orthogonal in FP64; the extreme eigenvalues of the k x k tridiagonal
+// matrix are found by Sturm-sequence bisection.
+#pragma once
+#include "dfom_solver.h"
+
+namespace duq {
+
+template <typename T>
+struct Lanczos {
+    DevProblem<T> P;
+    LanczosWork L;
+    Team tm;
+    int k;
+    int use_gtg;
+    int nlo, nhi, plo, phi;
+    double* xl;
+    double* vl;
+    double* hl;      // LDS: k+2 reduced values
+    double* red;
+
+    // h[j] = sum_i V[j][i] w[i] for j < m over the team; result in hl.
+    __device__ bool dots(const double* w, int m) {
+        const int n = P.n;
+        const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        const int ncol = k + 2;
+        for (int j = wid; j < m; j += nw) {
+            double s = 0.0;
+            for (int i = nlo + lane; i < nhi; i += kWave) s += L.V[(long)j * n + i] * w[i];
+            s = wave_sum(s);
+            if (lane == 0) {
+                if (tm.size == 1) hl[j] = s;
+                else L.part[(long)tm.rank * ncol + j] = s;
+            }
+        }
+        if (tm.size == 1) { __syncthreads(); return true; }
+        if (tm.sync()) return false;
+        for (int j = wid; j < m; j += nw) {
+            double s = 0.0;
+            for (int b = lane; b < tm.size; b += kWave) s += L.part[(long)b * ncol + j];
+            s = wave_sum(s);
+            if (lane == 0) hl[j] = s;
+        }
+        __syncthreads();
+        // the next writer of part must not overtake readers: barrier
+        if (tm.sync()) return false;
+        return true;
+    }
+
+    __device__ bool apply(const double* v, double* w) {
+        const int n = P.n;
+        stage(v, n, xl);
+        if (!use_gtg) {
+            gemv_rows<T, double>(P.Q, n, nlo, nhi, n, xl, w, nullptr);
+            __syncthreads();
+            return true;
+        }
+        gemv_rows<T, double>(P.G, n, plo, phi, n, xl, L.r, nullptr);
+        __syncthreads();
+        for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) vl[i - plo] = L.r[i];
+        __syncthreads();
+        if (tm.size == 1) {
+            gemvT_rows<T, double>(P.G, n, plo, phi, n, vl, w, nullptr);
+            __syncthreads();
+            return true;
+        }
+        gemvT_rows<T, double>(P.G, n, plo, phi, n, vl, L.gtp + (long)tm.rank * n, nullptr);
+        if (tm.sync()) return false;
+        const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        for (int j = nlo + wid; j < nhi; j += nw) {
+            double s = 0.0;
+            for (int b = lane; b < tm.size; b += kWave) s += L.gtp[(long)b * n + j];
+            s = wave_sum(s);
+            if (lane == 0) w[j] = s;
+        }
+        __syncthreads();
+        return true;
+    }
+
+    // Number of eigenvalues of the tridiagonal (a, b) below x (Sturm count).
+    __device__ static int sturm(const double* a, const double* b, int m, double x) {
+        int cnt = 0;
+        double d = 1.0;
+        for (int i = 0; i < m; ++i) {
+            const double bb = i > 0 ? b[i] * b[i] : 0.0;
+            d = (a[i] - x) - (i > 0 ? bb / d : 0.0);
+            if (d == 0.0) d = -1e-300;
+            if (d < 0.0) ++cnt;
+        }
+        return cnt;
+    }
+
+    __device__ void run() {
+        const int n = P.n;
+        double* a = L.ab;        // written by rank 0 only, read back by it
+        double* b = L.ab + k;
+        // v_1: deterministic start vector with no special structure
+        for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x)
+            L.V[i] = 1.0 + 0.5 * sin(0.7 * i + 0.3) + 0.25 * cos(1.9 * i);
+        __syncthreads();
+        if (!dots(L.V, 1)) return;
+        {
+            const double s = 1.0 / sqrt(hl[0]);
+            for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x) L.V[i] *= s;
+        }
+        double alpha0 = 0.0;
+        int m = 0;
+        for (int j = 0; j < k; ++j) {
+            if (tm.size > 1 && tm.sync()) return;   // V[j] complete before it is staged
+            if (!apply(L.V + (long)j * n, L.w)) return;
+            // w <- w - V (V^T w), two classical Gram-Schmidt passes; the
+            // coefficient of v_j accumulates alpha_j = <A v_j, v_j>
+            double aj = 0.0;
+            for (int pass = 0; pass < 2; ++pass) {
+                if (!dots(L.w, j + 1)) return;
+                aj += hl[j];
+                for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x) {
+                    double s = L.w[i];
+                    for (int q = 0; q <= j; ++q) s -= hl[q] * L.V[(long)q * n + i];
+                    L.w[i] = s;
+                }
+                __syncthreads();
+            }
+            if (j == 0) alpha0 = aj;
+            if (!dots_self()) return;
+            const double beta = sqrt(hl[0]);
+            if (tm.rank == 0 && threadIdx.x == 0) {
+                a[j] = aj;
+                b[j + 1] = beta;
+            }
+            m = j + 1;
+            if (!(beta > 1e-13 * fabs(alpha0) + 1e-300)) break;   // invariant subspace
+            const double inv = 1.0 / beta;
+            for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x)
+                L.V[(long)(j + 1) * n + i] = L.w[i] * inv;
+        }
+        if (tm.rank == 0 && threadIdx.x == 0) {
+            // extreme eigenvalues of the m x m tridiagonal (a, b[1..m-1]) by bisection
+            double lo = INFINITY, hi = -INFINITY;
+            for (int i = 0; i < m; ++i) {
+                const double r = (i > 0 ? fabs(b[i]) : 0.0) + (i + 1 < m ? fabs(b[i + 1]) : 0.0);
+                lo = fmin(lo, a[i] - r);
+                hi = fmax(hi, a[i] + r);
+            }
+            double x0 = lo, x1 = hi;
+            for (int it = 0; it < 200; ++it) {
+                const double mid = 0.5 * (x0 + x1);
+                if (sturm(a, b, m, mid) >= 1) x1 = mid; else x0 = mid;
+            }
+            L.out[0] = 0.5 * (x0 + x1);
+            x0 = lo;
+            x1 = hi;
+            for (int it = 0; it < 200; ++it) {
+                const double mid = 0.5 * (x0 + x1);
+                if (sturm(a, b, m, mid) >= m) x1 = mid; else x0 = mid;
+            }
+            L.out[1] = 0.5 * (x0 + x1);
+            L.out[2] = m;
+        }
+    }
+
+    // hl[0] = ||w||^2 over the team.
+    __device__ bool dots_self() {
+        const int n = P.n;
+        (void)n;
+        const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
+        const int ncol = k + 2;
+        double s = 0.0;
+        for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x) s += L.w[i] * L.w[i];
+        double v[1] = {s};
+        block_allreduce<1>(v, red);
+        if (tm.size == 1) {
+            if (threadIdx.x == 0) hl[0] = v[0];
+            __syncthreads();
+            return true;
+        }
+        if (threadIdx.x == 0) L.part[(long)tm.rank * ncol + k + 1] = v[0];
+        if (tm.sync()) return false;
+        if (wid == 0) {
+            double t = 0.0;
+            for (int b = lane; b < tm.size; b += kWave) t += L.part[(long)b * ncol + k + 1];
+            t = wave_sum(t);
+            if (lane == 0) hl[0] = t;
+        }
+        __syncthreads();
+        if (tm.sync()) return false;
+        return true;
+    }
+};
+
+}  // namespace duq

@@ -1,0 +1,212 @@
+"""ctypes binding of libduq.so (include/duq.h).  Argument marshalling only.
+
+Host inputs are NumPy arrays; device inputs are torch tensors on the HIP
+device (PyTorch is used for device memory and streams, nothing else).  The
+library must be built (python -m paper_1504_05708_amd.build); loading fails
+loudly otherwise -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, Structure, c_char_p, c_double, c_int32, c_int64, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libduq.so")
+
+DUQ_OK, DUQ_EINVAL, DUQ_ENOMEM, DUQ_EDEVICE, DUQ_EMAXITER, DUQ_ENUMERIC, DUQ_EAGAIN, DUQ_ENOTFOUND = \
+    0, -1, -2, -3, -4, -5, -6, -7
+F64, F32, BF16 = 0, 1, 2
+HOST, DEVICE = 0, 1
+DGM, DFGM = 0, 1
+LAST, AVG = 0, 1
+CERT, FIXED = 0, 1
+INNER_AUTO, INNER_GM, INNER_FGM, INNER_FGM_SIGMA = 0, 1, 2, 3
+ACC_F64, ACC_F32 = 0, 1
+ENGINE_AUTO, ENGINE_BLOCK, ENGINE_GRID = 0, 1, 2
+TRACE_SCALARS = 16
+
+EXPORTS = ["duq_default_options", "duq_setup", "duq_solve", "duq_get_trace", "duq_get_constants",
+           "duq_destroy", "duq_last_error", "duq_strerror"]
+
+
+class DuqProblem(Structure):
+    _fields_ = [("n", c_int32), ("p", c_int32), ("dtype", c_int32), ("memspace", c_int32),
+                ("Q", c_void_p), ("G", c_void_p), ("q", c_void_p), ("g", c_void_p),
+                ("lb", c_void_p), ("ub", c_void_p)]
+
+
+class DuqOptions(Structure):
+    _fields_ = [("method", c_int32), ("output", c_int32), ("inner_rule", c_int32),
+                ("inner_variant", c_int32), ("accumulate", c_int32), ("engine", c_int32),
+                ("max_outer", c_int32), ("max_inner", c_int32), ("lanczos_steps", c_int32),
+                ("trace_outer", c_int32), ("eps_out", c_double), ("eps_in", c_double),
+                ("rho", c_double), ("lam_min", c_double), ("lam_max", c_double),
+                ("G_norm2", c_double), ("safety", c_double), ("switch_factor", c_double),
+                ("switch_stall", c_int32), ("reserved", c_int32 * 7)]
+
+
+class DuqResult(Structure):
+    _fields_ = [("status", c_int32), ("outer_iters", c_int32), ("inner_iters", c_int64),
+                ("gt_rows", c_int64), ("f", c_double), ("lb_dual", c_double), ("gap", c_double),
+                ("feas", c_double), ("time_ms", c_double), ("f64_outer_iters", c_int32),
+                ("engine", c_int32), ("lam_min", c_double), ("lam_max", c_double),
+                ("G_norm2", c_double), ("reserved", c_double * 4)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class DuqError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"duq error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libduq.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_1504_05708_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    L.duq_default_options.argtypes = [POINTER(DuqOptions)]
+    L.duq_default_options.restype = None
+    L.duq_setup.argtypes = [POINTER(DuqProblem), POINTER(DuqOptions), c_void_p, POINTER(c_void_p)]
+    L.duq_setup.restype = c_int32
+    L.duq_solve.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(DuqResult)]
+    L.duq_solve.restype = c_int32
+    L.duq_get_trace.argtypes = [c_void_p, c_void_p, c_int32, POINTER(c_int32)]
+    L.duq_get_trace.restype = c_int32
+    L.duq_get_constants.argtypes = [c_void_p] + [POINTER(c_double)] * 6
+    L.duq_get_constants.restype = c_int32
+    L.duq_destroy.argtypes = [c_void_p]
+    L.duq_destroy.restype = None
+    L.duq_last_error.argtypes = []
+    L.duq_last_error.restype = c_char_p
+    L.duq_strerror.argtypes = [c_int32]
+    L.duq_strerror.restype = c_char_p
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().duq_last_error().decode()
+
+
+def default_options(**kw) -> DuqOptions:
+    o = DuqOptions()
+    lib().duq_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return ctypes.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(c_void_p)
+
+
+def _stream_of(t):
+    if t is not None and hasattr(t, "data_ptr"):
+        import torch
+        return c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+    return c_void_p(None)
+
+
+class Solver:
+    """One QP set up on the device (duq_setup) and solved with duq_solve.
+
+    Q, G: NumPy float64/float32 arrays (copied) or torch tensors on the GPU
+    (borrowed: they must outlive the solver).  q, g, lb, ub: float64 of the
+    same kind."""
+
+    def __init__(self, Q, q, G, g, lb, ub, **opts):
+        self._keep = []
+        dev = hasattr(Q, "data_ptr")
+        if dev:
+            import torch
+            dt = {torch.float64: F64, torch.float32: F32}[Q.dtype]
+            for t in (q, g, lb, ub):
+                assert t.dtype == torch.float64 and t.is_contiguous()
+            Q = Q.contiguous()
+            G = G.contiguous()
+        else:
+            Q = np.ascontiguousarray(Q)
+            dt = {np.dtype(np.float64): F64, np.dtype(np.float32): F32}[Q.dtype]
+            G = np.ascontiguousarray(G, dtype=Q.dtype)
+            q, g, lb, ub = (np.ascontiguousarray(v, dtype=np.float64) for v in (q, g, lb, ub))
+        self._keep = [Q, G, q, g, lb, ub]
+        n, p = int(Q.shape[0]), int(G.shape[0])
+        self.n, self.p = n, p
+        prob = DuqProblem(n, p, dt, DEVICE if dev else HOST, _ptr(Q), _ptr(G) if p else None,
+                          _ptr(q), _ptr(g) if p else None, _ptr(lb), _ptr(ub))
+        self.opts = default_options(**opts)
+        h = c_void_p()
+        rc = lib().duq_setup(ctypes.byref(prob), ctypes.byref(self.opts), _stream_of(Q if dev else None),
+                             ctypes.byref(h))
+        if rc != DUQ_OK:
+            raise DuqError(rc, last_error())
+        self._h = h
+        if not dev:
+            self._keep = []   # host data was copied
+
+    def solve(self, x0=None, lam0=None, check=True):
+        x = np.empty(self.n)
+        lam = np.empty(self.p)
+        res = DuqResult()
+        x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
+        l0a = None if lam0 is None else np.ascontiguousarray(lam0, dtype=np.float64)
+        rc = lib().duq_solve(self._h, _ptr(x0a), _ptr(l0a), _ptr(x), _ptr(lam) if self.p else None,
+                             ctypes.byref(res))
+        if check and rc not in (DUQ_OK, DUQ_EMAXITER):
+            raise DuqError(rc, last_error())
+        return x, lam, res.as_dict()
+
+    def trace(self, max_records: int):
+        per = TRACE_SCALARS + 2 * self.p + self.n
+        out = np.zeros((max_records, per))
+        nrec = c_int32()
+        rc = lib().duq_get_trace(self._h, _ptr(out), max_records, ctypes.byref(nrec))
+        if rc != DUQ_OK:
+            raise DuqError(rc, last_error())
+        out = out[:nrec.value]
+        p, n = self.p, self.n
+        S = TRACE_SCALARS
+        return dict(scalars=out[:, :S], lam=out[:, S:S + p], mu=out[:, S + p:S + 2 * p],
+                    u=out[:, S + 2 * p:S + 2 * p + n])
+
+    def constants(self) -> dict:
+        vals = [c_double() for _ in range(6)]
+        rc = lib().duq_get_constants(self._h, *[ctypes.byref(v) for v in vals])
+        if rc != DUQ_OK:
+            raise DuqError(rc, last_error())
+        return dict(zip(["lam_min", "lam_max", "G_norm2", "Ld", "L_in", "sigma_in"], [v.value for v in vals]))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().duq_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,275 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+FP64 path: iterates lambda^k, mu^k, ubar^k match to 1e-9 relative over the
+first 200 outer iterations and the inner step counts t_k match exactly.
+Both sides get the same spectral constants (the oracle's exact ones).
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import dfom
+from oracle.ipm import ipm_qp
+from paper_1504_05708_amd import duq, gen
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-9
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    duq.lib()
+
+
+def consts_of(qp, rho=0.0, eps_in=1e-6):
+    return dfom.problem_constants(qp.Q, qp.G, qp.lb, qp.ub, rho, eps_in)
+
+
+def gpu_solver(qp, c, dtype=np.float64, **kw):
+    kw.setdefault("lam_min", c.lam_min)
+    kw.setdefault("lam_max", c.lam_max)
+    kw.setdefault("G_norm2", c.G_norm2 if qp.p else 0.0)
+    return duq.Solver(qp.Q.astype(dtype), qp.q, qp.G.astype(dtype), qp.g, qp.lb, qp.ub, **kw)
+
+
+def close(a, b, rel=REL, what=""):
+    a = np.asarray(a, float)
+    b = np.asarray(b, float)
+    if a.size == 0:
+        return
+    scale = max(1.0, float(np.max(np.abs(b))))
+    err = float(np.max(np.abs(a - b)))
+    assert err <= rel * scale, f"{what}: max err {err:.3e} > {rel:.1e} * {scale:.3e}"
+
+
+def compare_trace(tr, log, K, what):
+    S = tr["scalars"]
+    assert S.shape[0] == K, (S.shape, K)
+    assert len(log) >= K
+    for k in range(K):
+        e = log[k]
+        assert int(S[k, 0]) == e["k"]
+        assert int(S[k, 1]) == e["t"], f"{what}: inner count differs at k={k + 1}: {int(S[k, 1])} vs {e['t']}"
+        close(tr["lam"][k], e["lam"], what=f"{what} lambda^{k + 1}")
+        close(tr["mu"][k], e["mu"], what=f"{what} mu^{k + 1}")
+        close(tr["u"][k], e["u"], what=f"{what} ubar^{k + 1}")
+        sc = max(1.0, abs(e["dbar"]))
+        assert abs(S[k, 3] - e["dbar"]) <= REL * sc, (what, k)
+        assert abs(S[k, 2] - e["gap"]) <= REL * sc, (what, k)
+        if math.isfinite(e["LB"]):
+            assert abs(S[k, 4] - e["LB"]) <= REL * sc, (what, k)
+        assert S[k, 5] == pytest.approx(e["theta"], rel=1e-14)
+        assert S[k, 6] == pytest.approx(e["S"], rel=1e-14)
+
+
+def run_trace_case(qp, method, output, rho=0.0, K=200, engine=duq.ENGINE_AUTO, dtype=np.float64,
+                   eps_in=1e-6, variant=dfom.INNER_AUTO):
+    qpo = qp if dtype == np.float64 else qp.rounded(dtype)
+    c = consts_of(qpo, rho, eps_in)
+    opts = dfom.Options(method=method, output=output, rho=rho, eps_out=1e-13, eps_in=eps_in,
+                        max_outer=K, log_vectors=K, inner_variant=variant)
+    ref = dfom.dfom_solve(qpo, opts, consts=c)
+    with gpu_solver(qp, c, dtype, method=method, output=output, rho=rho, eps_out=1e-13, eps_in=eps_in,
+                    max_outer=K, trace_outer=K, engine=engine, inner_variant=variant) as s:
+        x, lam, res = s.solve()
+        tr = s.trace(K)
+    Kg, Ko = res["outer_iters"], ref.outer_iters
+    what = f"n={qp.n} p={qp.p} m={method} o={output} rho={rho}"
+    # Tiny instances reach the 1e-13 outer test at the rounding floor, where the
+    # two summation orders may decide one iteration apart: compare the common
+    # prefix and require the later side to sit at the floor where the other stopped.
+    Kc = min(Kg, Ko)
+    compare_trace({k: v[:Kc] for k, v in tr.items()}, ref.log, Kc, what)
+    if Kg != Ko:
+        e = ref.log[Kc - 1] if Ko > Kg else None
+        Fk, LBk, fk = (e["F"], e["LB"], e["feas"]) if e else (tr["scalars"][Kc - 1, 7], tr["scalars"][Kc - 1, 4],
+                                                               tr["scalars"][Kc - 1, 8])
+        sc = max(1.0, abs(Fk))
+        assert Fk - LBk <= 1e-11 * sc and fk <= 1e-11 * max(1.0, np.linalg.norm(qp.g)), (what, Kg, Ko)
+    else:
+        assert res["inner_iters"] == ref.inner_iters
+        assert res["status"] == (duq.DUQ_EMAXITER if ref.status == dfom.STATUS_MAXITER else duq.DUQ_OK)
+    return ref, x, lam, res
+
+
+# ----------------------------------------------------------------------------
+# config 0 (n=50, p=25): iterate parity over 200 outer iterations
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("method,output", [(duq.DFGM, duq.LAST), (duq.DGM, duq.AVG),
+                                           (duq.DGM, duq.LAST), (duq.DFGM, duq.AVG)])
+def test_config0_trace_parity(method, output):
+    print(f"[case] config0 trace m={method} o={output}", flush=True)
+    run_trace_case(gen.config0(), method, output)
+
+
+@pytest.mark.parametrize("rho", [0.5, 1.0])
+def test_config0_augmented_trace_parity(rho):
+    print(f"[case] config0 augmented rho={rho}", flush=True)
+    run_trace_case(gen.config0(), duq.DFGM, duq.LAST, rho=rho, K=120)
+
+
+def test_config0_inner_fgm_variant_parity():
+    print("[case] config0 inner FGM theta rule", flush=True)
+    run_trace_case(gen.config0(), duq.DFGM, duq.LAST, K=60, variant=dfom.INNER_FGM)
+
+
+@pytest.mark.parametrize("method,output,eps_in", [(duq.DFGM, duq.LAST, 1e-8), (duq.DGM, duq.LAST, 1e-6),
+                                                  (duq.DFGM, duq.AVG, 1e-8)])
+def test_config0_converged_solution(method, output, eps_in):
+    print(f"[case] config0 converged m={method} o={output}", flush=True)
+    qp = gen.config0()
+    c = consts_of(qp, 0.0, eps_in)
+    ref = dfom.dfom_solve(qp, dfom.Options(method=method, output=output, eps_out=1e-4, eps_in=eps_in,
+                                           max_outer=100000), consts=c)
+    with gpu_solver(qp, c, method=method, output=output, eps_out=1e-4, eps_in=eps_in, max_outer=100000) as s:
+        x, lam, res = s.solve()
+    assert res["status"] == duq.DUQ_OK
+    assert res["outer_iters"] == ref.outer_iters
+    assert res["inner_iters"] == ref.inner_iters
+    close(x, ref.x, rel=1e-7, what="x")
+    close(lam, ref.lam, rel=1e-7, what="lambda")
+    _, fstar, _ = ipm_qp(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub)
+    assert abs(res["f"] - fstar) / abs(fstar) <= 1e-4
+    assert res["feas"] / max(1.0, np.linalg.norm(qp.g)) <= 1e-4
+    assert res["lb_dual"] <= fstar + 1e-9 * abs(fstar)
+
+
+# ----------------------------------------------------------------------------
+# ragged shapes, both engines
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("engine", [duq.ENGINE_BLOCK, duq.ENGINE_GRID])
+@pytest.mark.parametrize("n,p", [(1, 1), (2, 0), (3, 5), (63, 31), (64, 64), (65, 1), (130, 257), (257, 100)])
+def test_ragged_shapes_parity(engine, n, p):
+    print(f"[case] ragged n={n} p={p} engine={engine}", flush=True)
+    qp = gen.random_dense_qp(n, p, seed=1000 + n + 7 * p)
+    run_trace_case(qp, duq.DFGM, duq.LAST, K=40, engine=engine)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_grid_medium_parity(dtype):
+    print(f"[case] grid n=1536 dtype={np.dtype(dtype).name}", flush=True)
+    qp = gen.config1(n=1536, p=768, seed=11)
+    run_trace_case(qp, duq.DFGM, duq.LAST, K=30, engine=duq.ENGINE_GRID, dtype=dtype)
+
+
+def test_fp32_storage_block_parity():
+    print("[case] fp32 storage block", flush=True)
+    qp = gen.random_dense_qp(301, 150, seed=5)
+    run_trace_case(qp, duq.DGM, duq.AVG, K=60, engine=duq.ENGINE_BLOCK, dtype=np.float32)
+
+
+def test_grid_augmented_parity():
+    print("[case] grid rho=1 n=1024", flush=True)
+    qp = gen.config1(n=1024, p=512, seed=12)
+    run_trace_case(qp, duq.DFGM, duq.LAST, rho=1.0, K=20, engine=duq.ENGINE_GRID)
+
+
+# ----------------------------------------------------------------------------
+# full size of the large single QP (n=8192, p=4096): first outer iterations
+# ----------------------------------------------------------------------------
+
+def test_config1_full_size_first_iterations():
+    print("[case] config1 full size, 2 outer iterations", flush=True)
+    qp = gen.config1()
+    run_trace_case(qp, duq.DFGM, duq.LAST, K=2, engine=duq.ENGINE_GRID)
+
+
+# ----------------------------------------------------------------------------
+# constants (Lanczos) and robustness
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,p,engine", [(50, 25, duq.ENGINE_BLOCK), (1536, 768, duq.ENGINE_GRID)])
+def test_lanczos_constants(n, p, engine):
+    print(f"[case] lanczos n={n}", flush=True)
+    qp = gen.config1(n=n, p=p, seed=13) if n > 100 else gen.config0()
+    ev = np.linalg.eigvalsh(qp.Q)
+    g2 = np.linalg.norm(qp.G, 2) ** 2
+    with duq.Solver(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub, engine=engine, lanczos_steps=96) as s:
+        c = s.constants()
+    sf = 1.02
+    # safe side after the safety factor, and accurate before it
+    assert c["lam_max"] >= ev[-1] and c["lam_max"] / sf == pytest.approx(ev[-1], rel=2e-3)
+    assert c["lam_min"] <= ev[0] and c["lam_min"] * sf == pytest.approx(ev[0], rel=2e-2)
+    assert c["G_norm2"] >= g2 and c["G_norm2"] / sf == pytest.approx(g2, rel=2e-3)
+
+
+def test_estimated_constants_reach_accuracy():
+    print("[case] estimated constants solve", flush=True)
+    qp = gen.config0()
+    with duq.Solver(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub, method=duq.DGM, eps_out=1e-4) as s:
+        x, lam, res = s.solve()
+    _, fstar, _ = ipm_qp(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub)
+    assert res["status"] == duq.DUQ_OK
+    assert abs(res["f"] - fstar) / abs(fstar) <= 1e-4
+
+
+def test_invalid_inputs_rejected():
+    qp = gen.random_dense_qp(10, 4, seed=3)
+    Q = qp.Q.copy()
+    Q[2, 3] = np.nan
+    with pytest.raises(duq.DuqError) as e:
+        duq.Solver(Q, qp.q, qp.G, qp.g, qp.lb, qp.ub)
+    assert e.value.code == duq.DUQ_EINVAL
+    lb = qp.lb.copy()
+    lb[0] = 2.0
+    with pytest.raises(duq.DuqError) as e:
+        duq.Solver(qp.Q, qp.q, qp.G, qp.g, lb, qp.ub)
+    assert e.value.code == duq.DUQ_EINVAL
+    with pytest.raises(duq.DuqError):
+        duq.Solver(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub, eps_out=0.0)
+
+
+def test_max_outer_one_writes_iterate():
+    qp = gen.config0()
+    c = consts_of(qp)
+    ref = dfom.dfom_solve(qp, dfom.Options(max_outer=1), consts=c)
+    with gpu_solver(qp, c, max_outer=1) as s:
+        x, lam, res = s.solve(check=False)
+    assert res["status"] == duq.DUQ_EMAXITER and res["outer_iters"] == 1
+    close(x, ref.x, what="x after one iteration")
+    close(lam, ref.lam, what="lambda after one iteration")
+
+
+def test_warm_start_inputs():
+    qp = gen.config0()
+    c = consts_of(qp)
+    rng = np.random.default_rng(0)
+    x0 = rng.uniform(-1.2, 1.2, qp.n)
+    l0 = np.abs(rng.standard_normal(qp.p))
+    ref = dfom.dfom_solve(qp, dfom.Options(max_outer=30, eps_out=1e-13, log_vectors=30), consts=c,
+                          x_start=np.clip(x0, qp.lb, qp.ub), lam_start=l0)
+    with gpu_solver(qp, c, max_outer=30, eps_out=1e-13, trace_outer=30) as s:
+        x, lam, res = s.solve(x0=x0, lam0=l0, check=False)
+        tr = s.trace(30)
+    compare_trace(tr, ref.log, 30, "warm start")
+
+
+def test_device_resident_inputs():
+    import torch
+    qp = gen.config0()
+    c = consts_of(qp)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    ref = dfom.dfom_solve(qp, dfom.Options(max_outer=50, eps_out=1e-13), consts=c)
+    with duq.Solver(d(qp.Q), d(qp.q), d(qp.G), d(qp.g), d(qp.lb), d(qp.ub), max_outer=50, eps_out=1e-13,
+                    lam_min=c.lam_min, lam_max=c.lam_max, G_norm2=c.G_norm2) as s:
+        x, lam, res = s.solve(check=False)
+    close(x, ref.x, what="x")
+
+
+def test_deterministic_across_runs():
+    qp = gen.config1(n=1536, p=768, seed=14)
+    c = consts_of(qp)
+    with gpu_solver(qp, c, max_outer=25, eps_out=1e-13, engine=duq.ENGINE_GRID) as s:
+        x1, l1, r1 = s.solve(check=False)
+        x2, l2, r2 = s.solve(check=False)
+    assert np.array_equal(x1, x2) and np.array_equal(l1, l2)
+    assert r1["inner_iters"] == r2["inner_iters"]
