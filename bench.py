@@ -1,0 +1,238 @@
+"""Benchmark of the DFOM hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision f64|f32]
+                    [--method dfgm|dgm] [--eps-in E] [--rho R] [--no-cpu]
+
+Workload (one step = one end-to-end solve of the large single QP):
+  random_dense_qp(n=8192, p=4096, seed=1, reg=0.01): Q = A^T A / n + 0.01 I with
+  A (2n x n) i.i.d. N(0,1), G i.i.d. N(0,1), g = -(G x0) - s (strictly
+  feasible), box [-1, 1].  Inputs are resident in HBM before timing.  A step
+  runs duq_setup (Lanczos constants on the device, workspace) + duq_solve
+  (Algorithm DFOM to the on-device outer test at eps_out = 1e-4) +
+  duq_destroy.
+
+Prints one JSON line.  `roofline` covers the dominant kernel (the
+persistent DFOM kernel, one launch per solve): algorithmic matrix bytes per
+launch / its HIP-event duration on the stream it runs on.  `cpu_baseline`
+times the FP64 NumPy oracle on a bounded sample of the same solve.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "QP solves/s at 1e-4 subopt+feas, batched vs plain; HBM GB/s; p50/p99 latency"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--method", choices=["dfgm", "dgm"], default="dfgm")
+    ap.add_argument("--output", choices=["last", "avg"], default="last")
+    ap.add_argument("--eps-in", type=float, default=None)
+    ap.add_argument("--eps-out", type=float, default=1e-4)
+    ap.add_argument("--rho", type=float, default=0.0)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--p", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run only a plain device copy of 1 GiB (counter calibration)")
+    return ap.parse_args()
+
+
+def copy_probe():
+    import torch
+    x = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)   # 1 GiB
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each_way": x.numel() * 8, "launches": 3}))
+
+
+def reference_fstar(key):
+    path = os.path.join(ROOT, "tests", "golden", "reference_values.json")
+    if os.path.exists(path):
+        vals = json.load(open(path))
+        if key in vals:
+            return vals[key]["fstar"]
+    return None
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
+              "the single large QP would shard by rows over RCCL, which is not built.", file=sys.stderr)
+        sys.exit(2)
+    if a.copy_probe:
+        copy_probe()
+        return
+    import torch
+    from paper_1504_05708_amd import duq, gen
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    duq.lib()   # fails loudly when the HIP library is missing
+    method = duq.DFGM if a.method == "dfgm" else duq.DGM
+    output = duq.LAST if a.output == "last" else duq.AVG
+    eps_in = a.eps_in if a.eps_in is not None else (1e-8 if method == duq.DFGM else 1e-6)
+    t0 = time.time()
+    qp = gen.config1(n=a.n, p=a.p, seed=1)
+    gen_s = time.time() - t0
+    npdt = np.float64 if a.precision == "f64" else np.float32
+    s_bytes = 8 if a.precision == "f64" else 4
+    dev = lambda v, dt=np.float64: torch.from_numpy(np.ascontiguousarray(v.astype(dt))).cuda()
+    Qd, Gd = dev(qp.Q, npdt), dev(qp.G, npdt)
+    qd, gd, lbd, ubd = dev(qp.q), dev(qp.g), dev(qp.lb), dev(qp.ub)
+    torch.cuda.synchronize()
+    opts = dict(method=method, output=output, eps_out=a.eps_out, eps_in=eps_in, rho=a.rho,
+                max_outer=200000, engine=duq.ENGINE_GRID)
+
+    def step():
+        t = time.perf_counter()
+        s = duq.Solver(Qd, qd, Gd, gd, lbd, ubd, **opts)
+        t_setup = time.perf_counter() - t
+        x, lam, res = s.solve()
+        consts = s.constants()
+        s.close()
+        return x, lam, res, consts, t_setup
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    results = []
+    t_wall = time.perf_counter()
+    ev0.record()
+    for _ in range(a.steps):
+        results.append(step())
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ev_ms = ev0.elapsed_time(ev1)
+    ms_per_step = 1e3 * wall / a.steps
+    x, lam, res, consts, _ = results[-1]
+    for r in results:
+        assert r[2]["status"] == duq.DUQ_OK, r[2]
+    n, p = a.n, a.p
+    kern_ms = [r[2]["time_ms"] for r in results]
+    setup_ms = [1e3 * r[4] for r in results]
+    kern_avg = float(np.mean(kern_ms))
+    # algorithmic matrix bytes of one launch: every Q product (inner steps +
+    # the initial warm-start product), one G product per outer iteration and
+    # per extra last-iterate solve (rho = 0), and the G rows actually read by
+    # G^T v (rows with v_i = 0 need no read).
+    inner, outer, gt_rows = res["inner_iters"], res["outer_iters"], res["gt_rows"]
+    nn = float(n) * n * s_bytes
+    pn = float(p) * n * s_bytes
+    if a.rho > 0.0:
+        q_products = inner + 1
+        g_products = inner + 1
+    else:
+        q_products = inner + 1
+        g_products = outer + (1 if (method == duq.DFGM and output == duq.LAST) else 0)
+    alg_bytes = q_products * nn + g_products * pn + gt_rows * n * s_bytes
+    achieved = alg_bytes / (kern_avg * 1e-3) / 1e9
+    F, LB, feas = res["f"], res["lb_dual"], res["feas"]
+    gnorm = float(np.linalg.norm(qp.g))
+    acc = {"cert_subopt_rel": (F - LB) / max(1.0, abs(F)), "feas_rel": feas / max(1.0, gnorm)}
+    fref = reference_fstar("config1_f64" if a.precision == "f64" else "config1_f32")
+    if fref is not None and a.n == 8192 and a.p == 4096:
+        acc["subopt_rel_vs_ipm"] = abs(F - fref) / max(1.0, abs(fref))
+    value = a.steps / wall
+    line = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"single dense QP n={n} p={p}: Q=A^T A/n+0.01I (A {2 * n}x{n} N(0,1)), G N(0,1), "
+                        f"g=-(G x0)-s strictly feasible, box [-1,1], seed 1; "
+                        f"{a.method.upper()}-{a.output} eps_out={a.eps_out:g} eps_in={eps_in:g} rho={a.rho:g}; "
+                        f"Q,G stored {a.precision}, FP64 arithmetic; end-to-end step = setup (Lanczos "
+                        f"constants) + solve",
+            "n": n, "p": p, "storage": a.precision, "method": a.method, "output": a.output,
+            "eps_out": a.eps_out, "eps_in": eps_in, "rho": a.rho,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "kernel": "dfom_kernel (persistent cooperative, one launch per solve)",
+            "alg_bytes_per_launch": alg_bytes,
+            "launch_ms_avg": round(kern_avg, 3),
+        },
+        "solve": {"outer_iters": outer, "inner_iters": inner, "gt_rows_read": gt_rows,
+                  "f": F, "lb": LB, "feas": feas, "online_solves_per_s": round(1e3 / kern_avg, 4),
+                  "setup_ms_avg": round(float(np.mean(setup_ms)), 2),
+                  "event_ms_per_step": round(ev_ms / a.steps, 3),
+                  "constants": consts},
+        "accuracy": acc,
+        "gen_seconds": round(gen_s, 1),
+    }
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(qp if a.precision == "f64" else qp.rounded(np.float32), consts, res,
+                                            method, output, eps_in, a)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(qp, consts, res, method, output, eps_in, a):
+    """The FP64 oracle on the host cores: the first outer iterations of the same
+    solve (same constants), stopped after about `cpu_seconds`, then scaled by
+    matrix-pass count to the full solve the GPU performed."""
+    from oracle import dfom
+    cores = len(os.sched_getaffinity(0))
+    opts = dfom.Options(method=method, output=output, eps_out=a.eps_out, eps_in=eps_in, rho=a.rho,
+                        lam_min=consts["lam_min"], lam_max=consts["lam_max"], G_norm2=consts["G_norm2"])
+    # a one-iteration probe sizes the sample to about `cpu_seconds`
+    opts.max_outer = 1
+    t0 = time.perf_counter()
+    dfom.dfom_solve(qp, opts)
+    t_one = time.perf_counter() - t0
+    k = int(max(1, min(res["outer_iters"], a.cpu_seconds / max(t_one, 1e-3))))
+    opts.max_outer = k
+    t1 = time.perf_counter()
+    r = dfom.dfom_solve(qp, opts)
+    sample_s = time.perf_counter() - t1
+    # one inner step of the oracle reads Q twice (gradient at y and at x), one outer
+    # iteration reads G twice (G^T mu and G u): weight passes by bytes
+    n, p = qp.n, qp.p
+    per_inner = 2.0 * n * n
+    per_outer = 2.0 * p * n
+    sample_work = r.inner_iters * per_inner + k * per_outer
+    full_work = res["inner_iters"] * per_inner + res["outer_iters"] * per_outer
+    est_s = sample_s * full_work / max(sample_work, 1.0)
+    return {"value": round(1.0 / est_s, 6), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {k} outer iterations ({r.inner_iters} inner steps) of the same solve in "
+                      f"{sample_s:.1f} s, scaled by matrix passes to the full solve "
+                      f"({res['outer_iters']} outer, {res['inner_iters']} inner)",
+            "est_seconds_per_solve": round(est_s, 1)}
+
+
+if __name__ == "__main__":
+    main()

@@ -47,55 +47,69 @@ __device__ __forceinline__ void block_allreduce(double (&v)[K], double* scratch)
     __syncthreads();
 }
 
+// Data that crosses workgroups of a cooperative grid is written and read only
+// with device-scope relaxed atomics.  On this chip family those write through
+// and read around the per-XCD L2, so no device-scope fence (which writes back
+// and invalidates the whole L2) is needed at a barrier: a thread drains its own
+// stores with s_waitcnt before the workgroup announces its arrival.
+__device__ __forceinline__ void xstore(double* p, double v) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), __double_as_longlong(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double xload(const double* p) {
+    return __longlong_as_double(__hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT));
+}
+
 // A team is either one workgroup (size 1) or every workgroup of a
-// cooperative launch.  The grid barrier spins with a bounded count so that
-// every wave exits even if a peer never arrives; the failure is flagged in
-// bar[2] and reported by the host.
+// cooperative launch.  Grid barrier: each workgroup publishes its arrival
+// epoch in its own 128-byte line, workgroup 0 polls all of them in parallel
+// and publishes the generation.  Every spin is bounded, so each wave exits
+// even if a peer never arrives; the failure is flagged in bar[kBarErr] and
+// reported by the host.
 struct Team {
     int rank;
     int size;
     unsigned* bar;
+    unsigned epoch;
+
+    __device__ __forceinline__ bool spin_until(unsigned* a) const {
+        unsigned spins = 0;
+        while ((int)(__hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - epoch) < 0) {
+            __builtin_amdgcn_s_sleep(1);
+            ++spins;
+            if ((spins & 1023u) == 0u &&
+                __hip_atomic_load(&bar[kBarErr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+                return false;   // another workgroup gave up
+            if (spins > (1u << 23)) {   // far beyond any phase: a peer is gone
+                __hip_atomic_store(&bar[kBarErr], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return false;
+            }
+        }
+        return true;
+    }
 
     // Returns true when the team must abort (barrier timeout seen).
-    __device__ __forceinline__ bool sync() const {
+    __device__ __forceinline__ bool sync() {
         if (size == 1) {
             __syncthreads();
             return false;
         }
         __shared__ int s_abort;
+        __builtin_amdgcn_s_waitcnt(0);   // this thread's device-scope stores are complete
         __syncthreads();
-        if (threadIdx.x == 0) {
-            int abort = 0;
-            __threadfence();  // release this block's writes at device scope
-            const unsigned gen0 =
-                __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned arrived =
-                __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            if (arrived == (unsigned)size - 1u) {
-                __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&bar[1], gen0 + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                unsigned spins = 0;
-                while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen0) {
-                    __builtin_amdgcn_s_sleep(2);
-                    ++spins;
-                    if ((spins & 1023u) == 0u &&
-                        __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                        abort = 1;   // another block gave up
-                        break;
-                    }
-                    if (spins > (1u << 23)) {  // far beyond any phase: a peer is gone
-                        __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        abort = 1;
-                        break;
-                    }
-                }
-            }
-            __threadfence();  // acquire: see every block's writes
-            if (!abort)
-                abort = __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
-            s_abort = abort;
+        ++epoch;
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&bar[kBarFlag + 32 * rank], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (rank == 0) {
+            for (int b = threadIdx.x; b < size; b += blockDim.x) spin_until(&bar[kBarFlag + 32 * b]);
+            __syncthreads();
+            if (threadIdx.x == 0) __hip_atomic_store(&bar[0], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (threadIdx.x == 0) {
+            spin_until(&bar[0]);
         }
+        if (threadIdx.x == 0)
+            s_abort = __hip_atomic_load(&bar[kBarErr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
         __syncthreads();
         return s_abort != 0;
     }

@@ -363,7 +363,7 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
         h->W.gtp = c.take<double>(nb > 1 ? (size_t)nb * n : 1);
         h->W.trace = c.take<double>(trace > 0 ? (size_t)trace * (kTraceScalars + 2 * p + n) : 1);
         h->W.st = c.take<DevState>(1);
-        h->W.bar = c.take<unsigned>(4);
+        h->W.bar = c.take<unsigned>(bar_words(nb));
         h->xstage = c.take<double>(n);
         h->lstage = c.take<double>(pp);
     };
@@ -442,7 +442,7 @@ int estimate_constants(duq_handle* h, const DeviceInfo& di) {
         L.gtp = c.take<double>(nb > 1 ? (size_t)nb * n : 1);
         L.ab = c.take<double>(2 * (size_t)k + 2);
         L.out = c.take<double>(4);
-        L.bar = c.take<unsigned>(4);
+        L.bar = c.take<unsigned>(bar_words(nb));
     };
     carve(c0);
     void* buf = nullptr;
@@ -458,15 +458,15 @@ int estimate_constants(duq_handle* h, const DeviceInfo& di) {
     }
     GenericProblem gp{n, p, h->dQ, h->dG, h->dq, h->dg, h->dlb, h->dub};
     double outQ[4] = {0, 0, 0, 0}, outG[4] = {0, 0, 0, 0};
-    unsigned flag[4] = {0, 0, 0, 0};
+    unsigned flag = 0;
     auto run = [&](int use_gtg, double* out) -> int {
         hipError_t e = hipMemsetAsync(buf, 0, c0.off, h->stream);
         e = e ? e : launch_lanczos(h->dtype, cfg, gp, L, k, use_gtg);
         e = e ? e : hipMemcpyAsync(out, L.out, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
-        e = e ? e : hipMemcpyAsync(flag, L.bar, 4 * sizeof(unsigned), hipMemcpyDeviceToHost, h->stream);
+        e = e ? e : hipMemcpyAsync(&flag, L.bar + kBarErr, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream);
         e = e ? e : hipStreamSynchronize(h->stream);
         if (e != hipSuccess) return fail(DUQ_EDEVICE, std::string("Lanczos: ") + hipGetErrorString(e));
-        if (flag[2]) return fail(DUQ_EDEVICE, "Lanczos: grid barrier timeout");
+        if (flag) return fail(DUQ_EDEVICE, "Lanczos: grid barrier timeout");
         return DUQ_OK;
     };
     int rc = DUQ_OK;
@@ -512,7 +512,7 @@ extern "C" int duq_solve(duq_handle* h, const double* x0, const double* lam0, do
         HIP_TRY(hipMemcpyAsync(h->lstage, lam0, p * sizeof(double), hipMemcpyHostToDevice, h->stream));
     }
     HIP_TRY(hipMemsetAsync(h->W.st, 0, sizeof(DevState), h->stream));
-    HIP_TRY(hipMemsetAsync(h->W.bar, 0, 4 * sizeof(unsigned), h->stream));
+    HIP_TRY(hipMemsetAsync(h->W.bar, 0, bar_words(h->cfg.nblocks) * sizeof(unsigned), h->stream));
     DevWork W = h->W;
     W.x0 = h->xstage;
     W.lam0 = h->lstage;
@@ -540,16 +540,16 @@ extern "C" int duq_solve(duq_handle* h, const double* x0, const double* lam0, do
     HIP_TRY(launch_dfom(h->dtype, h->dtype == DUQ_F32 ? o.accumulate : 0, h->cfg, gp, par, W));
     HIP_TRY(hipEventRecord(h->ev1, h->stream));
     DevState st;
-    unsigned bar[4];
+    unsigned bar_err = 0;
     HIP_TRY(hipMemcpyAsync(&st, h->W.st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipMemcpyAsync(bar, h->W.bar, sizeof(bar), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(&bar_err, h->W.bar + kBarErr, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
     if (x_out) HIP_TRY(hipMemcpyAsync(x_out, h->W.xout, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     if (lam_out && p > 0)
         HIP_TRY(hipMemcpyAsync(lam_out, h->W.lamp, p * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-    if (bar[2]) return fail(DUQ_EDEVICE, "grid barrier timeout (a workgroup did not arrive)");
+    if (bar_err) return fail(DUQ_EDEVICE, "grid barrier timeout (a workgroup did not arrive)");
     h->last_records = st.n_trace;
     int code = st.status == 0 ? DUQ_OK : (st.status == 1 ? DUQ_EMAXITER : DUQ_ENUMERIC);
     if (res) {

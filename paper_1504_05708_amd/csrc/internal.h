@@ -6,6 +6,12 @@ namespace duq {
 
 // Scalars reduced per block: count of slots in one partial record.
 constexpr int kNP = 12;
+// Grid-barrier words: generation at 0, error flag at kBarErr, arrival epoch
+// of workgroup b at kBarFlag + 32 b (one 128-byte line each).
+constexpr int kBarErr = 32;
+constexpr int kBarFlag = 64;
+constexpr long bar_words(int nblocks) { return (long)kBarFlag + 32L * (nblocks + 1); }
+
 // Scalars of one trace record.
 constexpr int kTraceScalars = 16;
 

@@ -29,6 +29,7 @@ __global__ void __launch_bounds__(512) dfom_kernel(DevProblem<T> P, DevParams pa
     s.tm.rank = blockIdx.x;
     s.tm.size = gridDim.x;
     s.tm.bar = W.bar;
+    s.tm.epoch = 0;
     share(P.n, blockIdx.x, gridDim.x, s.nlo, s.nhi);
     share(P.p, blockIdx.x, gridDim.x, s.plo, s.phi);
     const int pmax = (P.p + gridDim.x - 1) / gridDim.x + 1;
@@ -49,6 +50,7 @@ __global__ void __launch_bounds__(512) lanczos_kernel(DevProblem<T> P, LanczosWo
     s.tm.rank = blockIdx.x;
     s.tm.size = gridDim.x;
     s.tm.bar = L.bar;
+    s.tm.epoch = 0;
     share(P.n, blockIdx.x, gridDim.x, s.nlo, s.nhi);
     share(P.p, blockIdx.x, gridDim.x, s.plo, s.phi);
     const int pmax = (P.p + gridDim.x - 1) / gridDim.x + 1;

@@ -24,6 +24,16 @@ struct Lanczos {
     double* hl;      // LDS: k+2 reduced values
     double* red;
 
+    // The Krylov basis V is staged by every workgroup: device-scope accesses
+    // on a grid team.  w is private to its owner rows.
+    __device__ __forceinline__ void vput(double* p, double v) const {
+        if (tm.size > 1) xstore(p, v); else *p = v;
+    }
+    __device__ __forceinline__ double vget(const double* p) const { return tm.size > 1 ? xload(p) : *p; }
+    __device__ __forceinline__ double wget(const double* w, int i) const {
+        return (w == L.V) ? vget(w + i) : w[i];
+    }
+
     // h[j] = sum_i V[j][i] w[i] for j < m over the team; result in hl.
     __device__ bool dots(const double* w, int m) {
         const int n = P.n;
@@ -31,18 +41,18 @@ struct Lanczos {
         const int ncol = k + 2;
         for (int j = wid; j < m; j += nw) {
             double s = 0.0;
-            for (int i = nlo + lane; i < nhi; i += kWave) s += L.V[(long)j * n + i] * w[i];
+            for (int i = nlo + lane; i < nhi; i += kWave) s += vget(L.V + (long)j * n + i) * wget(w, i);
             s = wave_sum(s);
             if (lane == 0) {
                 if (tm.size == 1) hl[j] = s;
-                else L.part[(long)tm.rank * ncol + j] = s;
+                else xstore(L.part + (long)tm.rank * ncol + j, s);
             }
         }
         if (tm.size == 1) { __syncthreads(); return true; }
         if (tm.sync()) return false;
         for (int j = wid; j < m; j += nw) {
             double s = 0.0;
-            for (int b = lane; b < tm.size; b += kWave) s += L.part[(long)b * ncol + j];
+            for (int b = lane; b < tm.size; b += kWave) s += xload(L.part + (long)b * ncol + j);
             s = wave_sum(s);
             if (lane == 0) hl[j] = s;
         }
@@ -54,7 +64,7 @@ struct Lanczos {
 
     __device__ bool apply(const double* v, double* w) {
         const int n = P.n;
-        stage(v, n, xl);
+        if (tm.size > 1) stage_shared(v, n, xl); else stage(v, n, xl);
         if (!use_gtg) {
             gemv_rows<T, double>(P.Q, n, nlo, nhi, n, xl, w, nullptr);
             __syncthreads();
@@ -65,16 +75,16 @@ struct Lanczos {
         for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) vl[i - plo] = L.r[i];
         __syncthreads();
         if (tm.size == 1) {
-            gemvT_rows<T, double>(P.G, n, plo, phi, n, vl, w, nullptr);
+            gemvT_rows<T, double>(P.G, n, plo, phi, n, vl, w, nullptr, false);
             __syncthreads();
             return true;
         }
-        gemvT_rows<T, double>(P.G, n, plo, phi, n, vl, L.gtp + (long)tm.rank * n, nullptr);
+        gemvT_rows<T, double>(P.G, n, plo, phi, n, vl, L.gtp + (long)tm.rank * n, nullptr, true);
         if (tm.sync()) return false;
         const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
         for (int j = nlo + wid; j < nhi; j += nw) {
             double s = 0.0;
-            for (int b = lane; b < tm.size; b += kWave) s += L.gtp[(long)b * n + j];
+            for (int b = lane; b < tm.size; b += kWave) s += xload(L.gtp + (long)b * n + j);
             s = wave_sum(s);
             if (lane == 0) w[j] = s;
         }
@@ -101,12 +111,12 @@ struct Lanczos {
         double* b = L.ab + k;
         // v_1: deterministic start vector with no special structure
         for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x)
-            L.V[i] = 1.0 + 0.5 * sin(0.7 * i + 0.3) + 0.25 * cos(1.9 * i);
+            vput(L.V + i, 1.0 + 0.5 * sin(0.7 * i + 0.3) + 0.25 * cos(1.9 * i));
         __syncthreads();
         if (!dots(L.V, 1)) return;
         {
             const double s = 1.0 / sqrt(hl[0]);
-            for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x) L.V[i] *= s;
+            for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x) vput(L.V + i, vget(L.V + i) * s);
         }
         double alpha0 = 0.0;
         int m = 0;
@@ -121,7 +131,7 @@ struct Lanczos {
                 aj += hl[j];
                 for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x) {
                     double s = L.w[i];
-                    for (int q = 0; q <= j; ++q) s -= hl[q] * L.V[(long)q * n + i];
+                    for (int q = 0; q <= j; ++q) s -= hl[q] * vget(L.V + (long)q * n + i);
                     L.w[i] = s;
                 }
                 __syncthreads();
@@ -137,7 +147,7 @@ struct Lanczos {
             if (!(beta > 1e-13 * fabs(alpha0) + 1e-300)) break;   // invariant subspace
             const double inv = 1.0 / beta;
             for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x)
-                L.V[(long)(j + 1) * n + i] = L.w[i] * inv;
+                vput(L.V + (long)(j + 1) * n + i, L.w[i] * inv);
         }
         if (tm.rank == 0 && threadIdx.x == 0) {
             // extreme eigenvalues of the m x m tridiagonal (a, b[1..m-1]) by bisection
@@ -179,11 +189,11 @@ struct Lanczos {
             __syncthreads();
             return true;
         }
-        if (threadIdx.x == 0) L.part[(long)tm.rank * ncol + k + 1] = v[0];
+        if (threadIdx.x == 0) xstore(L.part + (long)tm.rank * ncol + k + 1, v[0]);
         if (tm.sync()) return false;
         if (wid == 0) {
             double t = 0.0;
-            for (int b = lane; b < tm.size; b += kWave) t += L.part[(long)b * ncol + k + 1];
+            for (int b = lane; b < tm.size; b += kWave) t += xload(L.part + (long)b * ncol + k + 1);
             t = wave_sum(t);
             if (lane == 0) hl[0] = t;
         }
