@@ -158,6 +158,40 @@ int duq_get_trace(duq_handle *h, double *out, int32_t max_records, int32_t *n_re
 int duq_get_constants(duq_handle *h, double *lam_min, double *lam_max,
                       double *G_norm2, double *Ld, double *L_in, double *sigma_in);
 
+/* ---- batches (no batching in the paper; the instances are independent) -- *
+ * DUQ_BATCH_UNEVEN: B independent QPs of different sizes, packed.  Instance
+ *   i has n[i] variables and p[i] rows; Q_i starts at element qoff[i] of Q
+ *   (n_i x n_i row-major), G_i at goff[i] of G (p_i x n_i), q_i / lb_i / ub_i
+ *   at voff[i] of q / lb / ub, g_i at coff[i] of g.
+ * DUQ_BATCH_SHARED: B QPs sharing Q (n x n), G (p x n), lb, ub; q is B x n
+ *   and g is B x p (row b belongs to instance b); voff/coff are unused.
+ * lam_min / lam_max / G_norm2: per-instance constants (B each) or NULL to
+ *   estimate them on the device (one value each for SHARED).               */
+enum { DUQ_BATCH_UNEVEN = 0, DUQ_BATCH_SHARED = 1 };
+typedef struct duq_batch {
+    int32_t kind;               /* DUQ_BATCH_UNEVEN | DUQ_BATCH_SHARED            */
+    int32_t B;                  /* number of instances, B >= 1                    */
+    int32_t dtype;              /* DUQ_F64 | DUQ_F32 storage of Q and G           */
+    int32_t memspace;           /* DUQ_HOST (copied) | DUQ_DEVICE (borrowed)      */
+    int32_t n_shared, p_shared; /* sizes for DUQ_BATCH_SHARED                     */
+    const int32_t *n, *p;       /* B sizes (UNEVEN)                               */
+    const int64_t *qoff, *goff, *voff, *coff;   /* element offsets (UNEVEN)      */
+    const void *Q, *G;
+    const double *q, *g, *lb, *ub;
+    const double *lam_min, *lam_max, *G_norm2;  /* optional constants (NULL)      */
+} duq_batch;
+
+/* Solve every instance of the batch in one persistent launch: workgroups take
+ * instances from a device work queue (largest first) and run Algorithm DFOM on
+ * each with the same options (engine is ignored; max_outer, eps and rho apply
+ * per instance; tracing is not available).  X_out (sum n_i, or B x n) and
+ * Lam_out (sum p_i, or B x p) are host buffers laid out like q and g; res has
+ * B entries (time_ms is the batch's device time).  Returns DUQ_OK when every
+ * instance passed its outer test, DUQ_EMAXITER / DUQ_ENUMERIC when one did
+ * not (see res[i].status), or an error code.                                */
+int duq_solve_batch(const duq_batch *batch, const duq_options *opts, void *stream,
+                    double *X_out, double *Lam_out, duq_result *res);
+
 /* Release every resource of the handle (NULL is allowed).                  */
 void duq_destroy(duq_handle *h);
 

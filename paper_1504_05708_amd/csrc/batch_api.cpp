@@ -1,0 +1,315 @@
+// Host side of duq_solve_batch: validation, packing, work order, slots,
+// one persistent launch, result transfer.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/duq.h"
+#include "internal.h"
+#include "launch.h"
+
+using namespace duq;
+
+namespace duq {
+int set_error(int code, const std::string& msg);
+int device_cus();
+}
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+#define BTRY(expr)                                                                                 \
+    do {                                                                                           \
+        hipError_t _e = (expr);                                                                    \
+        if (_e != hipSuccess)                                                                      \
+            return set_error(_e == hipErrorOutOfMemory ? DUQ_ENOMEM : DUQ_EDEVICE,                 \
+                             std::string(#expr) + ": " + hipGetErrorString(_e));                   \
+    } while (0)
+
+template <typename T>
+bool all_finite(const T* a, long long len) {
+    for (long long i = 0; i < len; ++i)
+        if (!std::isfinite((double)a[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* stream, double* X_out,
+                               double* Lam_out, duq_result* res) {
+    if (!b || !o) return set_error(DUQ_EINVAL, "null batch or options");
+    const int B = b->B;
+    if (B < 1) return set_error(DUQ_EINVAL, "B must be >= 1");
+    if (b->kind != DUQ_BATCH_UNEVEN && b->kind != DUQ_BATCH_SHARED) return set_error(DUQ_EINVAL, "bad kind");
+    if (b->dtype != DUQ_F64 && b->dtype != DUQ_F32) return set_error(DUQ_EINVAL, "dtype must be F64 or F32");
+    if (b->memspace != DUQ_HOST && b->memspace != DUQ_DEVICE) return set_error(DUQ_EINVAL, "bad memspace");
+    if (!(o->eps_out > 0.0) || !(o->eps_in > 0.0) || !(o->rho >= 0.0) || o->max_outer < 1 || o->max_inner < 0)
+        return set_error(DUQ_EINVAL, "bad options");
+    if (o->method != DUQ_DGM && o->method != DUQ_DFGM) return set_error(DUQ_EINVAL, "bad method");
+    if (o->output != DUQ_LAST && o->output != DUQ_AVG) return set_error(DUQ_EINVAL, "bad output");
+    if (o->inner_variant < 0 || o->inner_variant > 3) return set_error(DUQ_EINVAL, "bad inner_variant");
+    if (o->accumulate != DUQ_ACC_F64) return set_error(DUQ_EINVAL, "batches accumulate in FP64");
+    if (!b->Q || !b->q || !b->lb || !b->ub) return set_error(DUQ_EINVAL, "null data pointer");
+    const bool shared = b->kind == DUQ_BATCH_SHARED;
+    const size_t es = b->dtype == DUQ_F64 ? 8 : 4;
+    hipStream_t s = (hipStream_t)stream;
+
+    // sizes and offsets (host metadata)
+    std::vector<int> ns(B), ps(B);
+    std::vector<long long> qo(B), go(B), vo(B), co(B);
+    long long qtot = 0, gtot = 0, vtot = 0, ctot = 0;
+    int n_max = 0, p_max = 0;
+    if (shared) {
+        if (b->n_shared < 1 || b->p_shared < 0) return set_error(DUQ_EINVAL, "bad shared sizes");
+        if (b->p_shared > 0 && (!b->G || !b->g)) return set_error(DUQ_EINVAL, "null G or g");
+        n_max = b->n_shared;
+        p_max = b->p_shared;
+        for (int i = 0; i < B; ++i) {
+            ns[i] = n_max;
+            ps[i] = p_max;
+            vo[i] = (long long)i * n_max;
+            co[i] = (long long)i * p_max;
+        }
+        qtot = (long long)n_max * n_max;
+        gtot = (long long)p_max * n_max;
+        vtot = (long long)B * n_max;
+        ctot = (long long)B * p_max;
+    } else {
+        if (!b->n || !b->p || !b->qoff || !b->goff || !b->voff || !b->coff)
+            return set_error(DUQ_EINVAL, "null size/offset arrays");
+        for (int i = 0; i < B; ++i) {
+            ns[i] = b->n[i];
+            ps[i] = b->p[i];
+            qo[i] = b->qoff[i];
+            go[i] = b->goff[i];
+            vo[i] = b->voff[i];
+            co[i] = b->coff[i];
+            if (ns[i] < 1 || ps[i] < 0 || qo[i] < 0 || go[i] < 0 || vo[i] < 0 || co[i] < 0)
+                return set_error(DUQ_EINVAL, "bad size or offset of instance " + std::to_string(i));
+            n_max = std::max(n_max, ns[i]);
+            p_max = std::max(p_max, ps[i]);
+            qtot = std::max(qtot, qo[i] + (long long)ns[i] * ns[i]);
+            gtot = std::max(gtot, go[i] + (long long)ps[i] * ns[i]);
+            vtot = std::max(vtot, vo[i] + ns[i]);
+            ctot = std::max(ctot, co[i] + ps[i]);
+        }
+        if (gtot > 0 && (!b->G || !b->g)) return set_error(DUQ_EINVAL, "null G or g");
+    }
+    const long long lbn = shared ? n_max : vtot;
+
+    // device data: copy (HOST) or borrow (DEVICE)
+    DevBuf data;
+    const void *dQ = b->Q, *dG = b->G;
+    const double *dq = b->q, *dg = b->g, *dlb = b->lb, *dub = b->ub;
+    if (b->memspace == DUQ_HOST) {
+        bool ok = (b->dtype == DUQ_F64 ? all_finite((const double*)b->Q, qtot) : all_finite((const float*)b->Q, qtot));
+        if (gtot > 0)
+            ok = ok && (b->dtype == DUQ_F64 ? all_finite((const double*)b->G, gtot)
+                                            : all_finite((const float*)b->G, gtot));
+        ok = ok && all_finite(b->q, vtot) && (ctot == 0 || all_finite(b->g, ctot));
+        if (!ok) return set_error(DUQ_EINVAL, "non-finite batch data");
+        for (long long j = 0; j < lbn; ++j)
+            if (!std::isfinite(b->lb[j]) || !std::isfinite(b->ub[j]) || b->lb[j] > b->ub[j])
+                return set_error(DUQ_EINVAL, "box must be finite with lb <= ub");
+        const size_t bytes = qtot * es + std::max<long long>(gtot, 1) * es + 8 * (vtot + std::max<long long>(ctot, 1) + 2 * lbn) + 6 * 256;
+        BTRY(hipMalloc(&data.p, bytes));
+        char* c = (char*)data.p;
+        auto take = [&](size_t n) { char* r = c; c += ((n + 255) / 256) * 256; return r; };
+        char* Qd = take(qtot * es);
+        char* Gd = take(std::max<long long>(gtot, 1) * es);
+        double* qd = (double*)take(8 * vtot);
+        double* gd = (double*)take(8 * std::max<long long>(ctot, 1));
+        double* lbd = (double*)take(8 * lbn);
+        double* ubd = (double*)take(8 * lbn);
+        BTRY(hipMemcpyAsync(Qd, b->Q, qtot * es, hipMemcpyHostToDevice, s));
+        if (gtot > 0) BTRY(hipMemcpyAsync(Gd, b->G, gtot * es, hipMemcpyHostToDevice, s));
+        BTRY(hipMemcpyAsync(qd, b->q, 8 * vtot, hipMemcpyHostToDevice, s));
+        if (ctot > 0) BTRY(hipMemcpyAsync(gd, b->g, 8 * ctot, hipMemcpyHostToDevice, s));
+        BTRY(hipMemcpyAsync(lbd, b->lb, 8 * lbn, hipMemcpyHostToDevice, s));
+        BTRY(hipMemcpyAsync(ubd, b->ub, 8 * lbn, hipMemcpyHostToDevice, s));
+        dQ = Qd; dG = Gd; dq = qd; dg = gd; dlb = lbd; dub = ubd;
+    }
+
+    // constants: per instance from the caller, or one estimate for a shared batch
+    const bool have_c = b->lam_min && b->lam_max && b->G_norm2;
+    const int nc = shared ? 1 : B;
+    std::vector<double> cmin(nc), cmax(nc), cg2(nc);
+    bool dev_consts = have_c;
+    if (have_c) {
+        for (int i = 0; i < nc; ++i) {
+            cmin[i] = b->lam_min[i];
+            cmax[i] = b->lam_max[i];
+            cg2[i] = b->G_norm2[i];
+        }
+    } else if (shared) {
+        duq_problem pr{n_max, p_max, b->dtype, DUQ_DEVICE, dQ, p_max ? dG : nullptr, dq, p_max ? dg : nullptr, dlb, dub};
+        duq_options oo = *o;
+        oo.lam_min = oo.lam_max = oo.G_norm2 = 0.0;
+        oo.trace_outer = 0;
+        duq_handle* h = nullptr;
+        int rc = duq_setup(&pr, &oo, stream, &h);
+        if (rc) return rc;
+        duq_get_constants(h, &cmin[0], &cmax[0], &cg2[0], nullptr, nullptr, nullptr);
+        duq_destroy(h);
+        dev_consts = true;
+    }
+
+    // processing order: largest work first
+    std::vector<int> order(B);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        const long long wa = (long long)ns[a] * ns[a] + (long long)ps[a] * ns[a];
+        const long long wc = (long long)ns[c] * ns[c] + (long long)ps[c] * ns[c];
+        return wa > wc;
+    });
+
+    const int k_req = o->lanczos_steps > 0 ? o->lanczos_steps : 96;
+    const int k = std::min(k_req, n_max);
+    const size_t shmem = batch_lds_bytes(n_max, p_max, k);
+    int bpc = 0;
+    BTRY(batch_occupancy(b->dtype, shmem, &bpc));
+    if (bpc < 1) return set_error(DUQ_EINVAL, "batch instance too large for one workgroup's LDS");
+    const int nblocks = std::max(1, std::min(B, device_cus() * bpc));
+    const long long slot = batch_slot_bytes_host(n_max, p_max, k);
+
+    // device workspace
+    DevBuf ws;
+    size_t off = 0;
+    auto plan = [&](size_t n) { size_t r = off; off += ((n + 255) / 256) * 256; return r; };
+    const size_t o_slots = plan((size_t)slot * nblocks);
+    const size_t o_X = plan(8 * vtot);
+    const size_t o_L = plan(8 * std::max<long long>(ctot, 1));
+    const size_t o_res = plan(sizeof(BatchResultDev) * B);
+    const size_t o_meta = plan((sizeof(int) * 3 + sizeof(long long) * 4) * B);
+    const size_t o_c = plan(8 * 3 * nc);
+    const size_t o_q = plan(256);
+    BTRY(hipMalloc(&ws.p, off));
+    char* w = (char*)ws.p;
+    int* d_order = (int*)(w + o_meta);
+    int* d_n = d_order + B;
+    int* d_p = d_n + B;
+    long long* d_off = (long long*)(w + o_meta + ((sizeof(int) * 3 * B + 7) / 8) * 8);
+    std::vector<char> meta(o_c - o_meta, 0);
+    std::memcpy(meta.data(), order.data(), sizeof(int) * B);
+    std::memcpy(meta.data() + sizeof(int) * B, ns.data(), sizeof(int) * B);
+    std::memcpy(meta.data() + 2 * sizeof(int) * B, ps.data(), sizeof(int) * B);
+    char* mo = meta.data() + ((sizeof(int) * 3 * B + 7) / 8) * 8;
+    std::memcpy(mo, qo.data(), 8 * B);
+    std::memcpy(mo + 8 * B, go.data(), 8 * B);
+    std::memcpy(mo + 16 * B, vo.data(), 8 * B);
+    std::memcpy(mo + 24 * B, co.data(), 8 * B);
+    BTRY(hipMemcpyAsync(w + o_meta, meta.data(), meta.size(), hipMemcpyHostToDevice, s));
+    double* d_c = (double*)(w + o_c);
+    if (dev_consts) {
+        std::vector<double> cc(3 * nc);
+        std::copy(cmin.begin(), cmin.end(), cc.begin());
+        std::copy(cmax.begin(), cmax.end(), cc.begin() + nc);
+        std::copy(cg2.begin(), cg2.end(), cc.begin() + 2 * nc);
+        BTRY(hipMemcpyAsync(d_c, cc.data(), 8 * 3 * nc, hipMemcpyHostToDevice, s));
+    }
+    BTRY(hipMemsetAsync(w + o_q, 0, 256, s));
+
+    BatchLaunch L{};
+    L.B = B;
+    L.shared = shared ? 1 : 0;
+    L.order = d_order;
+    L.n = d_n;
+    L.p = d_p;
+    L.qoff = d_off;
+    L.goff = d_off + B;
+    L.voff = d_off + 2 * B;
+    L.coff = d_off + 3 * B;
+    L.n_shared = n_max;
+    L.p_shared = p_max;
+    L.Q = dQ;
+    L.G = dG;
+    L.q = dq;
+    L.g = dg;
+    L.lb = dlb;
+    L.ub = dub;
+    L.lam_min = dev_consts ? d_c : nullptr;
+    L.lam_max = dev_consts ? d_c + nc : nullptr;
+    L.g2 = dev_consts ? d_c + 2 * nc : nullptr;
+    L.X = (double*)(w + o_X);
+    L.Lam = (double*)(w + o_L);
+    L.res = w + o_res;
+    DevParams par{};
+    par.method = o->method;
+    par.output = o->output;
+    par.inner_rule = o->inner_rule;
+    par.inner_variant = o->inner_variant;
+    par.max_outer = o->max_outer;
+    par.eps_out = o->eps_out;
+    par.eps_in = o->eps_in;
+    par.rho = o->rho;
+    L.base = par;
+    L.max_inner = o->max_inner;
+    L.lanczos_k = k_req;
+    L.lanczos_alloc = k;
+    L.safety = o->safety;
+    L.slots = w + o_slots;
+    L.slot_bytes = slot;
+    L.n_max = n_max;
+    L.p_max = p_max;
+    L.queue = (unsigned*)(w + o_q);
+
+    hipEvent_t e0, e1;
+    BTRY(hipEventCreate(&e0));
+    BTRY(hipEventCreate(&e1));
+    BTRY(hipEventRecord(e0, s));
+    hipError_t le = launch_batch(b->dtype, nblocks, shmem, s, L);
+    BTRY(hipEventRecord(e1, s));
+    std::vector<BatchResultDev> rd(B);
+    if (le == hipSuccess) {
+        BTRY(hipMemcpyAsync(rd.data(), w + o_res, sizeof(BatchResultDev) * B, hipMemcpyDeviceToHost, s));
+        if (X_out) BTRY(hipMemcpyAsync(X_out, w + o_X, 8 * vtot, hipMemcpyDeviceToHost, s));
+        if (Lam_out && ctot > 0) BTRY(hipMemcpyAsync(Lam_out, w + o_L, 8 * ctot, hipMemcpyDeviceToHost, s));
+    }
+    hipError_t se = hipStreamSynchronize(s);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    BTRY(le);
+    BTRY(se);
+    int code = DUQ_OK;
+    for (int i = 0; i < B; ++i) {
+        const BatchResultDev& r = rd[i];
+        int st = r.status == 0 ? DUQ_OK
+                 : r.status == 2 ? DUQ_ENUMERIC
+                 : r.status == 4 ? DUQ_EINVAL
+                                 : DUQ_EMAXITER;
+        if (st != DUQ_OK && code == DUQ_OK) code = st;
+        if (res) {
+            duq_result& q = res[i];
+            std::memset(&q, 0, sizeof(q));
+            q.status = st;
+            q.outer_iters = r.outer;
+            q.inner_iters = r.inner;
+            q.gt_rows = r.gt_rows;
+            q.f = r.F;
+            q.lb_dual = r.LB;
+            q.gap = r.F - r.LB;
+            q.feas = r.feas;
+            q.time_ms = ms;
+            q.f64_outer_iters = r.outer;
+            q.engine = DUQ_ENGINE_BLOCK;
+            q.lam_min = r.lam_min;
+            q.lam_max = r.lam_max;
+            q.G_norm2 = r.G2;
+        }
+    }
+    if (code != DUQ_OK) set_error(code, "at least one instance did not pass its outer test");
+    return code;
+}

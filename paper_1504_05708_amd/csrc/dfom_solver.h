@@ -63,6 +63,18 @@ __device__ __forceinline__ void gemv_rows(const T* A, long ld, int rlo, int rhi,
                 for (int e = 0; e < V; ++e) s += (Acc)a[e] * (Acc)xv[e];
             }
             j0 = nv * V;
+        } else {
+            // rows not 16-byte aligned: element loads, but each lane accumulates
+            // the same elements in the same order as the vector path, so the
+            // result does not depend on where the matrix sits in memory
+            const int nv = ncols / V;
+            for (int v = lane; v < nv; v += kWave) {
+                const T* pv = row + (long)v * V;
+                const double* xv = xl + (long)v * V;
+#pragma unroll
+                for (int e = 0; e < V; ++e) s += (Acc)pv[e] * (Acc)xv[e];
+            }
+            j0 = nv * V;
         }
         for (int j = j0 + lane; j < ncols; j += kWave) s += (Acc)row[j] * (Acc)xl[j];
         s = wave_sum(s);
@@ -462,7 +474,14 @@ struct Dfom {
             k0 = st->k;
             inner_total = st->inner;
             gt_rows = 0;
+            // products of the warm start in this launch's accumulation precision
+            stage_x(X(cur));
+            gemv_rows<T, Acc, 16>(P.Q, n, nlo, nhi, n, xl, QX(cur), nullptr);
+            if (par.rho > 0.0) gemv_rows<T, Acc>(P.G, n, plo, phi, n, xl, GX(cur), nullptr);
+            __syncthreads();
         }
+        double best = par.resume ? st->best_metric : INFINITY;
+        int stall = par.resume ? st->stall : 0;
         int status = 1;  // max outer unless the test passes
         double Fc = 0.0, feasc = 0.0, lnc = 0.0;
         int ans_cur = cur;   // buffer of the answer (LAST)
@@ -550,7 +569,7 @@ struct Dfom {
             ans_cur = cur;
             ans_avg = par.output == 1;
             double ex[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // extra_t, extra_gap, F2, feas2, passed2
-            if (ok1 && par.output == 0 && par.method == 1) {
+            if (ok1 && par.output == 0 && par.method == 1 && !par.phase1) {
                 // Last iterate of DFGM: ubar(lambda^k), eq. last_primal.
                 for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x) {
                     W.usave[i] = get(X(cur) + i);
@@ -616,8 +635,14 @@ struct Dfom {
             }
             theta = thn;
             if (ok) { status = 0; break; }
-            // precision switch support: stop this launch once the looser
-            // tolerance of a first phase is met
+            if (par.phase1 && par.stall_iters > 0) {
+                // progress measure of the outer test; the phase ends when it has not
+                // improved by 1% for stall_iters iterations
+                const double sc = fmax(1.0, fabs(F));
+                const double m = fmax(fmax(feas / fmax(1.0, gnorm), (F - LB) / sc), lnorm * feas / sc);
+                if (m < 0.99 * best) { best = m; stall = 0; }
+                else if (++stall >= par.stall_iters) { status = 3; break; }
+            }
         }
         // outputs
         if (ans_avg) write_outputs(W.us, 1.0 / S, false);
@@ -635,6 +660,8 @@ struct Dfom {
             st->feas = feasc;
             st->lnorm = lnc;
             st->gnorm = gnorm;
+            st->best_metric = best;
+            st->stall = stall;
         }
         // rows of G touched, summed over the team (for reporting)
         if (threadIdx.x == 0 && gt_rows > 0)

@@ -83,6 +83,15 @@ struct Carve {
 
 }  // namespace
 
+namespace duq {
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+int device_cus() {
+    DeviceInfo di;
+    if (device_info(&di) != DUQ_OK) return 1;
+    return std::max(1, di.cus);
+}
+}  // namespace duq
+
 struct duq_handle {
     int n = 0, p = 0, dtype = 0;
     hipStream_t stream = nullptr;
@@ -536,11 +545,35 @@ extern "C" int duq_solve(duq_handle* h, const double* x0, const double* lam0, do
     par.sigma = h->sigma;
     par.beta_in = h->beta_in;
     GenericProblem gp{n, p, h->dQ, h->dG, h->dq, h->dg, h->dlb, h->dub};
-    HIP_TRY(hipEventRecord(h->ev0, h->stream));
-    HIP_TRY(launch_dfom(h->dtype, h->dtype == DUQ_F32 ? o.accumulate : 0, h->cfg, gp, par, W));
-    HIP_TRY(hipEventRecord(h->ev1, h->stream));
     DevState st;
     unsigned bar_err = 0;
+    int k_phase1 = 0;
+    const bool two_phase = h->dtype == DUQ_F32 && o.accumulate == DUQ_ACC_F32;
+    HIP_TRY(hipEventRecord(h->ev0, h->stream));
+    if (two_phase) {
+        // a8: FP32-accumulated products until the outer test passes at
+        // switch_factor * eps_out or stalls, then FP64 accumulation from the
+        // same device state (a warm start) to eps_out.
+        DevParams p1 = par;
+        p1.phase1 = 1;
+        p1.stall_iters = o.switch_stall;
+        p1.eps_out = o.eps_out * std::max(1.0, o.switch_factor);
+        HIP_TRY(launch_dfom(h->dtype, DUQ_ACC_F32, h->cfg, gp, p1, W));
+        HIP_TRY(hipMemcpyAsync(&st, h->W.st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(&bar_err, h->W.bar + kBarErr, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        if (bar_err) return fail(DUQ_EDEVICE, "grid barrier timeout (a workgroup did not arrive)");
+        k_phase1 = st.k;
+        if (st.status != 2 && st.k < o.max_outer) {
+            DevParams p2 = par;
+            p2.resume = 1;
+            HIP_TRY(hipMemsetAsync(h->W.bar, 0, bar_words(h->cfg.nblocks) * sizeof(unsigned), h->stream));
+            HIP_TRY(launch_dfom(h->dtype, DUQ_ACC_F64, h->cfg, gp, p2, W));
+        }
+    } else {
+        HIP_TRY(launch_dfom(h->dtype, 0, h->cfg, gp, par, W));
+    }
+    HIP_TRY(hipEventRecord(h->ev1, h->stream));
     HIP_TRY(hipMemcpyAsync(&st, h->W.st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipMemcpyAsync(&bar_err, h->W.bar + kBarErr, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
     if (x_out) HIP_TRY(hipMemcpyAsync(x_out, h->W.xout, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -551,7 +584,7 @@ extern "C" int duq_solve(duq_handle* h, const double* x0, const double* lam0, do
     HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
     if (bar_err) return fail(DUQ_EDEVICE, "grid barrier timeout (a workgroup did not arrive)");
     h->last_records = st.n_trace;
-    int code = st.status == 0 ? DUQ_OK : (st.status == 1 ? DUQ_EMAXITER : DUQ_ENUMERIC);
+    int code = st.status == 0 ? DUQ_OK : (st.status == 2 ? DUQ_ENUMERIC : DUQ_EMAXITER);
     if (res) {
         std::memset(res, 0, sizeof(*res));
         res->status = code;
@@ -563,7 +596,7 @@ extern "C" int duq_solve(duq_handle* h, const double* x0, const double* lam0, do
         res->gap = st.F - st.LB;
         res->feas = st.feas;
         res->time_ms = ms;
-        res->f64_outer_iters = (h->dtype == DUQ_F32 && o.accumulate == DUQ_ACC_F32) ? 0 : st.k;
+        res->f64_outer_iters = two_phase ? st.k - k_phase1 : st.k;
         res->engine = h->engine;
         res->lam_min = h->lam_min;
         res->lam_max = h->lam_max;

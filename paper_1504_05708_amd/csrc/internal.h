@@ -41,7 +41,9 @@ struct DevParams {
     int has_x0;
     int has_lam0;
     int resume;        // continue from the state left by a previous launch
-    int pad;
+    int phase1;        // first precision phase: no last-iterate solve, stall exit
+    int stall_iters;   // phase 1 ends after this many iterations without progress
+    int pad2;
     double eps_out;    // outer tolerance used by this launch
     double eps_in;
     double rho;
@@ -96,6 +98,16 @@ struct DevWork {
     const double* lam0;
     DevState* st;
     unsigned* bar;     // [0] arrival count, [1] generation, [2] error flag
+};
+
+// Per-instance result of a batched solve.
+struct BatchResultDev {
+    int status;          // 0 ok, 1 max outer, 2 numeric, 4 invalid constants
+    int outer;
+    long long inner;
+    long long gt_rows;
+    double F, LB, feas;
+    double lam_min, lam_max, G2;
 };
 
 // Workspace of the Lanczos constant estimate.

@@ -2,6 +2,7 @@
 // Lanczos constant estimate.  Built for gfx950 only.
 #include <hip/hip_runtime.h>
 
+#include "batch.h"
 #include "dfom_solver.h"
 #include "lanczos.h"
 #include "launch.h"
@@ -59,6 +60,26 @@ __global__ void __launch_bounds__(512) lanczos_kernel(DevProblem<T> P, LanczosWo
     s.hl = lds + P.n + pmax;
     s.red = s.hl + (k + 2);
     s.run();
+}
+
+template <typename T, typename Acc>
+__global__ void __launch_bounds__(256) dfom_batch_kernel(BatchArgs<T> a) {
+    extern __shared__ __align__(16) double lds[];
+    batch_solve<T, Acc>(a, lds);
+}
+
+size_t batch_lds_bytes(int n_max, int p_max, int k) {
+    return ((size_t)n_max + p_max + 1 + (size_t)(k + 2) + (size_t)kMaxWaves * kNP + 16) * sizeof(double);
+}
+
+long long batch_slot_bytes_host(int n_max, int p_max, int k) { return batch_slot_bytes(n_max, p_max, k); }
+
+hipError_t batch_occupancy(int dtype, size_t shmem, int* blocks_per_cu) {
+    const void* f = dtype == 0 ? reinterpret_cast<const void*>(&dfom_batch_kernel<double, double>)
+                               : reinterpret_cast<const void*>(&dfom_batch_kernel<float, double>);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, 256, shmem);
 }
 
 // Count of non-finite entries of a device array (validation of borrowed data).
@@ -137,6 +158,20 @@ hipError_t launch_count_nonfinite(int dtype, const void* a, long len, unsigned* 
     else
         hipLaunchKernelGGL(count_nonfinite_kernel<float>, dim3(nb), dim3(256), 0, s, (const float*)a, len, out);
     return hipGetLastError();
+}
+
+hipError_t launch_batch(int dtype, int nblocks, size_t shmem, hipStream_t stream, const BatchLaunch& b) {
+    LaunchCfg cfg{nblocks, 256, shmem, false, stream};
+    if (dtype == 0) {
+        BatchArgs<double> a;
+        fill_batch_args(a, b);
+        void* args[] = {&a};
+        return launch_any(&dfom_batch_kernel<double, double>, cfg, args);
+    }
+    BatchArgs<float> a;
+    fill_batch_args(a, b);
+    void* args[] = {&a};
+    return launch_any(&dfom_batch_kernel<float, double>, cfg, args);
 }
 
 }  // namespace duq

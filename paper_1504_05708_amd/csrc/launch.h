@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace duq {
@@ -27,6 +29,49 @@ struct GenericProblem {
 };
 
 struct LanczosWork;
+
+// Type-erased batch description filled by the host runtime.
+struct BatchLaunch {
+    int B, shared;
+    const int* order;
+    const int* n;
+    const int* p;
+    const long long *qoff, *goff, *voff, *coff;
+    int n_shared, p_shared;
+    const void* Q;
+    const void* G;
+    const double *q, *g, *lb, *ub;
+    const double *lam_min, *lam_max, *g2;
+    double* X;
+    double* Lam;
+    void* res;
+    DevParams base;
+    int max_inner, lanczos_k, lanczos_alloc;
+    double safety;
+    char* slots;
+    long long slot_bytes;
+    int n_max, p_max;
+    unsigned* queue;
+};
+
+template <typename A>
+inline void fill_batch_args(A& a, const BatchLaunch& b) {
+    typedef typename std::remove_const<typename std::remove_pointer<decltype(a.Q)>::type>::type T;
+    a.B = b.B; a.shared = b.shared; a.order = b.order; a.n = b.n; a.p = b.p;
+    a.qoff = b.qoff; a.goff = b.goff; a.voff = b.voff; a.coff = b.coff;
+    a.n_shared = b.n_shared; a.p_shared = b.p_shared;
+    a.Q = (const T*)b.Q; a.G = (const T*)b.G;
+    a.q = b.q; a.g = b.g; a.lb = b.lb; a.ub = b.ub;
+    a.lam_min = b.lam_min; a.lam_max = b.lam_max; a.g2 = b.g2;
+    a.X = b.X; a.Lam = b.Lam; a.res = (decltype(a.res))b.res;
+    a.base = b.base; a.max_inner = b.max_inner; a.lanczos_k = b.lanczos_k; a.lanczos_alloc = b.lanczos_alloc; a.safety = b.safety;
+    a.slots = b.slots; a.slot_bytes = b.slot_bytes; a.n_max = b.n_max; a.p_max = b.p_max; a.queue = b.queue;
+}
+
+size_t batch_lds_bytes(int n_max, int p_max, int k);
+long long batch_slot_bytes_host(int n_max, int p_max, int k);
+hipError_t batch_occupancy(int dtype, size_t shmem, int* blocks_per_cu);
+hipError_t launch_batch(int dtype, int nblocks, size_t shmem, hipStream_t stream, const BatchLaunch& b);
 
 size_t dfom_lds_bytes(int n, int p, int nblocks);
 size_t lanczos_lds_bytes(int n, int p, int nblocks, int k);

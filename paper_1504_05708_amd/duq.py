@@ -28,8 +28,10 @@ ACC_F64, ACC_F32 = 0, 1
 ENGINE_AUTO, ENGINE_BLOCK, ENGINE_GRID = 0, 1, 2
 TRACE_SCALARS = 16
 
+BATCH_UNEVEN, BATCH_SHARED = 0, 1
+
 EXPORTS = ["duq_default_options", "duq_setup", "duq_solve", "duq_get_trace", "duq_get_constants",
-           "duq_destroy", "duq_last_error", "duq_strerror"]
+           "duq_destroy", "duq_last_error", "duq_strerror", "duq_solve_batch"]
 
 
 class DuqProblem(Structure):
@@ -57,6 +59,15 @@ class DuqResult(Structure):
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class DuqBatch(Structure):
+    _fields_ = [("kind", c_int32), ("B", c_int32), ("dtype", c_int32), ("memspace", c_int32),
+                ("n_shared", c_int32), ("p_shared", c_int32),
+                ("n", c_void_p), ("p", c_void_p), ("qoff", c_void_p), ("goff", c_void_p),
+                ("voff", c_void_p), ("coff", c_void_p), ("Q", c_void_p), ("G", c_void_p),
+                ("q", c_void_p), ("g", c_void_p), ("lb", c_void_p), ("ub", c_void_p),
+                ("lam_min", c_void_p), ("lam_max", c_void_p), ("G_norm2", c_void_p)]
 
 
 class DuqError(RuntimeError):
@@ -92,6 +103,9 @@ def lib() -> ctypes.CDLL:
     L.duq_last_error.restype = c_char_p
     L.duq_strerror.argtypes = [c_int32]
     L.duq_strerror.restype = c_char_p
+    L.duq_solve_batch.argtypes = [POINTER(DuqBatch), POINTER(DuqOptions), c_void_p, c_void_p, c_void_p,
+                                  POINTER(DuqResult)]
+    L.duq_solve_batch.restype = c_int32
     _lib = L
     return L
 
@@ -210,3 +224,54 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def solve_batch_uneven(batch, constants=None, check=True, **opts):
+    """duq_solve_batch on a packed gen.UnevenBatch (host arrays).
+
+    constants: optional (lam_min, lam_max, G_norm2) arrays of length B.
+    Returns (X, Lam, results) with X, Lam packed like q and g."""
+    B = batch.B
+    n = np.ascontiguousarray(batch.n, dtype=np.int32)
+    p = np.ascontiguousarray(batch.p, dtype=np.int32)
+    offs = [np.ascontiguousarray(v, dtype=np.int64) for v in (batch.qoff, batch.goff, batch.voff, batch.coff)]
+    Q = np.ascontiguousarray(batch.Q)
+    G = np.ascontiguousarray(batch.G, dtype=Q.dtype)
+    dt = {np.dtype(np.float64): F64, np.dtype(np.float32): F32}[Q.dtype]
+    vecs = [np.ascontiguousarray(v, dtype=np.float64) for v in (batch.q, batch.g, batch.lb, batch.ub)]
+    cs = [None, None, None] if constants is None else [np.ascontiguousarray(c, dtype=np.float64)
+                                                       for c in constants]
+    b = DuqBatch(BATCH_UNEVEN, B, dt, HOST, 0, 0, _ptr(n), _ptr(p), *[_ptr(o) for o in offs],
+                 _ptr(Q), _ptr(G), *[_ptr(v) for v in vecs], *[_ptr(c) for c in cs])
+    return _run_batch(b, B, int(batch.q.shape[0]), int(batch.g.shape[0]), check, opts)
+
+
+def solve_batch_shared(Q, G, lb, ub, q, g, constants=None, check=True, **opts):
+    """duq_solve_batch on B instances sharing Q, G, lb, ub; q is B x n, g is B x p.
+
+    constants: optional (lam_min, lam_max, G_norm2) scalars."""
+    Q = np.ascontiguousarray(Q)
+    dt = {np.dtype(np.float64): F64, np.dtype(np.float32): F32}[Q.dtype]
+    G = np.ascontiguousarray(G, dtype=Q.dtype)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    lb = np.ascontiguousarray(lb, dtype=np.float64)
+    ub = np.ascontiguousarray(ub, dtype=np.float64)
+    B, n = q.shape
+    p = g.shape[1]
+    cs = [None, None, None] if constants is None else [np.array([c], dtype=np.float64) for c in constants]
+    b = DuqBatch(BATCH_SHARED, B, dt, HOST, n, p, None, None, None, None, None, None,
+                 _ptr(Q), _ptr(G), _ptr(q), _ptr(g), _ptr(lb), _ptr(ub), *[_ptr(c) for c in cs])
+    X, Lam, res = _run_batch(b, B, B * n, B * p, check, opts)
+    return X.reshape(B, n), Lam.reshape(B, p), res
+
+
+def _run_batch(b, B, nx, nl, check, opts):
+    o = default_options(**opts)
+    X = np.empty(max(nx, 1))
+    Lam = np.empty(max(nl, 1))
+    res = (DuqResult * B)()
+    rc = lib().duq_solve_batch(ctypes.byref(b), ctypes.byref(o), c_void_p(None), _ptr(X), _ptr(Lam), res)
+    if check and rc not in (DUQ_OK, DUQ_EMAXITER):
+        raise DuqError(rc, last_error())
+    return X[:nx], Lam[:nl], [r.as_dict() for r in res]

@@ -49,7 +49,7 @@ def test_struct_layout_matches_header(tmp_path):
     if cc is None:
         pytest.skip("no host C compiler")
     structs = {"duq_problem": duq.DuqProblem, "duq_options": duq.DuqOptions,
-               "duq_result": duq.DuqResult}
+               "duq_result": duq.DuqResult, "duq_batch": duq.DuqBatch}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "duq.h"', 'int main(void){']
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')

@@ -1,0 +1,104 @@
+"""GPU parity of the batched forms (duq_solve_batch) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import dfom
+from oracle.ipm import ipm_qp
+from paper_1504_05708_amd import duq, gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    duq.lib()
+
+
+def exact_constants(qp):
+    c = dfom.problem_constants(qp.Q, qp.G, qp.lb, qp.ub, 0.0, 1e-6)
+    return c.lam_min, c.lam_max, c.G_norm2
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_uneven_batch_matches_oracle_per_instance(dtype):
+    print(f"[case] uneven batch parity {np.dtype(dtype).name}", flush=True)
+    ub = gen.uneven_batch(B=24, seed=31, n_lo=20, n_hi=160, dtype=dtype)
+    consts = [exact_constants(ub.instance(i)) for i in range(ub.B)]
+    C = [np.array([c[j] for c in consts]) for j in range(3)]
+    X, Lam, res = duq.solve_batch_uneven(ub, constants=C, method=duq.DFGM, eps_out=1e-4, eps_in=1e-8,
+                                         max_outer=20000)
+    for i in range(ub.B):
+        qp = ub.instance(i)
+        lmin, lmax, g2 = consts[i]
+        ref = dfom.dfom_solve(qp, dfom.Options(method=dfom.DFGM, eps_out=1e-4, eps_in=1e-8, max_outer=20000,
+                                               lam_min=lmin, lam_max=lmax, G_norm2=g2))
+        r = res[i]
+        assert r["status"] == duq.DUQ_OK, (i, r)
+        assert r["outer_iters"] == ref.outer_iters, (i, r["outer_iters"], ref.outer_iters)
+        assert r["inner_iters"] == ref.inner_iters, i
+        x = X[ub.voff[i]:ub.voff[i] + qp.n]
+        lam = Lam[ub.coff[i]:ub.coff[i] + qp.p]
+        np.testing.assert_allclose(x, ref.x, rtol=0, atol=1e-7)
+        np.testing.assert_allclose(lam, ref.lam, rtol=0, atol=1e-7 * max(1, np.abs(ref.lam).max()))
+
+
+def test_uneven_batch_estimated_constants_accuracy():
+    print("[case] uneven batch with in-kernel Lanczos", flush=True)
+    ub = gen.uneven_batch(B=16, seed=32, n_lo=20, n_hi=300, dtype=np.float32)
+    X, Lam, res = duq.solve_batch_uneven(ub, method=duq.DFGM, eps_out=1e-4, eps_in=1e-8, max_outer=50000)
+    for i in range(ub.B):
+        qp = ub.instance(i)
+        _, fstar, _ = ipm_qp(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub)
+        r = res[i]
+        assert r["status"] == duq.DUQ_OK
+        assert abs(r["f"] - fstar) / max(1.0, abs(fstar)) <= 1e-4
+        assert r["feas"] / max(1.0, np.linalg.norm(qp.g)) <= 1e-4
+        ev = np.linalg.eigvalsh(qp.Q)
+        assert r["lam_max"] >= ev[-1] and r["lam_min"] <= ev[0] * (1 + 1e-9)
+
+
+def test_alone_equals_in_the_mix_bitwise():
+    print("[case] alone vs mix", flush=True)
+    ub = gen.uneven_batch(B=12, seed=33, n_lo=20, n_hi=120, dtype=np.float64)
+    X, Lam, res = duq.solve_batch_uneven(ub, method=duq.DGM, eps_out=1e-4, eps_in=1e-6, max_outer=50000)
+    for i in (0, 5, 11):
+        one = gen.UnevenBatch(ub.n[i:i + 1], ub.p[i:i + 1],
+                              ub.Q[ub.qoff[i]:ub.qoff[i] + ub.n[i] ** 2],
+                              ub.G[ub.goff[i]:ub.goff[i] + ub.p[i] * ub.n[i]],
+                              ub.q[ub.voff[i]:ub.voff[i] + ub.n[i]], ub.g[ub.coff[i]:ub.coff[i] + ub.p[i]],
+                              ub.lb[ub.voff[i]:ub.voff[i] + ub.n[i]], ub.ub[ub.voff[i]:ub.voff[i] + ub.n[i]],
+                              np.zeros(1, np.int64), np.zeros(1, np.int64), np.zeros(1, np.int64),
+                              np.zeros(1, np.int64))
+        X1, L1, r1 = duq.solve_batch_uneven(one, method=duq.DGM, eps_out=1e-4, eps_in=1e-6, max_outer=50000)
+        assert np.array_equal(X1, X[ub.voff[i]:ub.voff[i] + ub.n[i]])
+        assert np.array_equal(L1, Lam[ub.coff[i]:ub.coff[i] + ub.p[i]])
+        assert r1[0]["outer_iters"] == res[i]["outer_iters"] and r1[0]["inner_iters"] == res[i]["inner_iters"]
+
+
+def test_shared_hessian_batch_matches_oracle():
+    print("[case] shared MPC batch parity", flush=True)
+    sysm = gen.mpc_system(seed=2, N=10)
+    X0, Qlin, Glin = gen.mpc_batch(sysm, 12, seed=21)
+    qp0 = gen.mpc_instance(sysm, X0[0])
+    lmin, lmax, g2 = exact_constants(qp0)
+    X, Lam, res = duq.solve_batch_shared(sysm.H, sysm.G, sysm.lb, sysm.ub, Qlin, Glin,
+                                         constants=(lmin, lmax, g2), method=duq.DFGM, eps_out=1e-4,
+                                         eps_in=1e-8, max_outer=50000)
+    for b in range(12):
+        qp = gen.mpc_instance(sysm, X0[b])
+        ref = dfom.dfom_solve(qp, dfom.Options(method=dfom.DFGM, eps_out=1e-4, eps_in=1e-8, max_outer=50000,
+                                               lam_min=lmin, lam_max=lmax, G_norm2=g2))
+        assert res[b]["status"] == duq.DUQ_OK
+        assert res[b]["outer_iters"] == ref.outer_iters and res[b]["inner_iters"] == ref.inner_iters
+        np.testing.assert_allclose(X[b], ref.x, rtol=0, atol=1e-7)
+
+
+def test_batch_rejects_bad_input():
+    ub = gen.uneven_batch(B=3, seed=34, n_lo=20, n_hi=40)
+    ub.Q[5] = np.nan
+    with pytest.raises(duq.DuqError) as e:
+        duq.solve_batch_uneven(ub)
+    assert e.value.code == duq.DUQ_EINVAL

@@ -273,3 +273,30 @@ def test_deterministic_across_runs():
         x2, l2, r2 = s.solve(check=False)
     assert np.array_equal(x1, x2) and np.array_equal(l1, l2)
     assert r1["inner_iters"] == r2["inner_iters"]
+
+
+# ----------------------------------------------------------------------------
+# a8: FP32-accumulated first phase, FP64 refinement from the same state
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,p,engine,key", [(50, 25, duq.ENGINE_BLOCK, "config0"),
+                                            (1536, 768, duq.ENGINE_GRID, None)])
+def test_mixed_precision_switch_accuracy(n, p, engine, key):
+    print(f"[case] two-phase precision n={n}", flush=True)
+    qp = gen.config0() if key else gen.config1(n=n, p=p, seed=15)
+    qp32 = qp.rounded(np.float32)
+    _, fstar, _ = ipm_qp(qp32.Q, qp32.q, qp32.G, qp32.g, qp32.lb, qp32.ub)
+    c = consts_of(qp32)
+    with gpu_solver(qp, c, np.float32, method=duq.DFGM, eps_out=1e-4, eps_in=1e-8, engine=engine,
+                    accumulate=duq.ACC_F32, switch_factor=10.0, switch_stall=20, trace_outer=4000) as s:
+        x, lam, res = s.solve()
+        tr = s.trace(4000)
+    assert res["status"] == duq.DUQ_OK
+    assert 0 < res["f64_outer_iters"] < res["outer_iters"]
+    assert abs(res["f"] - fstar) / max(1.0, abs(fstar)) <= 1e-4
+    assert res["feas"] / max(1.0, np.linalg.norm(qp.g)) <= 1e-4
+    ks = tr["scalars"][:, 0]
+    assert np.array_equal(ks, np.arange(1, len(ks) + 1))     # one numbering across both phases
+    # the returned point is feasible to the tolerance on the FP64 data as well
+    feas64 = np.linalg.norm(np.maximum(qp32.G @ x + qp32.g, 0))
+    assert feas64 / max(1.0, np.linalg.norm(qp.g)) <= 1e-4 * (1 + 1e-6)
