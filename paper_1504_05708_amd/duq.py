@@ -235,13 +235,20 @@ def solve_batch_uneven(batch, constants=None, check=True, **opts):
     n = np.ascontiguousarray(batch.n, dtype=np.int32)
     p = np.ascontiguousarray(batch.p, dtype=np.int32)
     offs = [np.ascontiguousarray(v, dtype=np.int64) for v in (batch.qoff, batch.goff, batch.voff, batch.coff)]
-    Q = np.ascontiguousarray(batch.Q)
-    G = np.ascontiguousarray(batch.G, dtype=Q.dtype)
-    dt = {np.dtype(np.float64): F64, np.dtype(np.float32): F32}[Q.dtype]
-    vecs = [np.ascontiguousarray(v, dtype=np.float64) for v in (batch.q, batch.g, batch.lb, batch.ub)]
+    dev = hasattr(batch.Q, "data_ptr")
+    if dev:   # torch tensors on the GPU: borrowed
+        import torch
+        Q, G = batch.Q, batch.G
+        dt = {torch.float64: F64, torch.float32: F32}[Q.dtype]
+        vecs = [batch.q, batch.g, batch.lb, batch.ub]
+    else:
+        Q = np.ascontiguousarray(batch.Q)
+        G = np.ascontiguousarray(batch.G, dtype=Q.dtype)
+        dt = {np.dtype(np.float64): F64, np.dtype(np.float32): F32}[Q.dtype]
+        vecs = [np.ascontiguousarray(v, dtype=np.float64) for v in (batch.q, batch.g, batch.lb, batch.ub)]
     cs = [None, None, None] if constants is None else [np.ascontiguousarray(c, dtype=np.float64)
                                                        for c in constants]
-    b = DuqBatch(BATCH_UNEVEN, B, dt, HOST, 0, 0, _ptr(n), _ptr(p), *[_ptr(o) for o in offs],
+    b = DuqBatch(BATCH_UNEVEN, B, dt, DEVICE if dev else HOST, 0, 0, _ptr(n), _ptr(p), *[_ptr(o) for o in offs],
                  _ptr(Q), _ptr(G), *[_ptr(v) for v in vecs], *[_ptr(c) for c in cs])
     return _run_batch(b, B, int(batch.q.shape[0]), int(batch.g.shape[0]), check, opts)
 
@@ -250,17 +257,22 @@ def solve_batch_shared(Q, G, lb, ub, q, g, constants=None, check=True, **opts):
     """duq_solve_batch on B instances sharing Q, G, lb, ub; q is B x n, g is B x p.
 
     constants: optional (lam_min, lam_max, G_norm2) scalars."""
-    Q = np.ascontiguousarray(Q)
-    dt = {np.dtype(np.float64): F64, np.dtype(np.float32): F32}[Q.dtype]
-    G = np.ascontiguousarray(G, dtype=Q.dtype)
-    q = np.ascontiguousarray(q, dtype=np.float64)
-    g = np.ascontiguousarray(g, dtype=np.float64)
-    lb = np.ascontiguousarray(lb, dtype=np.float64)
-    ub = np.ascontiguousarray(ub, dtype=np.float64)
-    B, n = q.shape
-    p = g.shape[1]
+    dev = hasattr(Q, "data_ptr")
+    if dev:   # torch tensors on the GPU: borrowed
+        import torch
+        dt = {torch.float64: F64, torch.float32: F32}[Q.dtype]
+    else:
+        Q = np.ascontiguousarray(Q)
+        dt = {np.dtype(np.float64): F64, np.dtype(np.float32): F32}[Q.dtype]
+        G = np.ascontiguousarray(G, dtype=Q.dtype)
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        lb = np.ascontiguousarray(lb, dtype=np.float64)
+        ub = np.ascontiguousarray(ub, dtype=np.float64)
+    B, n = int(q.shape[0]), int(q.shape[1])
+    p = int(g.shape[1])
     cs = [None, None, None] if constants is None else [np.array([c], dtype=np.float64) for c in constants]
-    b = DuqBatch(BATCH_SHARED, B, dt, HOST, n, p, None, None, None, None, None, None,
+    b = DuqBatch(BATCH_SHARED, B, dt, DEVICE if dev else HOST, n, p, None, None, None, None, None, None,
                  _ptr(Q), _ptr(G), _ptr(q), _ptr(g), _ptr(lb), _ptr(ub), *[_ptr(c) for c in cs])
     X, Lam, res = _run_batch(b, B, B * n, B * p, check, opts)
     return X.reshape(B, n), Lam.reshape(B, p), res

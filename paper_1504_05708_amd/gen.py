@@ -231,12 +231,29 @@ class UnevenBatch:
                   self.lb[sl].copy(), self.ub[sl].copy(), dict(kind="uneven", index=i))
 
 
+def _uneven_chunk(args):
+    children, ns, ps, reg, dtype = args
+    out = []
+    try:   # small products: one BLAS thread per worker is fastest
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    for ch, n, p in zip(children, ns, ps):
+        qp = random_dense_qp(int(n), int(p), seed=np.random.default_rng(ch), reg=reg)
+        out.append((qp.Q.astype(dtype).ravel(), qp.G.astype(dtype).ravel(), qp.q, qp.g, qp.lb, qp.ub))
+    if limiter is not None:
+        limiter.unregister() if hasattr(limiter, "unregister") else limiter.restore_original_limits()
+    return out
+
+
 def uneven_batch(B: int = 10000, seed: int = 3, n_lo: int = 20, n_hi: int = 512,
-                 reg: float = 0.1, dtype=np.float32) -> UnevenBatch:
+                 reg: float = 0.1, dtype=np.float32, workers: int = 1) -> UnevenBatch:
     """B random_dense_qp instances with n ~ U{n_lo..n_hi}, p = n // 2.
 
-    Instance i draws from SeedSequence(seed).spawn(B)[i]; sizes come from a
-    separate stream of the same seed."""
+    Instance i draws from SeedSequence(seed).spawn(B + 1)[i + 1]; sizes come
+    from child 0.  `workers` > 1 draws instances in parallel processes (the
+    result does not depend on it)."""
     ss = np.random.SeedSequence(seed)
     children = ss.spawn(B + 1)
     size_rng = np.random.default_rng(children[0])
@@ -256,14 +273,23 @@ def uneven_batch(B: int = 10000, seed: int = 3, n_lo: int = 20, n_hi: int = 512,
     gf = np.empty(int(ps.sum()))
     lbf = np.empty(int(ns.sum()))
     ubf = np.empty(int(ns.sum()))
-    for i in range(B):
-        qp = random_dense_qp(int(ns[i]), int(ps[i]), seed=np.random.default_rng(children[i + 1]),
-                             reg=reg)
-        n, p = qp.n, qp.p
-        Qf[qoff[i]:qoff[i] + n * n] = qp.Q.ravel()
-        Gf[goff[i]:goff[i] + p * n] = qp.G.ravel()
-        qf[voff[i]:voff[i] + n] = qp.q
-        lbf[voff[i]:voff[i] + n] = qp.lb
-        ubf[voff[i]:voff[i] + n] = qp.ub
-        gf[coff[i]:coff[i] + p] = qp.g
+    chunks = [(children[1 + a:1 + min(B, a + 256)], ns[a:a + 256], ps[a:a + 256], reg, dtype)
+              for a in range(0, B, 256)]
+    if workers > 1 and B > 256:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            parts = pool.map(_uneven_chunk, chunks)
+    else:
+        parts = [_uneven_chunk(c) for c in chunks]
+    i = 0
+    for part in parts:
+        for Qi, Gi, qi, gi, lbi, ubi in part:
+            n, p = int(ns[i]), int(ps[i])
+            Qf[qoff[i]:qoff[i] + n * n] = Qi
+            Gf[goff[i]:goff[i] + p * n] = Gi
+            qf[voff[i]:voff[i] + n] = qi
+            lbf[voff[i]:voff[i] + n] = lbi
+            ubf[voff[i]:voff[i] + n] = ubi
+            gf[coff[i]:coff[i] + p] = gi
+            i += 1
     return UnevenBatch(ns, ps, Qf, Gf, qf, gf, lbf, ubf, qoff, goff, voff, coff)
