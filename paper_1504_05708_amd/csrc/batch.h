@@ -102,8 +102,8 @@ __device__ inline void batch_carve(char* base, int n, int p, int k, DevWork& W, 
     W.lam0 = nullptr;
 }
 
-template <typename T, typename Acc>
-__device__ void batch_solve(const BatchArgs<T>& a, double* lds) {
+template <typename T, typename Acc, bool SHORT>
+__device__ __forceinline__ void batch_solve(const BatchArgs<T>& a, double* lds) {
     __shared__ int s_idx;
     DevWork W;
     LanczosWork LW;
@@ -138,7 +138,7 @@ __device__ void batch_solve(const BatchArgs<T>& a, double* lds) {
             lmax = a.lam_max[ci];
             g2 = p > 0 ? a.g2[ci] : 0.0;
         } else {
-            Lanczos<T> lz;
+            Lanczos<T, SHORT> lz;
             lz.P = P;
             lz.L = LW;
             lz.k = min(a.lanczos_k, n);
@@ -154,6 +154,7 @@ __device__ void batch_solve(const BatchArgs<T>& a, double* lds) {
             lz.vl = lds + a.n_max;
             lz.hl = lds + a.n_max + a.p_max + 1;
             lz.red = lz.hl + a.lanczos_alloc + 2;
+            lz.tl = lds + a.n_max + a.p_max + 1 + a.lanczos_alloc + 2 + kMaxWaves * kNP + 16;
             lz.use_gtg = 0;
             lz.run();
             __syncthreads();
@@ -204,7 +205,7 @@ __device__ void batch_solve(const BatchArgs<T>& a, double* lds) {
         par.resume = 0;
 
         if (!bad) {
-            Dfom<T, Acc> s;
+            Dfom<T, Acc, SHORT> s;
             s.P = P;
             s.par = par;
             s.W = W;
@@ -220,6 +221,7 @@ __device__ void batch_solve(const BatchArgs<T>& a, double* lds) {
             s.xl = lds;
             s.vl = lds + a.n_max;
             s.red = lds + a.n_max + a.p_max + 1;
+            s.tl = lds + a.n_max + a.p_max + 1 + a.lanczos_alloc + 2 + kMaxWaves * kNP + 16;
             if (threadIdx.x == 0) W.st->gt_rows = 0;
             __syncthreads();
             s.run();

@@ -178,7 +178,7 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
     const int k = std::min(k_req, n_max);
     const size_t shmem = batch_lds_bytes(n_max, p_max, k);
     int bpc = 0;
-    BTRY(batch_occupancy(b->dtype, shmem, &bpc));
+    BTRY(batch_occupancy(b->dtype, n_max, shmem, &bpc));
     if (bpc < 1) return set_error(DUQ_EINVAL, "batch instance too large for one workgroup's LDS");
     const int nblocks = std::max(1, std::min(B, device_cus() * bpc));
     const long long slot = batch_slot_bytes_host(n_max, p_max, k);

@@ -10,6 +10,7 @@ namespace duq {
 
 constexpr int kWave = 64;
 constexpr int kMaxWaves = 16;            // blocks of at most 1024 threads
+constexpr int kTlDoubles = 512 * 4;      // short-row G^T v scratch: blockDim (<= 512) x 4
 
 __device__ __forceinline__ double wave_sum(double v) {
     // xor butterfly: every lane ends with the bitwise-identical total

@@ -28,7 +28,23 @@ namespace duq {
 // loads (the matrix is read once per product and must not evict the vectors
 // from the caches; on this chip the streaming hint also raises the achieved
 // HBM rate from ~6.2 to ~7.3 TB/s for this access pattern).
-template <typename T, typename Acc, int U = 8>
+template <typename T, bool NT>
+__device__ __forceinline__ typename Vec16<T>::type vload(const typename Vec16<T>::type* p) {
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+
+template <typename T, bool NT>
+__device__ __forceinline__ T sload(const T* p) {
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+
+// NT: stream the matrix with non-temporal loads.  Used when the matrix is far
+// larger than the caches and read once per product (one large QP on the whole
+// grid); per-instance matrices that are re-read every inner step (one
+// workgroup per QP) use ordinary loads so that they stay cached.
+template <typename T, typename Acc, int U = 8, bool NT = true, bool SHORT = false>
 __device__ __forceinline__ void gemv_rows(const T* A, long ld, int rlo, int rhi, int ncols,
                                           const double* xl, double* out, const double* add) {
     typedef typename Vec16<T>::type VT;
@@ -37,6 +53,57 @@ __device__ __forceinline__ void gemv_rows(const T* A, long ld, int rlo, int rhi,
     const int wid = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
     const bool vec = ((ld * (long)sizeof(T)) % 16 == 0) && ((((uintptr_t)A) & 15) == 0);
+    if constexpr (SHORT) {
+        // Short rows (at most two 16-byte vectors per lane; the caller
+        // guarantees ncols <= 2*64*V): R rows in flight per wavefront.  Every
+        // row is summed in exactly the order of the long-row path below, so
+        // the choice of path never changes a result.
+        constexpr int R = 8;
+        const int nv = ncols / V;
+        for (int r0 = rlo + wid * R; r0 < rhi; r0 += nw * R) {
+            Acc s[R];
+#pragma unroll
+            for (int q = 0; q < R; ++q) s[q] = 0;
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                const int v = lane + kk * kWave;
+                if (v < nv) {
+                    const double* xv = xl + (long)v * V;
+                    VT a[R];
+#pragma unroll
+                    for (int q = 0; q < R; ++q) {
+                        if (r0 + q < rhi) {
+                            const T* row = A + (long)(r0 + q) * ld;
+                            if (vec) {
+                                a[q] = vload<T, NT>(reinterpret_cast<const VT*>(row) + v);
+                            } else {
+#pragma unroll
+                                for (int e = 0; e < V; ++e) a[q][e] = row[(long)v * V + e];
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < R; ++q) {
+                        if (r0 + q < rhi) {
+#pragma unroll
+                            for (int e = 0; e < V; ++e) s[q] += (Acc)a[q][e] * (Acc)xv[e];
+                        }
+                    }
+                }
+            }
+            for (int j = nv * V + lane; j < ncols; j += kWave) {
+#pragma unroll
+                for (int q = 0; q < R; ++q)
+                    if (r0 + q < rhi) s[q] += (Acc)A[(long)(r0 + q) * ld + j] * (Acc)xl[j];
+            }
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const Acc t = wave_sum(s[q]);
+                if (lane == 0 && r0 + q < rhi) out[r0 + q] = (double)t + (add ? add[r0 + q] : 0.0);
+            }
+        }
+        return;
+    } else {
     for (int r = rlo + wid; r < rhi; r += nw) {
         const T* row = A + (long)r * ld;
         Acc s = 0;
@@ -48,7 +115,7 @@ __device__ __forceinline__ void gemv_rows(const T* A, long ld, int rlo, int rhi,
             for (; v + kWave * (U - 1) < nv; v += kWave * U) {
                 VT a[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) a[u] = __builtin_nontemporal_load(rv + v + kWave * u);
+                for (int u = 0; u < U; ++u) a[u] = vload<T, NT>(rv + v + kWave * u);
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const double* xv = xl + (long)(v + kWave * u) * V;
@@ -57,7 +124,7 @@ __device__ __forceinline__ void gemv_rows(const T* A, long ld, int rlo, int rhi,
                 }
             }
             for (; v < nv; v += kWave) {
-                VT a = __builtin_nontemporal_load(rv + v);
+                VT a = vload<T, NT>(rv + v);
                 const double* xv = xl + (long)v * V;
 #pragma unroll
                 for (int e = 0; e < V; ++e) s += (Acc)a[e] * (Acc)xv[e];
@@ -80,18 +147,71 @@ __device__ __forceinline__ void gemv_rows(const T* A, long ld, int rlo, int rhi,
         s = wave_sum(s);
         if (lane == 0) out[r] = (double)s + (add ? add[r] : 0.0);
     }
+    }
 }
 
 // Phase 1 of z = A^T v over the rows [rlo, rhi) of A: dst[j] = sum_r A[r,j] v[r]
 // (+ add[j] when add != null).  Threads run over columns; rows with v[r] = 0
 // are skipped (exactly: they add +0).  vl holds v[rlo..rhi) in LDS.
 // Returns the number of rows with v != 0.
-template <typename T, typename Acc>
+template <typename T, typename Acc, bool NT = true>
 __device__ __forceinline__ int gemvT_rows(const T* A, long ld, int rlo, int rhi, int ncols,
-                                          const double* vl, double* dst, const double* add, bool shared_dst) {
+                                          const double* vl, double* dst, const double* add, bool shared_dst,
+                                          double* tl = nullptr) {
     typedef typename Vec16<T>::type VT;
     constexpr int V = Vec16<T>::N;
     const bool vec = ((ld * (long)sizeof(T)) % 16 == 0) && ((((uintptr_t)A) & 15) == 0);
+    {
+        // Short rows: split the rows over G thread groups.  Unit u is a
+        // 16-byte column vector (u < nvec) or one tail column; group g sums rows
+        // rlo+g, rlo+g+G, ... in order, and the G partials of a column are added
+        // in group order.  The order depends only on the shape, not on the
+        // alignment of A.  tl: LDS scratch of blockDim*V doubles.
+        const int nvec = ncols / V;
+        const int nunit = nvec + (ncols - nvec * V);
+        const int G = nunit > 0 ? (int)blockDim.x / nunit : 1;
+        if (tl != nullptr && G > 1) {
+            const int t = threadIdx.x;
+            const int u = t % nunit, grp = t / nunit;
+            if (grp < G) {
+                const bool isvec = u < nvec;
+                const int c0 = isvec ? u * V : nvec * V + (u - nvec);
+                Acc acc[V];
+#pragma unroll
+                for (int e = 0; e < V; ++e) acc[e] = 0;
+                for (int r = rlo + grp; r < rhi; r += G) {
+                    const double vr = vl[r - rlo];
+                    if (vr == 0.0) continue;
+                    const T* row = A + (long)r * ld;
+                    if (isvec) {
+                        VT a;
+                        if (vec) a = vload<T, NT>(reinterpret_cast<const VT*>(row) + u);
+                        else {
+#pragma unroll
+                            for (int e = 0; e < V; ++e) a[e] = row[c0 + e];
+                        }
+#pragma unroll
+                        for (int e = 0; e < V; ++e) acc[e] += (Acc)a[e] * (Acc)vr;
+                    } else {
+                        acc[0] += (Acc)row[c0] * (Acc)vr;
+                    }
+                }
+                const int ne = isvec ? V : 1;
+                for (int e = 0; e < ne; ++e) tl[(long)grp * ncols + c0 + e] = (double)acc[e];
+            }
+            __syncthreads();
+            for (int j = threadIdx.x; j < ncols; j += blockDim.x) {
+                double sum = 0.0;
+                for (int g2 = 0; g2 < G; ++g2) sum += tl[(long)g2 * ncols + j];
+                const double val = sum + (add ? add[j] : 0.0);
+                if (shared_dst) xstore(dst + j, val); else dst[j] = val;
+            }
+            __syncthreads();
+            int nz = 0;
+            for (int r = rlo; r < rhi; ++r) nz += (vl[r - rlo] != 0.0);
+            return nz;
+        }
+    }
     const int nv = vec ? ncols / V : 0;
     for (int cv = threadIdx.x; cv < nv; cv += blockDim.x) {
         Acc acc[V];
@@ -102,12 +222,12 @@ __device__ __forceinline__ int gemvT_rows(const T* A, long ld, int rlo, int rhi,
         for (; r + 1 < rhi; r += 2) {
             const double v0 = vl[r - rlo], v1 = vl[r - rlo + 1];
             if (v0 != 0.0) {
-                VT a = __builtin_nontemporal_load(reinterpret_cast<const VT*>(A + (long)r * ld) + cv);
+                VT a = vload<T, NT>(reinterpret_cast<const VT*>(A + (long)r * ld) + cv);
 #pragma unroll
                 for (int e = 0; e < V; ++e) acc[e] += (Acc)a[e] * (Acc)v0;
             }
             if (v1 != 0.0) {
-                VT a = __builtin_nontemporal_load(reinterpret_cast<const VT*>(A + (long)(r + 1) * ld) + cv);
+                VT a = vload<T, NT>(reinterpret_cast<const VT*>(A + (long)(r + 1) * ld) + cv);
 #pragma unroll
                 for (int e = 0; e < V; ++e) acc[e] += (Acc)a[e] * (Acc)v1;
             }
@@ -115,7 +235,7 @@ __device__ __forceinline__ int gemvT_rows(const T* A, long ld, int rlo, int rhi,
         if (r < rhi) {
             const double v0 = vl[r - rlo];
             if (v0 != 0.0) {
-                VT a = __builtin_nontemporal_load(reinterpret_cast<const VT*>(A + (long)r * ld) + cv);
+                VT a = vload<T, NT>(reinterpret_cast<const VT*>(A + (long)r * ld) + cv);
 #pragma unroll
                 for (int e = 0; e < V; ++e) acc[e] += (Acc)a[e] * (Acc)v0;
             }
@@ -171,7 +291,11 @@ __device__ __forceinline__ void stage_shared(const double* src, int len, double*
 // The solver
 // ---------------------------------------------------------------------------
 
-template <typename T, typename Acc>
+// Rows of at most 2*64 16-byte vectors take the short-row product.
+template <typename T>
+__host__ __device__ constexpr bool short_rows(int n) { return n <= 2 * kWave * (int)(16 / sizeof(T)); }
+
+template <typename T, typename Acc, bool SHORT>
 struct Dfom {
     DevProblem<T> P;
     DevParams par;
@@ -181,6 +305,7 @@ struct Dfom {
     double* xl;              // LDS: staged n-vector
     double* vl;              // LDS: staged owned rows of a p-vector
     double* red;             // LDS: reduction scratch
+    double* tl;              // LDS: blockDim*4 doubles for short-row G^T v
     int pp;                  // ping-pong index of the partial buffer
     long long gt_rows;       // rows of G touched by transposed products
 
@@ -196,6 +321,17 @@ struct Dfom {
     __device__ __forceinline__ double get(const double* p) const { return tm.size > 1 ? xload(p) : *p; }
     __device__ __forceinline__ void stage_x(const double* src) {
         if (tm.size > 1) stage_shared(src, P.n, xl); else stage(src, P.n, xl);
+    }
+
+    // Products over owned rows: streamed (non-temporal) on a grid team,
+    // cached inside a single workgroup.
+    __device__ __forceinline__ void prodQ(double* out) const {
+        if (tm.size > 1) gemv_rows<T, Acc, 16, true, SHORT>(P.Q, P.n, nlo, nhi, P.n, xl, out, nullptr);
+        else gemv_rows<T, Acc, 16, false, SHORT>(P.Q, P.n, nlo, nhi, P.n, xl, out, nullptr);
+    }
+    __device__ __forceinline__ void prodG(double* out, const double* add) const {
+        if (tm.size > 1) gemv_rows<T, Acc, 8, true, SHORT>(P.G, P.n, plo, phi, P.n, xl, out, add);
+        else gemv_rows<T, Acc, 8, false, SHORT>(P.G, P.n, plo, phi, P.n, xl, out, add);
     }
     __device__ __forceinline__ void bind_rings() {
         xb0 = W.xb[0]; xb1 = W.xb[1]; xb2 = W.xb[2];
@@ -245,11 +381,11 @@ struct Dfom {
         for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) vl[i - plo] = v[i];
         __syncthreads();
         if (tm.size == 1) {
-            gt_rows += gemvT_rows<T, Acc>(P.G, n, plo, phi, n, vl, z, add, false);
+            gt_rows += gemvT_rows<T, Acc, false>(P.G, n, plo, phi, n, vl, z, add, false, tl);
             __syncthreads();
             return true;
         }
-        gt_rows += gemvT_rows<T, Acc>(P.G, n, plo, phi, n, vl, W.gtp + (long)tm.rank * n, nullptr, true);
+        gt_rows += gemvT_rows<T, Acc, true>(P.G, n, plo, phi, n, vl, W.gtp + (long)tm.rank * n, nullptr, true, tl);
         if (tm.sync()) return false;
         gemvT_reduce(W.gtp, tm.size, n, nlo, nhi, add, z);
         __syncthreads();
@@ -320,7 +456,7 @@ struct Dfom {
             if (t > 0 && par.inner_variant == 2) th = 0.5 * (1.0 + sqrt(1.0 + 4.0 * th * th));
             // Q x^{t+1}; the barrier inside allreduce published every x^{t+1} entry
             stage_x(xn);
-            gemv_rows<T, Acc, 16>(P.Q, n, nlo, nhi, n, xl, QX(nxt), nullptr);
+            prodQ(QX(nxt));
             __syncthreads();
             prv = cur;
             cur = nxt;
@@ -376,8 +512,8 @@ struct Dfom {
             if (!(gap == gap)) return -2;
             // products of x^{t+1} (published by the barrier inside allreduce)
             stage_x(xn);
-            gemv_rows<T, Acc, 16>(P.Q, n, nlo, nhi, n, xl, QX(nxt), nullptr);
-            gemv_rows<T, Acc>(P.G, n, plo, phi, n, xl, GX(nxt), nullptr);
+            prodQ(QX(nxt));
+            prodG(GX(nxt), nullptr);
             __syncthreads();
             ++t;
             prv = cur;
@@ -408,7 +544,7 @@ struct Dfom {
             return;
         }
         stage_x(X(cur));
-        gemv_rows<T, Acc>(P.G, P.n, plo, phi, P.n, xl, W.r, P.g);
+        prodG(W.r, P.g);
         __syncthreads();
     }
 
@@ -457,8 +593,8 @@ struct Dfom {
             gnorm = sqrt(gg[0]);
             if (tm.size > 1 && tm.sync()) return;
             stage_x(xb0);
-            gemv_rows<T, Acc, 16>(P.Q, n, nlo, nhi, n, xl, qb0, nullptr);
-            if (par.rho > 0.0) gemv_rows<T, Acc>(P.G, n, plo, phi, n, xl, gx0, nullptr);
+            prodQ(qb0);
+            if (par.rho > 0.0) prodG(gx0, nullptr);
             __syncthreads();
             theta = 1.0;
             S = 0.0;
@@ -476,8 +612,8 @@ struct Dfom {
             gt_rows = 0;
             // products of the warm start in this launch's accumulation precision
             stage_x(X(cur));
-            gemv_rows<T, Acc, 16>(P.Q, n, nlo, nhi, n, xl, QX(cur), nullptr);
-            if (par.rho > 0.0) gemv_rows<T, Acc>(P.G, n, plo, phi, n, xl, GX(cur), nullptr);
+            prodQ(QX(cur));
+            if (par.rho > 0.0) prodG(GX(cur), nullptr);
             __syncthreads();
         }
         double best = par.resume ? st->best_metric : INFINITY;

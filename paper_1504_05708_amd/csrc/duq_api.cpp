@@ -340,7 +340,7 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
     if (h->cfg.cooperative) {
         for (int acc = 0; acc <= (dtype == DUQ_F32 ? 1 : 0); ++acc) {
             int bpc = 0;
-            if (dfom_occupancy(dtype, acc, h->cfg.nthreads, h->cfg.shmem, &bpc) != hipSuccess || bpc < 1) {
+            if (dfom_occupancy(dtype, acc, n, h->cfg.nthreads, h->cfg.shmem, &bpc) != hipSuccess || bpc < 1) {
                 duq_destroy(h);
                 return fail(DUQ_EDEVICE, "cooperative launch does not fit one block per CU");
             }

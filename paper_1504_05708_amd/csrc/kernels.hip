@@ -12,18 +12,18 @@ namespace duq {
 // LDS layout of the solver: [x staged (n)] [owned p rows (pmax)] [reduction scratch].
 static size_t solver_lds_doubles(int n, int p, int nblocks) {
     const int pmax = (p + nblocks - 1) / nblocks + 1;
-    return (size_t)n + (size_t)pmax + (size_t)kMaxWaves * kNP + 2;
+    return (size_t)n + (size_t)pmax + (size_t)kMaxWaves * kNP + 2 + kTlDoubles;
 }
 
 static size_t lanczos_lds_doubles(int n, int p, int nblocks, int k) {
     const int pmax = (p + nblocks - 1) / nblocks + 1;
-    return (size_t)n + (size_t)pmax + (size_t)(k + 2) + (size_t)kMaxWaves * 2 + 2;
+    return (size_t)n + (size_t)pmax + (size_t)(k + 2) + (size_t)kMaxWaves * 2 + 2 + kTlDoubles;
 }
 
-template <typename T, typename Acc>
+template <typename T, typename Acc, bool SHORT>
 __global__ void __launch_bounds__(512) dfom_kernel(DevProblem<T> P, DevParams par, DevWork W) {
     extern __shared__ __align__(16) double lds[];
-    Dfom<T, Acc> s;
+    Dfom<T, Acc, SHORT> s;
     s.P = P;
     s.par = par;
     s.W = W;
@@ -37,13 +37,14 @@ __global__ void __launch_bounds__(512) dfom_kernel(DevProblem<T> P, DevParams pa
     s.xl = lds;
     s.vl = lds + P.n;
     s.red = lds + P.n + pmax;
+    s.tl = s.red + kMaxWaves * kNP + 2;
     s.run();
 }
 
-template <typename T>
+template <typename T, bool SHORT>
 __global__ void __launch_bounds__(512) lanczos_kernel(DevProblem<T> P, LanczosWork L, int k, int use_gtg) {
     extern __shared__ __align__(16) double lds[];
-    Lanczos<T> s;
+    Lanczos<T, SHORT> s;
     s.P = P;
     s.L = L;
     s.k = k;
@@ -59,24 +60,33 @@ __global__ void __launch_bounds__(512) lanczos_kernel(DevProblem<T> P, LanczosWo
     s.vl = lds + P.n;
     s.hl = lds + P.n + pmax;
     s.red = s.hl + (k + 2);
+    s.tl = s.red + kMaxWaves * 2 + 2;
     s.run();
 }
 
-template <typename T, typename Acc>
-__global__ void __launch_bounds__(256) dfom_batch_kernel(BatchArgs<T> a) {
+template <typename T, typename Acc, bool SHORT>
+__global__ void __launch_bounds__(256, 3) dfom_batch_kernel(BatchArgs<T> a) {
     extern __shared__ __align__(16) double lds[];
-    batch_solve<T, Acc>(a, lds);
+    batch_solve<T, Acc, SHORT>(a, lds);
 }
 
 size_t batch_lds_bytes(int n_max, int p_max, int k) {
-    return ((size_t)n_max + p_max + 1 + (size_t)(k + 2) + (size_t)kMaxWaves * kNP + 16) * sizeof(double);
+    return ((size_t)n_max + p_max + 1 + (size_t)(k + 2) + (size_t)kMaxWaves * kNP + 16 + kTlDoubles) *
+           sizeof(double);
 }
 
 long long batch_slot_bytes_host(int n_max, int p_max, int k) { return batch_slot_bytes(n_max, p_max, k); }
 
-hipError_t batch_occupancy(int dtype, size_t shmem, int* blocks_per_cu) {
-    const void* f = dtype == 0 ? reinterpret_cast<const void*>(&dfom_batch_kernel<double, double>)
-                               : reinterpret_cast<const void*>(&dfom_batch_kernel<float, double>);
+static const void* batch_fn(int dtype, int n_max) {
+    if (dtype == 0)
+        return short_rows<double>(n_max) ? reinterpret_cast<const void*>(&dfom_batch_kernel<double, double, true>)
+                                         : reinterpret_cast<const void*>(&dfom_batch_kernel<double, double, false>);
+    return short_rows<float>(n_max) ? reinterpret_cast<const void*>(&dfom_batch_kernel<float, double, true>)
+                                    : reinterpret_cast<const void*>(&dfom_batch_kernel<float, double, false>);
+}
+
+hipError_t batch_occupancy(int dtype, int n_max, size_t shmem, int* blocks_per_cu) {
+    const void* f = batch_fn(dtype, n_max);
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, 256, shmem);
@@ -94,29 +104,35 @@ __global__ void count_nonfinite_kernel(const T* a, long len, unsigned* out) {
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
 }
 
-template <typename K>
-static hipError_t launch_any(K kernel, const LaunchCfg& cfg, void** args) {
+static hipError_t launch_fn(const void* kernel, const LaunchCfg& cfg, void** args) {
     const size_t shmem = cfg.shmem;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
     if (cfg.cooperative)
-        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kernel), dim3(cfg.nblocks),
-                                          dim3(cfg.nthreads), args, shmem, cfg.stream);
-    return hipLaunchKernel(reinterpret_cast<const void*>(kernel), dim3(cfg.nblocks), dim3(cfg.nthreads),
-                           args, shmem, cfg.stream);
+        return hipLaunchCooperativeKernel(kernel, dim3(cfg.nblocks), dim3(cfg.nthreads), args, shmem, cfg.stream);
+    return hipLaunchKernel(kernel, dim3(cfg.nblocks), dim3(cfg.nthreads), args, shmem, cfg.stream);
 }
+
 
 size_t dfom_lds_bytes(int n, int p, int nblocks) { return solver_lds_doubles(n, p, nblocks) * sizeof(double); }
 size_t lanczos_lds_bytes(int n, int p, int nblocks, int k) {
     return lanczos_lds_doubles(n, p, nblocks, k) * sizeof(double);
 }
 
-hipError_t dfom_occupancy(int dtype, int acc, int nthreads, size_t shmem, int* blocks_per_cu) {
-    const void* f = nullptr;
-    if (dtype == 0) f = reinterpret_cast<const void*>(&dfom_kernel<double, double>);
-    else if (acc == 0) f = reinterpret_cast<const void*>(&dfom_kernel<float, double>);
-    else f = reinterpret_cast<const void*>(&dfom_kernel<float, float>);
+template <bool SHORT>
+static const void* dfom_fn_t(int dtype, int acc) {
+    if (dtype == 0) return reinterpret_cast<const void*>(&dfom_kernel<double, double, SHORT>);
+    if (acc == 0) return reinterpret_cast<const void*>(&dfom_kernel<float, double, SHORT>);
+    return reinterpret_cast<const void*>(&dfom_kernel<float, float, SHORT>);
+}
+
+static const void* dfom_fn(int dtype, int acc, int n) {
+    const bool sh = dtype == 0 ? short_rows<double>(n) : short_rows<float>(n);
+    return sh ? dfom_fn_t<true>(dtype, acc) : dfom_fn_t<false>(dtype, acc);
+}
+
+hipError_t dfom_occupancy(int dtype, int acc, int n, int nthreads, size_t shmem, int* blocks_per_cu) {
+    const void* f = dfom_fn(dtype, acc, n);
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, nthreads, shmem);
@@ -126,15 +142,15 @@ hipError_t launch_dfom(int dtype, int acc, const LaunchCfg& cfg, const GenericPr
                        const DevParams& par, const DevWork& W) {
     DevParams pr = par;
     DevWork w = W;
+    const void* f = dfom_fn(dtype, acc, gp.n);
     if (dtype == 0) {
         DevProblem<double> P{gp.n, gp.p, (const double*)gp.Q, (const double*)gp.G, gp.q, gp.g, gp.lb, gp.ub};
         void* args[] = {&P, &pr, &w};
-        return launch_any(&dfom_kernel<double, double>, cfg, args);
+        return launch_fn(f, cfg, args);
     }
     DevProblem<float> P{gp.n, gp.p, (const float*)gp.Q, (const float*)gp.G, gp.q, gp.g, gp.lb, gp.ub};
     void* args[] = {&P, &pr, &w};
-    if (acc == 0) return launch_any(&dfom_kernel<float, double>, cfg, args);
-    return launch_any(&dfom_kernel<float, float>, cfg, args);
+    return launch_fn(f, cfg, args);
 }
 
 hipError_t launch_lanczos(int dtype, const LaunchCfg& cfg, const GenericProblem& gp, const LanczosWork& L,
@@ -144,11 +160,15 @@ hipError_t launch_lanczos(int dtype, const LaunchCfg& cfg, const GenericProblem&
     if (dtype == 0) {
         DevProblem<double> P{gp.n, gp.p, (const double*)gp.Q, (const double*)gp.G, gp.q, gp.g, gp.lb, gp.ub};
         void* args[] = {&P, &l, &kk, &ug};
-        return launch_any(&lanczos_kernel<double>, cfg, args);
+        const void* f = short_rows<double>(gp.n) ? reinterpret_cast<const void*>(&lanczos_kernel<double, true>)
+                                                 : reinterpret_cast<const void*>(&lanczos_kernel<double, false>);
+        return launch_fn(f, cfg, args);
     }
     DevProblem<float> P{gp.n, gp.p, (const float*)gp.Q, (const float*)gp.G, gp.q, gp.g, gp.lb, gp.ub};
     void* args[] = {&P, &l, &kk, &ug};
-    return launch_any(&lanczos_kernel<float>, cfg, args);
+    const void* f = short_rows<float>(gp.n) ? reinterpret_cast<const void*>(&lanczos_kernel<float, true>)
+                                            : reinterpret_cast<const void*>(&lanczos_kernel<float, false>);
+    return launch_fn(f, cfg, args);
 }
 
 hipError_t launch_count_nonfinite(int dtype, const void* a, long len, unsigned* out, hipStream_t s) {
@@ -162,16 +182,17 @@ hipError_t launch_count_nonfinite(int dtype, const void* a, long len, unsigned* 
 
 hipError_t launch_batch(int dtype, int nblocks, size_t shmem, hipStream_t stream, const BatchLaunch& b) {
     LaunchCfg cfg{nblocks, 256, shmem, false, stream};
+    const void* f = batch_fn(dtype, b.n_max);
     if (dtype == 0) {
         BatchArgs<double> a;
         fill_batch_args(a, b);
         void* args[] = {&a};
-        return launch_any(&dfom_batch_kernel<double, double>, cfg, args);
+        return launch_fn(f, cfg, args);
     }
     BatchArgs<float> a;
     fill_batch_args(a, b);
     void* args[] = {&a};
-    return launch_any(&dfom_batch_kernel<float, double>, cfg, args);
+    return launch_fn(f, cfg, args);
 }
 
 }  // namespace duq

@@ -11,7 +11,7 @@
 
 namespace duq {
 
-template <typename T>
+template <typename T, bool SHORT>
 struct Lanczos {
     DevProblem<T> P;
     LanczosWork L;
@@ -23,6 +23,7 @@ struct Lanczos {
     double* vl;
     double* hl;      // LDS: k+2 reduced values
     double* red;
+    double* tl;      // LDS: blockDim*4 doubles for short-row G^T v
 
     // The Krylov basis V is staged by every workgroup: device-scope accesses
     // on a grid team.  w is private to its owner rows.
@@ -35,7 +36,7 @@ struct Lanczos {
     }
 
     // h[j] = sum_i V[j][i] w[i] for j < m over the team; result in hl.
-    __device__ bool dots(const double* w, int m) {
+    __device__ __forceinline__ bool dots(const double* w, int m) {
         const int n = P.n;
         const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
         const int ncol = k + 2;
@@ -62,24 +63,26 @@ struct Lanczos {
         return true;
     }
 
-    __device__ bool apply(const double* v, double* w) {
+    __device__ __forceinline__ bool apply(const double* v, double* w) {
         const int n = P.n;
         if (tm.size > 1) stage_shared(v, n, xl); else stage(v, n, xl);
         if (!use_gtg) {
-            gemv_rows<T, double>(P.Q, n, nlo, nhi, n, xl, w, nullptr);
+            if (tm.size > 1) gemv_rows<T, double, 16, true, SHORT>(P.Q, n, nlo, nhi, n, xl, w, nullptr);
+            else gemv_rows<T, double, 16, false, SHORT>(P.Q, n, nlo, nhi, n, xl, w, nullptr);
             __syncthreads();
             return true;
         }
-        gemv_rows<T, double>(P.G, n, plo, phi, n, xl, L.r, nullptr);
+        if (tm.size > 1) gemv_rows<T, double, 8, true, SHORT>(P.G, n, plo, phi, n, xl, L.r, nullptr);
+        else gemv_rows<T, double, 8, false, SHORT>(P.G, n, plo, phi, n, xl, L.r, nullptr);
         __syncthreads();
         for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) vl[i - plo] = L.r[i];
         __syncthreads();
         if (tm.size == 1) {
-            gemvT_rows<T, double>(P.G, n, plo, phi, n, vl, w, nullptr, false);
+            gemvT_rows<T, double, false>(P.G, n, plo, phi, n, vl, w, nullptr, false, tl);
             __syncthreads();
             return true;
         }
-        gemvT_rows<T, double>(P.G, n, plo, phi, n, vl, L.gtp + (long)tm.rank * n, nullptr, true);
+        gemvT_rows<T, double, true>(P.G, n, plo, phi, n, vl, L.gtp + (long)tm.rank * n, nullptr, true, tl);
         if (tm.sync()) return false;
         const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
         for (int j = nlo + wid; j < nhi; j += nw) {
@@ -105,7 +108,7 @@ struct Lanczos {
         return cnt;
     }
 
-    __device__ void run() {
+    __device__ __forceinline__ void run() {
         const int n = P.n;
         double* a = L.ab;        // written by rank 0 only, read back by it
         double* b = L.ab + k;
@@ -175,7 +178,7 @@ struct Lanczos {
     }
 
     // hl[0] = ||w||^2 over the team.
-    __device__ bool dots_self() {
+    __device__ __forceinline__ bool dots_self() {
         const int n = P.n;
         (void)n;
         const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;

@@ -70,12 +70,12 @@ inline void fill_batch_args(A& a, const BatchLaunch& b) {
 
 size_t batch_lds_bytes(int n_max, int p_max, int k);
 long long batch_slot_bytes_host(int n_max, int p_max, int k);
-hipError_t batch_occupancy(int dtype, size_t shmem, int* blocks_per_cu);
+hipError_t batch_occupancy(int dtype, int n_max, size_t shmem, int* blocks_per_cu);
 hipError_t launch_batch(int dtype, int nblocks, size_t shmem, hipStream_t stream, const BatchLaunch& b);
 
 size_t dfom_lds_bytes(int n, int p, int nblocks);
 size_t lanczos_lds_bytes(int n, int p, int nblocks, int k);
-hipError_t dfom_occupancy(int dtype, int acc, int nthreads, size_t shmem, int* blocks_per_cu);
+hipError_t dfom_occupancy(int dtype, int acc, int n, int nthreads, size_t shmem, int* blocks_per_cu);
 hipError_t launch_dfom(int dtype, int acc, const LaunchCfg& cfg, const GenericProblem& gp,
                        const DevParams& par, const DevWork& W);
 hipError_t launch_lanczos(int dtype, const LaunchCfg& cfg, const GenericProblem& gp, const LanczosWork& L,
