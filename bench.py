@@ -48,10 +48,14 @@ def parse():
     ap.add_argument("--p", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--workload", choices=["single", "uneven", "mpc"], default="single",
+    ap.add_argument("--workload", choices=["single", "uneven", "mpc", "serve"], default="single",
                     help="single large QP (default), uneven batch, or shared-Hessian MPC batch")
     ap.add_argument("--batch", type=int, default=None, help="instances of a batch workload")
     ap.add_argument("--plain-sample", type=int, default=48)
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve: Poisson arrivals per second")
+    ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
+    ap.add_argument("--large-frac", type=float, default=0.01, help="serve: share of n=4096 requests")
+    ap.add_argument("--slice", type=int, default=16, help="serve: outer iterations per round")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain device copy of 1 GiB (counter calibration)")
     return ap.parse_args()
@@ -114,6 +118,9 @@ def main():
         sys.exit(2)
     if a.copy_probe:
         copy_probe()
+        return
+    if a.workload == "serve":
+        bench_serve(a)
         return
     if a.workload != "single":
         bench_batch(a)
@@ -419,6 +426,141 @@ def bench_batch(a):
                                 "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
                                 "sample": f"{done} instances of the batch solved by the oracle in {cs:.1f} s, "
                                           f"scaled by matrix work to all {B}"}
+    print(json.dumps(line), flush=True)
+
+
+def bench_serve(a):
+    """Serving loop: Poisson arrivals of a request mix, submitted from one host
+    thread to duq_submit, collected with duq_poll.  Mix: `large_frac` dense QPs
+    n=4096, p=2048 (config-1 generator; a pool of 8 (Q, G) made before the
+    timed window, fresh q, g per request), the rest half uneven random QPs
+    (n ~ U{20..512}, p = n//2) and half condensed MPC requests against 8
+    registered systems (seeds 40..47, fresh x0).  Matrices stored FP32."""
+    import threading
+
+    import torch
+    from paper_1504_05708_amd import duq, gen
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    duq.lib()
+    method = duq.DFGM if a.method == "dfgm" else duq.DGM
+    eps_in = a.eps_in if a.eps_in is not None else (1e-8 if method == duq.DFGM else 1e-6)
+    opts = dict(method=method, output=duq.LAST if a.output == "last" else duq.AVG, eps_out=a.eps_out,
+                eps_in=eps_in, rho=a.rho, max_outer=200000, serve_slice=a.slice)
+    npdt = np.float32 if a.precision == "f32" else np.float64
+    rng = np.random.default_rng(4)
+    t0 = time.time()
+    # arrivals and classes
+    gaps = rng.exponential(1.0 / a.rate, int(a.rate * a.duration * 1.5) + 16)
+    arr = np.cumsum(gaps)
+    arr = arr[arr < a.duration]
+    R = len(arr)
+    u = rng.uniform(size=R)
+    cls = np.where(u < a.large_frac, 2, np.where(u < a.large_frac + (1 - a.large_frac) / 2, 0, 1))
+    n_unev = int(np.sum(cls == 0))
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    ub = gen.uneven_batch(B=max(n_unev, 1), seed=4, dtype=npdt, workers=workers)
+    systems = [gen.mpc_system(seed=40 + j) for j in range(8)]
+    n_large = int(np.sum(cls == 2))
+    pool = []
+    if n_large:
+        for j in range(8):
+            qp = gen.config1(n=4096, p=2048, seed=100 + j)
+            pool.append((qp.Q.astype(npdt), qp.G.astype(npdt), qp.lb, qp.ub, qp.G))
+    reqs = []
+    iu = 0
+    for r in range(R):
+        if cls[r] == 0:
+            qp = ub.instance(iu)
+            iu += 1
+            reqs.append(("uneven", dict(Q=qp.Q.astype(npdt), q=qp.q, G=qp.G.astype(npdt), g=qp.g, lb=qp.lb,
+                                        ub=qp.ub)))
+        elif cls[r] == 1:
+            j = int(rng.integers(8))
+            q, g = gen.mpc_linear_terms(systems[j], rng.uniform(-1.0, 1.0, 12))
+            reqs.append(("mpc", dict(q=q, g=g, sys=j)))
+        else:
+            j = int(rng.integers(len(pool)))
+            Q, G, lb, ubx, G64 = pool[j]
+            q, g = gen.fresh_linear_terms(G64, rng)
+            reqs.append(("large", dict(Q=Q, q=q, G=G, g=g, lb=lb, ub=ubx)))
+    gen_s = time.time() - t0
+    budget = 32 << 30
+    srv = duq.Server(budget, **opts)
+    sids = [srv.register_shared(sy.H.astype(npdt), sy.G.astype(npdt), sy.lb, sy.ub) for sy in systems]
+    # warm-up: one request of each class, untimed
+    for kind, d in reqs[:: max(1, R // 3)][:3]:
+        t = srv.submit(q=d["q"], g=d["g"], shared_id=sids[d["sys"]]) if kind == "mpc" else srv.submit(**d)
+        srv.wait(t, timeout=300)
+    tickets = [None] * R
+    sub_t = np.zeros(R)
+    t_start = time.perf_counter()
+
+    def submitter():
+        for r, (kind, d) in enumerate(reqs):
+            delay = arr[r] - (time.perf_counter() - t_start)
+            if delay > 0:
+                time.sleep(delay)
+            sub_t[r] = time.perf_counter() - t_start
+            if kind == "mpc":
+                tickets[r] = srv.submit(q=d["q"], g=d["g"], shared_id=sids[d["sys"]])
+            else:
+                tickets[r] = srv.submit(**d)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    results = [None] * R
+    pending = set(range(R))
+    last_print = time.perf_counter()
+    while pending:
+        for r in list(pending):
+            if tickets[r] is None:
+                continue
+            out = srv.poll(tickets[r])
+            if out is not None:
+                results[r] = out
+                pending.discard(r)
+        now = time.perf_counter()
+        if now - last_print > 10:
+            print(f"[serve] t={now - t_start:.0f}s done {R - len(pending)}/{R}", file=sys.stderr, flush=True)
+            last_print = now
+        if now - t_start > a.duration + 240:
+            break
+        time.sleep(0.01)
+    th.join()
+    t_end = time.perf_counter()
+    srv.close()
+    done = [i for i in range(R) if results[i] is not None]
+    lat = np.array([results[i][3]["time_ms"] for i in done])
+    span = max(results[i][3]["time_ms"] * 1e-3 + sub_t[i] for i in done) if done else t_end - t_start
+    ok = sum(results[i][0] == duq.DUQ_OK for i in done)
+    by = {}
+    for k in ("uneven", "mpc", "large"):
+        ki = [i for i in done if reqs[i][0] == k]
+        li = [results[i][3]["time_ms"] for i in ki]
+        if li:
+            by[k] = {"count": len(li), "ok": sum(results[i][0] == duq.DUQ_OK for i in ki),
+                     "p50_ms": round(float(np.percentile(li, 50)), 3),
+                     "p99_ms": round(float(np.percentile(li, 99)), 3),
+                     "outer_mean": round(float(np.mean([results[i][3]["outer_iters"] for i in ki])), 1)}
+    cert = max((results[i][3]["f"] - results[i][3]["lb_dual"]) / max(1.0, abs(results[i][3]["f"])) for i in done)
+    line = {
+        "metric": METRIC, "value": round(len(done) / span, 2), "unit": "solves/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": round(span * 1e3, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"serving: Poisson arrivals {a.rate:g}/s for {a.duration:g} s (seed 4); "
+                               f"{a.large_frac:.0%} dense n=4096 p=2048 (pool of 8, fresh q,g), rest half uneven "
+                               f"n~U{{20..512}} and half MPC on 8 registered systems (seeds 40..47, fresh x0); "
+                               f"matrices {a.precision}; {a.method.upper()}-{a.output} eps_out={a.eps_out:g} "
+                               f"eps_in={eps_in:g}; {a.slice} outer iterations per round",
+                   "requests": R, "hbm_budget_bytes": budget},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
+                       "by_class": by},
+        "solve": {"completed": len(done), "ok": ok, "max_cert_subopt_rel": cert,
+                  "max_feas_abs": max(results[i][3]["feas"] for i in done)},
+        "offered_per_s": round(R / a.duration, 1),
+        "gen_seconds": round(gen_s, 1),
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -96,7 +96,8 @@ typedef struct duq_options {
     double safety;          /* inflation of estimated constants (default 1.02)   */
     double switch_factor;   /* DUQ_ACC_F32: switch to F64 at switch_factor*eps_out */
     int32_t switch_stall;   /* ... or after this many non-improving iterations   */
-    int32_t reserved[7];
+    int32_t serve_slice;    /* serving loop: outer iterations per round (0 = 16)  */
+    int32_t reserved[6];
 } duq_options;
 
 /* ---- per-solve result --------------------------------------------------- *
@@ -191,6 +192,68 @@ typedef struct duq_batch {
  * not (see res[i].status), or an error code.                                */
 int duq_solve_batch(const duq_batch *batch, const duq_options *opts, void *stream,
                     double *X_out, double *Lam_out, duq_result *res);
+
+/* ---- serving loop (the paper has none; requests are independent QPs) ---- *
+ * A server owns a device arena of hbm_budget_bytes (0 = 4 GiB), one HIP
+ * stream and one host thread.  The thread works in rounds:
+ *   1. admit pending requests in arrival order while their device footprint
+ *      (matrices, vectors, solver state) fits the arena, and upload them;
+ *   2. run one launch of the batch kernel over every admitted request with
+ *      n <= DUQ_SERVE_BATCH_NMAX; each runs a slice of outer iterations
+ *      worth about opts.serve_slice iterations at n = 256,
+ *      max(1, round(serve_slice (256^2 + 128^2) / (n^2 + 128^2))), and keeps
+ *      its whole state (iterates and their products) in the arena for the
+ *      next round;
+ *   3. run opts.serve_slice outer iterations of the admitted larger request
+ *      (one at a time, arrival order) on the single-QP engine (block or
+ *      grid, as duq_setup picks);
+ *   4. retire requests whose outer test passed (or that reached max_outer or
+ *      failed), free their memory, and go back to 1.
+ * Slicing changes no arithmetic: a request's iterates are those of the same
+ * request solved in one piece (duq_solve_batch for small requests), alone or
+ * in any mix.
+ * The options (fixed at creation) apply to every request; accumulate must be
+ * DUQ_ACC_F64 and tracing is not available.  All server calls are safe to
+ * make from several threads.                                               */
+#define DUQ_SERVE_BATCH_NMAX 1536
+typedef struct duq_server duq_server;
+
+typedef struct duq_request {
+    int32_t shared_id;      /* -1: the problem in `prob`; otherwise an id returned
+                               by duq_register_shared                           */
+    int32_t reserved;
+    duq_problem prob;       /* own problem: every field, memspace DUQ_HOST (the
+                               data are copied by duq_submit).  Registered system:
+                               only prob.q (n) and prob.g (p), host, are read.  */
+} duq_request;
+
+/* Create a server.  Errors: DUQ_EINVAL (options), DUQ_ENOMEM (the arena does
+ * not fit the free device memory), DUQ_EDEVICE.                            */
+int duq_server_create(size_t hbm_budget_bytes, const duq_options *opts, duq_server **out);
+
+/* Keep Q, G, lb, ub of one system resident (HOST copied, DEVICE copied into
+ * the arena) for requests that supply only q and g, e.g. an MPC problem
+ * whose linear terms follow the measured state.  Its constants come from the
+ * options or a device Lanczos estimate made here.  *id receives the id.
+ * Errors: DUQ_EINVAL, DUQ_ENOMEM (arena full), DUQ_EDEVICE.               */
+int duq_register_shared(duq_server *s, const duq_problem *shared_QG, int32_t *id);
+
+/* Queue one request; *ticket identifies it for duq_poll.  The request data
+ * are copied before the call returns.  Errors: DUQ_EINVAL (bad data,
+ * unknown shared_id), DUQ_ENOMEM (its footprint exceeds the whole arena),
+ * DUQ_EDEVICE (the server stopped after a device error).                   */
+int duq_submit(duq_server *s, const duq_request *req, uint64_t *ticket);
+
+/* DUQ_EAGAIN while the request is queued or running.  Once it has finished,
+ * writes x_out (n), lam_out (p) and res (any may be NULL; res->time_ms is the
+ * latency from duq_submit to completion), forgets the ticket and returns the
+ * request's status (DUQ_OK, DUQ_EMAXITER, DUQ_ENUMERIC or an error code).
+ * DUQ_ENOTFOUND for a ticket that is unknown or already collected.          */
+int duq_poll(duq_server *s, uint64_t ticket, double *x_out, double *lam_out, duq_result *res);
+
+/* Stop the server thread after its current round and free everything;
+ * requests not yet collected are dropped (NULL is allowed).                */
+void duq_server_destroy(duq_server *s);
 
 /* Release every resource of the handle (NULL is allowed).                  */
 void duq_destroy(duq_handle *h);

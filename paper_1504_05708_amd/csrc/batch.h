@@ -2,6 +2,14 @@
 // workgroup takes the next instance from a device work queue (instances are
 // ordered largest first), derives its constants (Sec. 2 eq. Ld, Sec. 3 Step 1,
 // Sec. 5 k_in) and runs Algorithm DFOM with the workgroup as the team.
+//
+// The same kernel serves the time-sliced serving loop: there each instance is
+// described by a ServeInst (its own pointers and workspace), runs at most
+// `slice` outer iterations per launch and resumes from its saved state in the
+// next launch (a separate instantiation, so the batch kernel carries none of
+// this).  The host launches short-row and long-row instances
+// (short_rows(n)) as separate kernels, so an instance runs the same code and
+// computes the same bits whatever else is in the batch.
 #pragma once
 #include "lanczos.h"
 
@@ -31,12 +39,14 @@ struct BatchArgs {
     double* X;
     double* Lam;
     BatchResultDev* res;
+    const ServeInst* inst;       // serving kernel: per-instance records (replace the fields above)
+    int slice;                   // serving: outer iterations per launch at n = 256 (scaled by work)
     DevParams base;              // options shared by every instance
     int max_inner;               // 0: k_in of Sec. 5
     int lanczos_k;               // requested Krylov steps (per instance: min(lanczos_k, n))
     int lanczos_alloc;           // min(lanczos_k, n_max): sizes the slot and LDS
     double safety;
-    char* slots;                 // per-workgroup workspace
+    char* slots;                 // per-workgroup workspace (batch mode)
     long long slot_bytes;
     int n_max, p_max;
     unsigned* queue;             // [0]: next queue position
@@ -102,12 +112,14 @@ __device__ inline void batch_carve(char* base, int n, int p, int k, DevWork& W, 
     W.lam0 = nullptr;
 }
 
-template <typename T, typename Acc, bool SHORT>
+template <typename T, typename Acc, bool SHORT, bool SERVE>
 __device__ __forceinline__ void batch_solve(const BatchArgs<T>& a, double* lds) {
     __shared__ int s_idx;
     DevWork W;
     LanczosWork LW;
-    batch_carve(a.slots + (long long)blockIdx.x * a.slot_bytes, a.n_max, a.p_max, a.lanczos_alloc, W, LW);
+    if constexpr (!SERVE) batch_carve(a.slots + (long long)blockIdx.x * a.slot_bytes, a.n_max, a.p_max, a.lanczos_alloc, W, LW);
+    double* const red = lds + a.n_max + a.p_max + 1;
+    double* const tl = lds + a.n_max + a.p_max + 1 + a.lanczos_alloc + 2 + kMaxWaves * kNP + 16;
     for (;;) {
         if (threadIdx.x == 0) s_idx = (int)atomicAdd(a.queue, 1u);
         __syncthreads();
@@ -115,33 +127,62 @@ __device__ __forceinline__ void batch_solve(const BatchArgs<T>& a, double* lds) 
         __syncthreads();
         if (qpos >= a.B) break;
         const int i = a.order[qpos];
-        const int n = a.shared ? a.n_shared : a.n[i];
-        const int p = a.shared ? a.p_shared : a.p[i];
         DevProblem<T> P;
-        P.n = n;
-        P.p = p;
-        P.Q = a.shared ? a.Q : a.Q + a.qoff[i];
-        P.G = a.shared ? a.G : a.G + a.goff[i];
-        const long long vo = a.shared ? (long long)i * n : a.voff[i];
-        const long long co = a.shared ? (long long)i * p : a.coff[i];
-        P.q = a.q + vo;
-        P.g = a.g + co;
-        P.lb = a.shared ? a.lb : a.lb + vo;
-        P.ub = a.shared ? a.ub : a.ub + vo;
-
-        // constants: supplied, or Lanczos on Q and on G^T G in this workgroup
+        double* xo;
+        double* lo;
+        int kk;
+        bool given, resume;
         double lmin, lmax, g2;
-        const int ci = a.shared ? 0 : i;
-        const bool given = a.lam_min && a.lam_max && a.g2;
-        if (given) {
-            lmin = a.lam_min[ci];
-            lmax = a.lam_max[ci];
-            g2 = p > 0 ? a.g2[ci] : 0.0;
+        if constexpr (SERVE) {
+            const ServeInst& si = a.inst[i];
+            P.n = si.n;
+            P.p = si.p;
+            P.Q = static_cast<const T*>(si.Q);
+            P.G = static_cast<const T*>(si.G);
+            P.q = si.q;
+            P.g = si.g;
+            P.lb = si.lb;
+            P.ub = si.ub;
+            xo = si.x;
+            lo = si.lam;
+            kk = si.k;
+            batch_carve(si.slot, si.n, si.p, si.k, W, LW);
+            resume = si.resume != 0;
+            given = si.given != 0 || resume;
+            lmin = si.lam_min;
+            lmax = si.lam_max;
+            g2 = si.g2;
         } else {
+            P.n = a.shared ? a.n_shared : a.n[i];
+            P.p = a.shared ? a.p_shared : a.p[i];
+            P.Q = a.shared ? a.Q : a.Q + a.qoff[i];
+            P.G = a.shared ? a.G : a.G + a.goff[i];
+            const long long vo = a.shared ? (long long)i * P.n : a.voff[i];
+            const long long co = a.shared ? (long long)i * P.p : a.coff[i];
+            P.q = a.q + vo;
+            P.g = a.g + co;
+            P.lb = a.shared ? a.lb : a.lb + vo;
+            P.ub = a.shared ? a.ub : a.ub + vo;
+            xo = a.X + vo;
+            lo = a.Lam + co;
+            kk = min(a.lanczos_k, P.n);
+            resume = false;
+            given = a.lam_min && a.lam_max && a.g2;
+            const int ci = a.shared ? 0 : i;
+            lmin = given ? a.lam_min[ci] : 0.0;
+            lmax = given ? a.lam_max[ci] : 0.0;
+            g2 = given ? a.g2[ci] : 0.0;
+        }
+        const int n = P.n, p = P.p;
+        if (p == 0) g2 = 0.0;
+
+        // constants: supplied (or found in an earlier slice), else Lanczos on
+        // Q and on G^T G in this workgroup
+        if (!given) {
             Lanczos<T, SHORT> lz;
             lz.P = P;
             lz.L = LW;
-            lz.k = min(a.lanczos_k, n);
+            lz.k = kk;
             lz.tm.rank = 0;
             lz.tm.size = 1;
             lz.tm.bar = nullptr;
@@ -152,9 +193,9 @@ __device__ __forceinline__ void batch_solve(const BatchArgs<T>& a, double* lds) 
             lz.phi = p;
             lz.xl = lds;
             lz.vl = lds + a.n_max;
-            lz.hl = lds + a.n_max + a.p_max + 1;
-            lz.red = lz.hl + a.lanczos_alloc + 2;
-            lz.tl = lds + a.n_max + a.p_max + 1 + a.lanczos_alloc + 2 + kMaxWaves * kNP + 16;
+            lz.hl = red;
+            lz.red = red + a.lanczos_alloc + 2;
+            lz.tl = tl;
             lz.use_gtg = 0;
             lz.run();
             __syncthreads();
@@ -178,10 +219,10 @@ __device__ __forceinline__ void batch_solve(const BatchArgs<T>& a, double* lds) 
             const double d = P.ub[j] - P.lb[j];
             du[0] += d * d;
         }
-        block_allreduce<1>(du, lds + a.n_max + a.p_max + 1);
+        block_allreduce<1>(du, red);
         const double D_U = sqrt(du[0]);
         const double denom = lmin + rho * g2;
-        int bad = (p > 0 && !(denom > 0.0)) || !(lmax > 0.0);
+        const int bad = (p > 0 && !(denom > 0.0)) || !(lmax > 0.0);
         const double Ld = p > 0 ? g2 / denom : 0.0;
         par.alpha = Ld > 0.0 ? 1.0 / (2.0 * Ld) : 0.0;
         par.L = lmax + rho * g2;
@@ -202,14 +243,21 @@ __device__ __forceinline__ void batch_solve(const BatchArgs<T>& a, double* lds) 
         par.trace_iters = 0;
         par.has_x0 = 0;
         par.has_lam0 = 0;
-        par.resume = 0;
+        par.resume = resume ? 2 : 0;
+        if constexpr (SERVE) {
+            // outer iterations in this launch: about the work of `slice`
+            // iterations at n = 256, from the instance's own n only
+            const double w = (256.0 * 256.0 + 128.0 * 128.0) / ((double)n * n + 128.0 * 128.0);
+            const int k_slice = max(1, (int)(a.slice * w + 0.5));
+            par.max_outer = min(par.max_outer, (resume ? W.st->k : 0) + k_slice);
+        }
 
         if (!bad) {
             Dfom<T, Acc, SHORT> s;
             s.P = P;
             s.par = par;
             s.W = W;
-            s.W.xout = a.X + vo;
+            s.W.xout = xo;
             s.tm.rank = 0;
             s.tm.size = 1;
             s.tm.bar = nullptr;
@@ -220,13 +268,13 @@ __device__ __forceinline__ void batch_solve(const BatchArgs<T>& a, double* lds) 
             s.phi = p;
             s.xl = lds;
             s.vl = lds + a.n_max;
-            s.red = lds + a.n_max + a.p_max + 1;
-            s.tl = lds + a.n_max + a.p_max + 1 + a.lanczos_alloc + 2 + kMaxWaves * kNP + 16;
-            if (threadIdx.x == 0) W.st->gt_rows = 0;
+            s.red = red;
+            s.tl = tl;
+            if (threadIdx.x == 0 && !resume) W.st->gt_rows = 0;
             __syncthreads();
             s.run();
             __syncthreads();
-            for (int j = threadIdx.x; j < p; j += blockDim.x) a.Lam[co + j] = W.lamp[j];
+            for (int j = threadIdx.x; j < p; j += blockDim.x) lo[j] = W.lamp[j];
         }
         if (threadIdx.x == 0) {
             BatchResultDev r;

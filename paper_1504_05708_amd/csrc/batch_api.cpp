@@ -165,7 +165,8 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
         dev_consts = true;
     }
 
-    // processing order: largest work first
+    // processing order: largest work first, long-row instances and
+    // short-row instances (separate kernels) each in that order
     std::vector<int> order(B);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
@@ -173,21 +174,41 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
         const long long wc = (long long)ns[c] * ns[c] + (long long)ps[c] * ns[c];
         return wa > wc;
     });
+    std::stable_partition(order.begin(), order.end(), [&](int i) { return !batch_short_class(b->dtype, ns[i]); });
 
     const int k_req = o->lanczos_steps > 0 ? o->lanczos_steps : 96;
-    const int k = std::min(k_req, n_max);
-    const size_t shmem = batch_lds_bytes(n_max, p_max, k);
-    int bpc = 0;
-    BTRY(batch_occupancy(b->dtype, n_max, shmem, &bpc));
-    if (bpc < 1) return set_error(DUQ_EINVAL, "batch instance too large for one workgroup's LDS");
-    const int nblocks = std::max(1, std::min(B, device_cus() * bpc));
-    const long long slot = batch_slot_bytes_host(n_max, p_max, k);
+    struct Cls {
+        bool sh;
+        int first = 0, count = 0, n_max = 1, p_max = 0, k = 0, nblocks = 0;
+        size_t shmem = 0;
+        long long slot = 0;
+        size_t o_slots = 0;
+    } cls[2];
+    cls[0].sh = false;
+    cls[1].sh = true;
+    for (int q = 0; q < B; ++q) {
+        Cls& c = cls[batch_short_class(b->dtype, ns[order[q]]) ? 1 : 0];
+        if (c.count == 0) c.first = q;
+        ++c.count;
+        c.n_max = std::max(c.n_max, ns[order[q]]);
+        c.p_max = std::max(c.p_max, ps[order[q]]);
+    }
+    for (Cls& c : cls) {
+        if (!c.count) continue;
+        c.k = std::min(k_req, c.n_max);
+        c.shmem = batch_lds_bytes(c.n_max, c.p_max, c.k);
+        int bpc = 0;
+        BTRY(batch_occupancy(b->dtype, c.sh, false, c.shmem, &bpc));
+        if (bpc < 1) return set_error(DUQ_EINVAL, "batch instance too large for one workgroup's LDS");
+        c.nblocks = std::max(1, std::min(c.count, device_cus() * bpc));
+        c.slot = batch_slot_bytes_host(c.n_max, c.p_max, c.k);
+    }
 
     // device workspace
     DevBuf ws;
     size_t off = 0;
     auto plan = [&](size_t n) { size_t r = off; off += ((n + 255) / 256) * 256; return r; };
-    const size_t o_slots = plan((size_t)slot * nblocks);
+    for (Cls& c : cls) c.o_slots = plan((size_t)c.slot * c.nblocks);
     const size_t o_X = plan(8 * vtot);
     const size_t o_L = plan(8 * std::max<long long>(ctot, 1));
     const size_t o_res = plan(sizeof(BatchResultDev) * B);
@@ -221,9 +242,7 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
     BTRY(hipMemsetAsync(w + o_q, 0, 256, s));
 
     BatchLaunch L{};
-    L.B = B;
     L.shared = shared ? 1 : 0;
-    L.order = d_order;
     L.n = d_n;
     L.p = d_p;
     L.qoff = d_off;
@@ -256,19 +275,43 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
     L.base = par;
     L.max_inner = o->max_inner;
     L.lanczos_k = k_req;
-    L.lanczos_alloc = k;
     L.safety = o->safety;
-    L.slots = w + o_slots;
-    L.slot_bytes = slot;
-    L.n_max = n_max;
-    L.p_max = p_max;
-    L.queue = (unsigned*)(w + o_q);
 
-    hipEvent_t e0, e1;
+    // the two classes run concurrently: long rows on `s`, short rows on a
+    // second stream joined back to `s`
+    const bool both = cls[0].count > 0 && cls[1].count > 0;
+    hipStream_t s2 = s;
+    hipEvent_t fork = nullptr, join = nullptr, e0, e1;
     BTRY(hipEventCreate(&e0));
     BTRY(hipEventCreate(&e1));
     BTRY(hipEventRecord(e0, s));
-    hipError_t le = launch_batch(b->dtype, nblocks, shmem, s, L);
+    if (both) {
+        BTRY(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+        BTRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        BTRY(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+        BTRY(hipEventRecord(fork, s));
+        BTRY(hipStreamWaitEvent(s2, fork, 0));
+    }
+    hipError_t le = hipSuccess;
+    for (int ci = 0; ci < 2 && le == hipSuccess; ++ci) {
+        const Cls& c = cls[ci];
+        if (!c.count) continue;
+        BatchLaunch Lc = L;
+        Lc.B = c.count;
+        Lc.order = d_order + c.first;
+        Lc.lanczos_alloc = c.k;
+        Lc.slots = w + c.o_slots;
+        Lc.slot_bytes = c.slot;
+        Lc.n_max = c.n_max;
+        Lc.p_max = c.p_max;
+        Lc.queue = (unsigned*)(w + o_q) + ci;
+        le = launch_batch(b->dtype, c.sh, c.nblocks, c.shmem, ci == 1 ? s2 : s, Lc);
+    }
+    if (both) {
+        hipError_t je = hipEventRecord(join, s2);
+        if (je == hipSuccess) je = hipStreamWaitEvent(s, join, 0);
+        if (le == hipSuccess) le = je;
+    }
     BTRY(hipEventRecord(e1, s));
     std::vector<BatchResultDev> rd(B);
     if (le == hipSuccess) {
@@ -281,6 +324,11 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
     (void)hipEventElapsedTime(&ms, e0, e1);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (both) {
+        (void)hipEventDestroy(fork);
+        (void)hipEventDestroy(join);
+        (void)hipStreamDestroy(s2);
+    }
     BTRY(le);
     BTRY(se);
     int code = DUQ_OK;

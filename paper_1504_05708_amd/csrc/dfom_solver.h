@@ -610,11 +610,13 @@ struct Dfom {
             k0 = st->k;
             inner_total = st->inner;
             gt_rows = 0;
-            // products of the warm start in this launch's accumulation precision
-            stage_x(X(cur));
-            prodQ(QX(cur));
-            if (par.rho > 0.0) prodG(GX(cur), nullptr);
-            __syncthreads();
+            if (par.resume == 1) {
+                // products of the warm start in this launch's accumulation precision
+                stage_x(X(cur));
+                prodQ(QX(cur));
+                if (par.rho > 0.0) prodG(GX(cur), nullptr);
+                __syncthreads();
+            }   // resume == 2: the stored products are this precision's; keep them
         }
         double best = par.resume ? st->best_metric : INFINITY;
         int stall = par.resume ? st->stall : 0;

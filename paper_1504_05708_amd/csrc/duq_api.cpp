@@ -142,6 +142,7 @@ void duq_default_options(duq_options* o) {
     o->safety = 1.02;
     o->switch_factor = 10.0;
     o->switch_stall = 20;
+    o->serve_slice = 16;
 }
 
 const char* duq_last_error(void) { return g_err.c_str(); }
@@ -606,6 +607,61 @@ extern "C" int duq_solve(duq_handle* h, const double* x0, const double* lam0, do
     if (code == DUQ_EMAXITER) g_err = "max_outer reached";
     return code;
 }
+
+namespace duq {
+
+// Serving loop: run at most `slice` more outer iterations of a handle's solve
+// (from the projection of 0 when `first`, else from the state the previous
+// slice left), with FP64 accumulation, and queue the copy of the scalar state
+// to `st_host`.  Nothing waits: the caller synchronises the stream.
+int handle_slice(duq_handle* h, bool first, int slice, int k_done, DevState* st_host) {
+    const duq_options& o = h->opts;
+    if (first) HIP_TRY(hipMemsetAsync(h->W.st, 0, sizeof(DevState), h->stream));
+    HIP_TRY(hipMemsetAsync(h->W.bar, 0, bar_words(h->cfg.nblocks) * sizeof(unsigned), h->stream));
+    DevParams par{};
+    par.method = o.method;
+    par.output = o.output;
+    par.inner_rule = o.inner_rule;
+    par.inner_variant = h->variant;
+    par.max_outer = std::min(o.max_outer, k_done + slice);
+    par.k_in_max = h->k_in;
+    par.Kd_nonneg = h->Kd_nonneg;
+    par.resume = first ? 0 : 2;
+    par.eps_out = o.eps_out;
+    par.eps_in = o.eps_in;
+    par.rho = o.rho;
+    par.alpha = h->alpha;
+    par.L = h->L_in;
+    par.sigma = h->sigma;
+    par.beta_in = h->beta_in;
+    GenericProblem gp{h->n, h->p, h->dQ, h->dG, h->dq, h->dg, h->dlb, h->dub};
+    HIP_TRY(launch_dfom(h->dtype, DUQ_ACC_F64, h->cfg, gp, par, h->W));
+    HIP_TRY(hipMemcpyAsync(st_host, h->W.st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    return DUQ_OK;
+}
+
+// Grid-barrier error flag of the last slice (read after the stream is idle).
+int handle_barrier_error(duq_handle* h, unsigned* flag) {
+    HIP_TRY(hipMemcpy(flag, h->W.bar + kBarErr, sizeof(unsigned), hipMemcpyDeviceToHost));
+    return DUQ_OK;
+}
+
+// Copy the returned primal point and multipliers of the last slice.
+int handle_outputs(duq_handle* h, double* x, double* lam) {
+    if (x) HIP_TRY(hipMemcpy(x, h->W.xout, h->n * sizeof(double), hipMemcpyDeviceToHost));
+    if (lam && h->p > 0) HIP_TRY(hipMemcpy(lam, h->W.lamp, h->p * sizeof(double), hipMemcpyDeviceToHost));
+    return DUQ_OK;
+}
+
+// Constants and engine of a handle, for reporting.
+void handle_info(duq_handle* h, double* lam_min, double* lam_max, double* g2, int* engine) {
+    *lam_min = h->lam_min;
+    *lam_max = h->lam_max;
+    *g2 = h->G2;
+    *engine = h->engine;
+}
+
+}  // namespace duq
 
 extern "C" int duq_get_trace(duq_handle* h, double* out, int32_t max_records, int32_t* n_records) {
     if (!h || !out || max_records < 0) return fail(DUQ_EINVAL, "bad trace arguments");

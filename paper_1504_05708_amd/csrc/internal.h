@@ -40,7 +40,9 @@ struct DevParams {
     int Kd_nonneg;     // project multipliers onto R^p_+
     int has_x0;
     int has_lam0;
-    int resume;        // continue from the state left by a previous launch
+    int resume;        // continue from the state left by a previous launch:
+                       // 1 recomputing the warm start's products (precision
+                       // switch), 2 keeping the stored ones (time slicing)
     int phase1;        // first precision phase: no last-iterate solve, stall exit
     int stall_iters;   // phase 1 ends after this many iterations without progress
     int pad2;
@@ -108,6 +110,25 @@ struct BatchResultDev {
     long long gt_rows;
     double F, LB, feas;
     double lam_min, lam_max, G2;
+};
+
+// One active request of the serving loop: where its data, outputs and
+// persistent workspace live, and the constants found in its first slice.
+struct ServeInst {
+    const void* Q;
+    const void* G;
+    const double* q;
+    const double* g;
+    const double* lb;
+    const double* ub;
+    double* x;
+    double* lam;
+    char* slot;          // workspace carved by batch_carve(n, p, k)
+    int n, p, k;         // k: Krylov steps (0 when the constants are given)
+    int resume;          // 1: continue from the state in `slot`
+    int given;           // 1: lam_min, lam_max, g2 below are to be used
+    int pad;
+    double lam_min, lam_max, g2;
 };
 
 // Workspace of the Lanczos constant estimate.

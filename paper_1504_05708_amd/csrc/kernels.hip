@@ -64,10 +64,10 @@ __global__ void __launch_bounds__(512) lanczos_kernel(DevProblem<T> P, LanczosWo
     s.run();
 }
 
-template <typename T, typename Acc, bool SHORT>
+template <typename T, typename Acc, bool SHORT, bool SERVE>
 __global__ void __launch_bounds__(256, 3) dfom_batch_kernel(BatchArgs<T> a) {
     extern __shared__ __align__(16) double lds[];
-    batch_solve<T, Acc, SHORT>(a, lds);
+    batch_solve<T, Acc, SHORT, SERVE>(a, lds);
 }
 
 size_t batch_lds_bytes(int n_max, int p_max, int k) {
@@ -77,16 +77,23 @@ size_t batch_lds_bytes(int n_max, int p_max, int k) {
 
 long long batch_slot_bytes_host(int n_max, int p_max, int k) { return batch_slot_bytes(n_max, p_max, k); }
 
-static const void* batch_fn(int dtype, int n_max) {
+template <bool SERVE>
+static const void* batch_fn_t(int dtype, bool sh) {
     if (dtype == 0)
-        return short_rows<double>(n_max) ? reinterpret_cast<const void*>(&dfom_batch_kernel<double, double, true>)
-                                         : reinterpret_cast<const void*>(&dfom_batch_kernel<double, double, false>);
-    return short_rows<float>(n_max) ? reinterpret_cast<const void*>(&dfom_batch_kernel<float, double, true>)
-                                    : reinterpret_cast<const void*>(&dfom_batch_kernel<float, double, false>);
+        return sh ? reinterpret_cast<const void*>(&dfom_batch_kernel<double, double, true, SERVE>)
+                  : reinterpret_cast<const void*>(&dfom_batch_kernel<double, double, false, SERVE>);
+    return sh ? reinterpret_cast<const void*>(&dfom_batch_kernel<float, double, true, SERVE>)
+              : reinterpret_cast<const void*>(&dfom_batch_kernel<float, double, false, SERVE>);
 }
 
-hipError_t batch_occupancy(int dtype, int n_max, size_t shmem, int* blocks_per_cu) {
-    const void* f = batch_fn(dtype, n_max);
+static const void* batch_fn(int dtype, bool short_class, bool serve) {
+    return serve ? batch_fn_t<true>(dtype, short_class) : batch_fn_t<false>(dtype, short_class);
+}
+
+bool batch_short_class(int dtype, int n) { return dtype == 0 ? short_rows<double>(n) : short_rows<float>(n); }
+
+hipError_t batch_occupancy(int dtype, bool short_class, bool serve, size_t shmem, int* blocks_per_cu) {
+    const void* f = batch_fn(dtype, short_class, serve);
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, 256, shmem);
@@ -180,9 +187,10 @@ hipError_t launch_count_nonfinite(int dtype, const void* a, long len, unsigned* 
     return hipGetLastError();
 }
 
-hipError_t launch_batch(int dtype, int nblocks, size_t shmem, hipStream_t stream, const BatchLaunch& b) {
+hipError_t launch_batch(int dtype, bool short_class, int nblocks, size_t shmem, hipStream_t stream,
+                        const BatchLaunch& b) {
     LaunchCfg cfg{nblocks, 256, shmem, false, stream};
-    const void* f = batch_fn(dtype, b.n_max);
+    const void* f = batch_fn(dtype, short_class, b.inst != nullptr);
     if (dtype == 0) {
         BatchArgs<double> a;
         fill_batch_args(a, b);

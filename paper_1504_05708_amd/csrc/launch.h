@@ -45,6 +45,8 @@ struct BatchLaunch {
     double* X;
     double* Lam;
     void* res;
+    const ServeInst* inst;
+    int slice;
     DevParams base;
     int max_inner, lanczos_k, lanczos_alloc;
     double safety;
@@ -64,14 +66,19 @@ inline void fill_batch_args(A& a, const BatchLaunch& b) {
     a.q = b.q; a.g = b.g; a.lb = b.lb; a.ub = b.ub;
     a.lam_min = b.lam_min; a.lam_max = b.lam_max; a.g2 = b.g2;
     a.X = b.X; a.Lam = b.Lam; a.res = (decltype(a.res))b.res;
+    a.inst = b.inst; a.slice = b.slice;
     a.base = b.base; a.max_inner = b.max_inner; a.lanczos_k = b.lanczos_k; a.lanczos_alloc = b.lanczos_alloc; a.safety = b.safety;
     a.slots = b.slots; a.slot_bytes = b.slot_bytes; a.n_max = b.n_max; a.p_max = b.p_max; a.queue = b.queue;
 }
 
 size_t batch_lds_bytes(int n_max, int p_max, int k);
 long long batch_slot_bytes_host(int n_max, int p_max, int k);
-hipError_t batch_occupancy(int dtype, int n_max, size_t shmem, int* blocks_per_cu);
-hipError_t launch_batch(int dtype, int nblocks, size_t shmem, hipStream_t stream, const BatchLaunch& b);
+// Instances with short_rows(n) run in the short-row kernel, the others in the
+// long-row kernel; `serve` selects the serving instantiation (b.inst set).
+bool batch_short_class(int dtype, int n);
+hipError_t batch_occupancy(int dtype, bool short_class, bool serve, size_t shmem, int* blocks_per_cu);
+hipError_t launch_batch(int dtype, bool short_class, int nblocks, size_t shmem, hipStream_t stream,
+                        const BatchLaunch& b);
 
 size_t dfom_lds_bytes(int n, int p, int nblocks);
 size_t lanczos_lds_bytes(int n, int p, int nblocks, int k);

@@ -30,8 +30,11 @@ TRACE_SCALARS = 16
 
 BATCH_UNEVEN, BATCH_SHARED = 0, 1
 
+SERVE_BATCH_NMAX = 1536
+
 EXPORTS = ["duq_default_options", "duq_setup", "duq_solve", "duq_get_trace", "duq_get_constants",
-           "duq_destroy", "duq_last_error", "duq_strerror", "duq_solve_batch"]
+           "duq_destroy", "duq_last_error", "duq_strerror", "duq_solve_batch", "duq_server_create",
+           "duq_register_shared", "duq_submit", "duq_poll", "duq_server_destroy"]
 
 
 class DuqProblem(Structure):
@@ -47,7 +50,7 @@ class DuqOptions(Structure):
                 ("trace_outer", c_int32), ("eps_out", c_double), ("eps_in", c_double),
                 ("rho", c_double), ("lam_min", c_double), ("lam_max", c_double),
                 ("G_norm2", c_double), ("safety", c_double), ("switch_factor", c_double),
-                ("switch_stall", c_int32), ("reserved", c_int32 * 7)]
+                ("switch_stall", c_int32), ("serve_slice", c_int32), ("reserved", c_int32 * 6)]
 
 
 class DuqResult(Structure):
@@ -68,6 +71,10 @@ class DuqBatch(Structure):
                 ("voff", c_void_p), ("coff", c_void_p), ("Q", c_void_p), ("G", c_void_p),
                 ("q", c_void_p), ("g", c_void_p), ("lb", c_void_p), ("ub", c_void_p),
                 ("lam_min", c_void_p), ("lam_max", c_void_p), ("G_norm2", c_void_p)]
+
+
+class DuqRequest(Structure):
+    _fields_ = [("shared_id", c_int32), ("reserved", c_int32), ("prob", DuqProblem)]
 
 
 class DuqError(RuntimeError):
@@ -106,6 +113,16 @@ def lib() -> ctypes.CDLL:
     L.duq_solve_batch.argtypes = [POINTER(DuqBatch), POINTER(DuqOptions), c_void_p, c_void_p, c_void_p,
                                   POINTER(DuqResult)]
     L.duq_solve_batch.restype = c_int32
+    L.duq_server_create.argtypes = [ctypes.c_size_t, POINTER(DuqOptions), POINTER(c_void_p)]
+    L.duq_server_create.restype = c_int32
+    L.duq_register_shared.argtypes = [c_void_p, POINTER(DuqProblem), POINTER(c_int32)]
+    L.duq_register_shared.restype = c_int32
+    L.duq_submit.argtypes = [c_void_p, POINTER(DuqRequest), POINTER(ctypes.c_uint64)]
+    L.duq_submit.restype = c_int32
+    L.duq_poll.argtypes = [c_void_p, ctypes.c_uint64, c_void_p, c_void_p, POINTER(DuqResult)]
+    L.duq_poll.restype = c_int32
+    L.duq_server_destroy.argtypes = [c_void_p]
+    L.duq_server_destroy.restype = None
     _lib = L
     return L
 
@@ -287,3 +304,102 @@ def _run_batch(b, B, nx, nl, check, opts):
     if check and rc not in (DUQ_OK, DUQ_EMAXITER):
         raise DuqError(rc, last_error())
     return X[:nx], Lam[:nl], [r.as_dict() for r in res]
+
+
+class Server:
+    """Serving loop (duq_server_*): submit QPs, poll for their results.
+
+    Requests are host NumPy data.  Own problems are (Q, q, G, g, lb, ub);
+    requests against a registered system (register_shared) give q and g."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, **opts):
+        self.opts = default_options(**opts)
+        s = c_void_p()
+        rc = lib().duq_server_create(hbm_budget_bytes, ctypes.byref(self.opts), ctypes.byref(s))
+        if rc != DUQ_OK:
+            raise DuqError(rc, last_error())
+        self._s = s
+        self._sizes = {}     # ticket -> (n, p)
+        self._shared = {}    # id -> (n, p)
+
+    @staticmethod
+    def _problem(Q, q, G, g, lb, ub):
+        Q = np.ascontiguousarray(Q)
+        dt = {np.dtype(np.float64): F64, np.dtype(np.float32): F32}[Q.dtype]
+        n = int(Q.shape[0])
+        G = np.ascontiguousarray(G, dtype=Q.dtype).reshape(-1, n)
+        p = int(G.shape[0])
+        vecs = [None if v is None else np.ascontiguousarray(v, dtype=np.float64) for v in (q, g, lb, ub)]
+        keep = [Q, G] + vecs
+        prob = DuqProblem(n, p, dt, HOST, _ptr(Q), _ptr(G) if p else None, _ptr(vecs[0]),
+                          _ptr(vecs[1]) if p else None, _ptr(vecs[2]), _ptr(vecs[3]))
+        return prob, keep, n, p
+
+    def register_shared(self, Q, G, lb, ub) -> int:
+        prob, keep, n, p = self._problem(Q, None, G, None, lb, ub)
+        sid = c_int32()
+        rc = lib().duq_register_shared(self._s, ctypes.byref(prob), ctypes.byref(sid))
+        if rc != DUQ_OK:
+            raise DuqError(rc, last_error())
+        self._shared[sid.value] = (n, p)
+        return sid.value
+
+    def submit(self, Q=None, q=None, G=None, g=None, lb=None, ub=None, shared_id: int = -1) -> int:
+        if shared_id >= 0:
+            qa = np.ascontiguousarray(q, dtype=np.float64)
+            ga = np.ascontiguousarray(g, dtype=np.float64)
+            n, p = self._shared.get(shared_id, (qa.size, ga.size))   # the library checks the id
+            keep = [qa, ga]
+            prob = DuqProblem(n, p, F64, HOST, None, None, _ptr(qa), _ptr(ga) if p else None, None, None)
+        else:
+            prob, keep, n, p = self._problem(Q, q, G, g, lb, ub)
+        req = DuqRequest(shared_id, 0, prob)
+        t = ctypes.c_uint64()
+        rc = lib().duq_submit(self._s, ctypes.byref(req), ctypes.byref(t))
+        del keep
+        if rc != DUQ_OK:
+            raise DuqError(rc, last_error())
+        self._sizes[t.value] = (n, p)
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending; else (status, x, lam, result dict)."""
+        n, p = self._sizes.get(ticket, (0, 0))
+        x = np.empty(max(n, 1))
+        lam = np.empty(max(p, 1))
+        res = DuqResult()
+        rc = lib().duq_poll(self._s, ticket, _ptr(x), _ptr(lam), ctypes.byref(res))
+        if rc == DUQ_EAGAIN:
+            return None
+        if rc == DUQ_ENOTFOUND:
+            raise DuqError(rc, last_error())
+        self._sizes.pop(ticket, None)
+        return rc, x[:n], lam[:p], res.as_dict()
+
+    def wait(self, ticket: int, timeout: float = 60.0, interval: float = 1e-4):
+        import time
+        t0 = time.perf_counter()
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.perf_counter() - t0 > timeout:
+                raise TimeoutError(f"ticket {ticket} not finished after {timeout} s")
+            time.sleep(interval)
+
+    def close(self):
+        if getattr(self, "_s", None):
+            lib().duq_server_destroy(self._s)
+            self._s = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -85,6 +85,18 @@ def random_dense_qp(n: int, p: int, seed=0, reg: float = 0.1,
                    seed=seed if not isinstance(seed, np.random.Generator) else None))
 
 
+def fresh_linear_terms(G: np.ndarray, seed, s_lo: float = 0.1, s_hi: float = 1.0):
+    """New (q, g) for fixed Q, G, drawn like random_dense_qp: q ~ N(0, I),
+    g = -(G x0) - s with x0 ~ U(-1/2, 1/2)^n, s ~ U(s_lo, s_hi)^p (x0 strictly
+    feasible)."""
+    rng = _rng(seed)
+    p, n = G.shape
+    q = rng.standard_normal(n)
+    x0 = rng.uniform(-0.5, 0.5, n)
+    s = rng.uniform(s_lo, s_hi, p)
+    return q, -(G @ x0) - s
+
+
 def config0() -> QP:
     """Small dense QP: n=50, p=25, reg 0.1, seed 0."""
     return random_dense_qp(50, 25, seed=0, reg=0.1)

@@ -30,13 +30,19 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_binding_covers_header():
-    assert set(duq.EXPORTS) <= set(declared_functions())
+    assert set(duq.EXPORTS) == set(declared_functions())
+
+
+def test_serve_threshold_matches_header():
+    text = open(os.path.join(ROOT, "include", "duq.h")).read()
+    m = re.search(r"#define DUQ_SERVE_BATCH_NMAX (\d+)", text)
+    assert m and int(m.group(1)) == duq.SERVE_BATCH_NMAX
 
 
 def test_default_options_and_strerror():
     o = duq.default_options()
     assert o.method == duq.DFGM and o.output == duq.LAST and o.eps_out == 1e-4 and o.eps_in == 1e-6
-    assert o.safety == 1.02 and o.max_outer > 0
+    assert o.safety == 1.02 and o.max_outer > 0 and o.serve_slice == 16
     assert duq.lib().duq_strerror(duq.DUQ_EINVAL) == b"invalid argument"
 
 
@@ -49,7 +55,7 @@ def test_struct_layout_matches_header(tmp_path):
     if cc is None:
         pytest.skip("no host C compiler")
     structs = {"duq_problem": duq.DuqProblem, "duq_options": duq.DuqOptions,
-               "duq_result": duq.DuqResult, "duq_batch": duq.DuqBatch}
+               "duq_result": duq.DuqResult, "duq_batch": duq.DuqBatch, "duq_request": duq.DuqRequest}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "duq.h"', 'int main(void){']
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')

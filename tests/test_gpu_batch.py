@@ -62,9 +62,11 @@ def test_uneven_batch_estimated_constants_accuracy():
 
 def test_alone_equals_in_the_mix_bitwise():
     print("[case] alone vs mix", flush=True)
-    ub = gen.uneven_batch(B=12, seed=33, n_lo=20, n_hi=120, dtype=np.float64)
+    # sizes on both sides of the short/long-row split (n = 256 in FP64)
+    ub = gen.uneven_batch(B=12, seed=33, n_lo=20, n_hi=400, dtype=np.float64)
+    assert ub.n.min() <= 256 < ub.n.max()
     X, Lam, res = duq.solve_batch_uneven(ub, method=duq.DGM, eps_out=1e-4, eps_in=1e-6, max_outer=50000)
-    for i in (0, 5, 11):
+    for i in sorted({int(np.argmin(ub.n)), int(np.argmax(ub.n)), 5}):
         one = gen.UnevenBatch(ub.n[i:i + 1], ub.p[i:i + 1],
                               ub.Q[ub.qoff[i]:ub.qoff[i] + ub.n[i] ** 2],
                               ub.G[ub.goff[i]:ub.goff[i] + ub.p[i] * ub.n[i]],
