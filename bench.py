@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFS = 78.6
 METRIC = "QP solves/s at 1e-4 subopt+feas, batched vs plain; HBM GB/s; p50/p99 latency"
 
 
@@ -52,6 +53,8 @@ def parse():
                     help="single large QP (default), uneven batch, or shared-Hessian MPC batch")
     ap.add_argument("--batch", type=int, default=None, help="instances of a batch workload")
     ap.add_argument("--plain-sample", type=int, default=48)
+    ap.add_argument("--batch-engine", choices=["auto", "block", "tile"], default="auto",
+                    help="batch kernel: tiles of 16 on MFMA (shared batches) or one workgroup per instance")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: Poisson arrivals per second")
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
     ap.add_argument("--large-frac", type=float, default=0.01, help="serve: share of n=4096 requests")
@@ -292,7 +295,8 @@ def bench_batch(a):
     method = duq.DFGM if a.method == "dfgm" else duq.DGM
     eps_in = a.eps_in if a.eps_in is not None else (1e-8 if method == duq.DFGM else 1e-6)
     opts = dict(method=method, output=duq.LAST if a.output == "last" else duq.AVG, eps_out=a.eps_out,
-                eps_in=eps_in, rho=a.rho, max_outer=200000)
+                eps_in=eps_in, rho=a.rho, max_outer=200000,
+                engine={"auto": duq.ENGINE_AUTO, "block": duq.ENGINE_BLOCK, "tile": duq.ENGINE_TILE}[a.batch_engine])
     npdt = np.float32 if a.precision == "f32" else np.float64
     s_bytes = 4 if npdt == np.float32 else 8
     cuda = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()
@@ -306,8 +310,8 @@ def bench_batch(a):
                               cuda(ub.ub), ub.qoff, ub.goff, ub.voff, ub.coff)
         ns, ps = ub.n.astype(np.int64), ub.p.astype(np.int64)
 
-        def run_batch():
-            return duq.solve_batch_uneven(dev, **opts)
+        def run_batch(consts=None, device_out=True):
+            return duq.solve_batch_uneven(dev, device_out=device_out, **opts)
 
         def plain_one(i, c):
             n, p = int(ns[i]), int(ps[i])
@@ -315,8 +319,8 @@ def bench_batch(a):
             Gi = dev.G[ub.goff[i]:ub.goff[i] + p * n].view(p, n)
             sl = slice(int(ub.voff[i]), int(ub.voff[i]) + n)
             sc = slice(int(ub.coff[i]), int(ub.coff[i]) + p)
-            with duq.Solver(Qi, dev.q[sl], Gi, dev.g[sc], dev.lb[sl], dev.ub[sl], engine=duq.ENGINE_BLOCK,
-                            lam_min=c["lam_min"], lam_max=c["lam_max"], G_norm2=c["G_norm2"], **opts) as sv:
+            with duq.Solver(Qi, dev.q[sl], Gi, dev.g[sc], dev.lb[sl], dev.ub[sl], lam_min=c["lam_min"],
+                            lam_max=c["lam_max"], G_norm2=c["G_norm2"], **dict(opts, engine=duq.ENGINE_BLOCK)) as sv:
                 return sv.solve()[2]
 
         def instance(i):
@@ -333,13 +337,14 @@ def bench_batch(a):
         ns = np.full(B, sysm.n, np.int64)
         ps = np.full(B, sysm.p, np.int64)
 
-        def run_batch():
-            X, L, r = duq.solve_batch_shared(Hd, Gd, lbd, ubd, Qld, Gld, **opts)
-            return X.ravel(), L.ravel(), r
+        def run_batch(consts=None, device_out=True):
+            # the constants belong to the shared system: estimated once, then given
+            return duq.solve_batch_shared(Hd, Gd, lbd, ubd, Qld, Gld, constants=consts, device_out=device_out,
+                                          **opts)
 
         def plain_one(i, c):
-            with duq.Solver(Hd, Qld[i], Gd, Gld[i], lbd, ubd, engine=duq.ENGINE_BLOCK, lam_min=c["lam_min"],
-                            lam_max=c["lam_max"], G_norm2=c["G_norm2"], **opts) as sv:
+            with duq.Solver(Hd, Qld[i], Gd, Gld[i], lbd, ubd, lam_min=c["lam_min"], lam_max=c["lam_max"],
+                            G_norm2=c["G_norm2"], **dict(opts, engine=duq.ENGINE_BLOCK)) as sv:
                 return sv.solve()[2]
 
         def instance(i):
@@ -348,17 +353,25 @@ def bench_batch(a):
         desc = (f"shared-Hessian batch of {B} condensed MPC QPs (nx=12, nu=4, N=30: n=120, p=720, "
                 f"|u|<=1, |x_k|<=5), x0~U(-1,1)^12, seed 2/20; H,G stored {a.precision}")
     torch.cuda.synchronize()
+    # end-to-end call: constants estimated, outputs copied to the host
+    t = time.perf_counter()
+    _, _, res0 = run_batch(None, device_out=False)
+    e2e_s = time.perf_counter() - t
+    sys_consts = None
+    if a.workload == "mpc":
+        sys_consts = (res0[0]["lam_min"], res0[0]["lam_max"], res0[0]["G_norm2"])
     for _ in range(a.warmup):
-        run_batch()
+        run_batch(sys_consts)
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(a.steps):
-        X, L, res = run_batch()
+        X, L, res = run_batch(sys_consts)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t
     kern_ms = res[0]["time_ms"]
     ok = sum(r["status"] == duq.DUQ_OK for r in res)
     value = B * a.steps / wall
+    engine = res[0]["engine"]
     # algorithmic matrix bytes of one launch, per instance: every Q product
     # (inner steps + warm start), the G product of each outer iteration and of
     # the extra last-iterate solve, the rows read by G^T mu, and the Lanczos
@@ -371,6 +384,25 @@ def bench_batch(a):
         lz = (k * n * n + 2 * k * p * n) if a.workload == "uneven" else 0.0
         alg += ((r["inner_iters"] + 1) * n * n + (r["outer_iters"] + extra) * p * n + r["gt_rows"] * n + lz) * s_bytes
     achieved = alg / (kern_ms * 1e-3) / 1e9
+    if engine == duq.ENGINE_TILE:
+        # matrix-core kernel: algorithmic FP64 flops of the Q, G and G^T products
+        flops = 0.0
+        for i, r in enumerate(res):
+            n, p = float(ns[i]), float(ps[i])
+            n_gt = r["gt_rows"] / p if p else 0.0
+            flops += 2.0 * n * n * (r["inner_iters"] + 1) + 2.0 * 2.0 * p * n * n_gt
+        tf = flops / (kern_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(tf, 2), "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
+                "frac": round(tf / FP64_MFMA_PEAK_TFS, 4), "traffic": None, "kernel": "dfom_tile_kernel",
+                "alg_flops_per_launch": flops, "launch_ms": round(kern_ms, 3),
+                "note": "FP64 MFMA 16x16x4; Q held in LDS, G through L2; flops of masked (finished) "
+                        "columns and of padding are not counted"}
+    else:
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "dfom_batch_kernel", "alg_bytes_per_launch": alg, "launch_ms": round(kern_ms, 3),
+                "note": "per-instance matrices are re-read from the on-die caches (MALL/L2); "
+                        "the unique HBM bytes are read once per launch"}
     # plain per-QP solver on a sample spread over the batch
     S = min(a.plain_sample, B)
     idx = np.linspace(0, B - 1, S).astype(int)
@@ -394,15 +426,16 @@ def bench_batch(a):
         "warmup": a.warmup, "ms_per_step": round(1e3 * wall / a.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc + f"; {a.method.upper()}-{a.output} eps_out={a.eps_out:g} eps_in={eps_in:g}; "
-                               f"one persistent launch per batch, workgroups take instances from a device queue",
+                               f"one persistent launch per batch ({'MFMA tiles of 16 instances' if engine == duq.ENGINE_TILE else 'one workgroup per instance'}); "
+                               f"inputs and outputs in HBM"
+                               + ("; system constants estimated once (end_to_end_solves_per_s includes the "
+                                  "estimate and the host copy of the outputs)" if a.workload == "mpc" else ""),
                    "B": B, "storage": a.precision},
         "plain_solves_per_s": round(plain_rate, 3),
         "speedup_vs_plain": round(value / plain_rate, 1),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "dfom_batch_kernel", "alg_bytes_per_launch": alg, "launch_ms": round(kern_ms, 3),
-                     "note": "per-instance matrices are re-read from the on-die caches (MALL/L2); "
-                             "the unique HBM bytes are read once per launch"},
+        "roofline": roof,
+        "end_to_end_solves_per_s": round(B / e2e_s, 2),
+        "kernel_solves_per_s": round(B / (kern_ms * 1e-3), 1),
         "solve": {"instances_ok": ok, "max_cert_subopt_rel": cert, "max_feas_abs": feas_rel,
                   "outer_mean": float(np.mean([r["outer_iters"] for r in res])),
                   "inner_mean": float(np.mean([r["inner_iters"] for r in res]))},

@@ -53,7 +53,8 @@ enum { DUQ_CERT = 0, DUQ_FIXED = 1 };                         /* inner stopping 
 enum { DUQ_INNER_AUTO = 0, DUQ_INNER_GM = 1, DUQ_INNER_FGM = 2,
        DUQ_INNER_FGM_SIGMA = 3 };                             /* inner FOM variant, Sec. 2.1 */
 enum { DUQ_ACC_F64 = 0, DUQ_ACC_F32 = 1 };                    /* product accumulation */
-enum { DUQ_ENGINE_AUTO = 0, DUQ_ENGINE_BLOCK = 1, DUQ_ENGINE_GRID = 2 };
+enum { DUQ_ENGINE_AUTO = 0, DUQ_ENGINE_BLOCK = 1, DUQ_ENGINE_GRID = 2,
+       DUQ_ENGINE_TILE = 3 };   /* TILE: shared batches only, see duq_solve_batch */
 
 /* ---- problem data (Sec. 2, eq. original_primal) ------------------------- */
 typedef struct duq_problem {
@@ -97,7 +98,9 @@ typedef struct duq_options {
     double switch_factor;   /* DUQ_ACC_F32: switch to F64 at switch_factor*eps_out */
     int32_t switch_stall;   /* ... or after this many non-improving iterations   */
     int32_t serve_slice;    /* serving loop: outer iterations per round (0 = 16)  */
-    int32_t reserved[6];
+    int32_t out_memspace;   /* duq_solve_batch: X_out / Lam_out are DUQ_HOST
+                               (default) or DUQ_DEVICE buffers                  */
+    int32_t reserved[5];
 } duq_options;
 
 /* ---- per-solve result --------------------------------------------------- *
@@ -183,9 +186,19 @@ typedef struct duq_batch {
 } duq_batch;
 
 /* Solve every instance of the batch in one persistent launch: workgroups take
- * instances from a device work queue (largest first) and run Algorithm DFOM on
- * each with the same options (engine is ignored; max_outer, eps and rho apply
- * per instance; tracing is not available).  X_out (sum n_i, or B x n) and
+ * work from a device queue and run Algorithm DFOM on each instance with the
+ * same options (max_outer, eps and rho apply per instance; tracing is not
+ * available).  opts.engine selects the kernel:
+ *   DUQ_ENGINE_AUTO   SHARED with rho = 0 and n <= 128: DUQ_ENGINE_TILE;
+ *                     otherwise DUQ_ENGINE_BLOCK;
+ *   DUQ_ENGINE_BLOCK  one workgroup per instance (largest first), products
+ *                     as GEMVs (DUQ_ENGINE_GRID is taken as BLOCK here);
+ *   DUQ_ENGINE_TILE   SHARED only: one workgroup per 16 instances in
+ *                     lockstep, Q X, G U and G^T M as FP64 MFMA GEMMs with Q
+ *                     held in LDS (rho = 0, n <= 128).
+ * Both accumulate in FP64 and give each instance the iterates it has alone.
+ * With opts.out_memspace = DUQ_DEVICE the kernels write X_out / Lam_out
+ * (device buffers) directly and nothing crosses PCIe but `res`.  X_out (sum n_i, or B x n) and
  * Lam_out (sum p_i, or B x p) are host buffers laid out like q and g; res has
  * B entries (time_ms is the batch's device time).  Returns DUQ_OK when every
  * instance passed its outer test, DUQ_EMAXITER / DUQ_ENUMERIC when one did

@@ -18,6 +18,9 @@ using namespace duq;
 namespace duq {
 int set_error(int code, const std::string& msg);
 int device_cus();
+void handle_params(duq_handle* h, DevParams* par);
+int derive_params(int p, double lam_min, double lam_max, double g2, double D_U, const duq_options& o,
+                  DevParams* par);
 }
 
 namespace {
@@ -46,6 +49,133 @@ bool all_finite(const T* a, long long len) {
 
 }  // namespace
 
+namespace {
+
+int to_status(int s) { return s == 0 ? DUQ_OK : s == 2 ? DUQ_ENUMERIC : s == 4 ? DUQ_EINVAL : DUQ_EMAXITER; }
+
+// Shared-Hessian batch on the MFMA tile kernel: constants and derived
+// parameters from the single-QP setup of the shared data (Lanczos estimate
+// unless given), one persistent launch over tiles of 16 instances.
+int solve_shared_tiles(const duq_batch* b, const duq_options* o, hipStream_t s, const void* dQ, const void* dG,
+                       const double* dq, const double* dg, const double* dlb, const double* dub, int bpc,
+                       double* X_out, double* Lam_out, duq_result* res) {
+    const int B = b->B, n = b->n_shared, p = b->p_shared;
+    duq_problem pr{n, p, b->dtype, DUQ_DEVICE, dQ, p ? dG : nullptr, dq, p ? dg : nullptr, dlb, dub};
+    duq_options oo = *o;
+    oo.trace_outer = 0;
+    oo.engine = DUQ_ENGINE_BLOCK;
+    const bool have_c = b->lam_min && b->lam_max && b->G_norm2;
+    oo.lam_min = have_c ? b->lam_min[0] : 0.0;
+    oo.lam_max = have_c ? b->lam_max[0] : 0.0;
+    oo.G_norm2 = have_c ? b->G_norm2[0] : 0.0;
+    TileLaunch t{};
+    if (have_c && oo.lam_min > 0.0 && oo.lam_max > 0.0 && (p == 0 || oo.G_norm2 > 0.0)) {
+        // given constants: derive the parameters here (D_U from the box)
+        std::vector<double> lo(n), hi(n);
+        BTRY(hipMemcpyAsync(lo.data(), dlb, 8 * (size_t)n, hipMemcpyDeviceToHost, s));
+        BTRY(hipMemcpyAsync(hi.data(), dub, 8 * (size_t)n, hipMemcpyDeviceToHost, s));
+        BTRY(hipStreamSynchronize(s));
+        double du2 = 0.0;
+        for (int i = 0; i < n; ++i) {
+            if (!std::isfinite(lo[i]) || !std::isfinite(hi[i]) || lo[i] > hi[i])
+                return set_error(DUQ_EINVAL, "box must be finite with lb <= ub");
+            du2 += (hi[i] - lo[i]) * (hi[i] - lo[i]);
+        }
+        int rc = derive_params(p, oo.lam_min, oo.lam_max, p ? oo.G_norm2 : 0.0, std::sqrt(du2), oo, &t.par);
+        if (rc) return rc;
+        t.lam_min = oo.lam_min;
+        t.lam_max = oo.lam_max;
+        t.g2 = p ? oo.G_norm2 : 0.0;
+    } else {
+        // Lanczos estimate and derivation through the single-QP setup
+        duq_handle* h = nullptr;
+        int rc = duq_setup(&pr, &oo, s, &h);
+        if (rc) return rc;
+        handle_params(h, &t.par);
+        duq_get_constants(h, &t.lam_min, &t.lam_max, &t.g2, nullptr, nullptr, nullptr);
+        duq_destroy(h);
+    }
+    const int pp = std::max(p, 1);
+    DevBuf ws;
+    size_t off = 0;
+    auto plan = [&](size_t bytes) { size_t r = off; off += ((bytes + 255) / 256) * 256; return r; };
+    const bool dev_out = o->out_memspace == DUQ_DEVICE;
+    const size_t o_X = plan(dev_out ? 0 : 8 * (size_t)B * n);
+    const size_t o_L = plan(dev_out ? 0 : 8 * (size_t)B * pp);
+    const size_t o_res = plan(sizeof(BatchResultDev) * (size_t)B);
+    const size_t o_dual = plan(8 * 3 * (size_t)B * pp);
+    const size_t o_prim = plan(8 * 2 * (size_t)B * n);
+    const size_t o_q = plan(256);
+    BTRY(hipMalloc(&ws.p, off));
+    char* w = (char*)ws.p;
+    BTRY(hipMemsetAsync(w + o_q, 0, 256, s));
+    t.B = B;
+    t.n = n;
+    t.p = p;
+    t.Q = dQ;
+    t.G = dG;
+    t.q = dq;
+    t.g = dg;
+    t.lb = dlb;
+    t.ub = dub;
+    t.X = dev_out ? X_out : (double*)(w + o_X);
+    t.Lam = dev_out ? Lam_out : (double*)(w + o_L);
+    t.res = w + o_res;
+    t.dual = (double*)(w + o_dual);
+    t.prim = (double*)(w + o_prim);
+    t.queue = (unsigned*)(w + o_q);
+    const int tiles = (B + 15) / 16;
+    const int nblocks = std::max(1, std::min(tiles, device_cus() * bpc));
+    hipEvent_t e0, e1;
+    BTRY(hipEventCreate(&e0));
+    BTRY(hipEventCreate(&e1));
+    BTRY(hipEventRecord(e0, s));
+    hipError_t le = launch_tile(b->dtype, nblocks, tile_lds_bytes(n), s, t);
+    BTRY(hipEventRecord(e1, s));
+    std::vector<BatchResultDev> rd(B);
+    if (le == hipSuccess) {
+        BTRY(hipMemcpyAsync(rd.data(), w + o_res, sizeof(BatchResultDev) * B, hipMemcpyDeviceToHost, s));
+        if (X_out && !dev_out) BTRY(hipMemcpyAsync(X_out, w + o_X, 8 * (size_t)B * n, hipMemcpyDeviceToHost, s));
+        if (Lam_out && p > 0 && !dev_out)
+            BTRY(hipMemcpyAsync(Lam_out, w + o_L, 8 * (size_t)B * p, hipMemcpyDeviceToHost, s));
+    }
+    hipError_t se = hipStreamSynchronize(s);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    BTRY(le);
+    BTRY(se);
+    int code = DUQ_OK;
+    for (int i = 0; i < B; ++i) {
+        const BatchResultDev& r = rd[i];
+        const int st = to_status(r.status);
+        if (st != DUQ_OK && code == DUQ_OK) code = st;
+        if (res) {
+            duq_result& q = res[i];
+            std::memset(&q, 0, sizeof(q));
+            q.status = st;
+            q.outer_iters = r.outer;
+            q.inner_iters = r.inner;
+            q.gt_rows = r.gt_rows;
+            q.f = r.F;
+            q.lb_dual = r.LB;
+            q.gap = r.F - r.LB;
+            q.feas = r.feas;
+            q.time_ms = ms;
+            q.f64_outer_iters = r.outer;
+            q.engine = DUQ_ENGINE_TILE;
+            q.lam_min = r.lam_min;
+            q.lam_max = r.lam_max;
+            q.G_norm2 = r.G2;
+        }
+    }
+    if (code != DUQ_OK) set_error(code, "at least one instance did not pass its outer test");
+    return code;
+}
+
+}  // namespace
+
 extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* stream, double* X_out,
                                double* Lam_out, duq_result* res) {
     if (!b || !o) return set_error(DUQ_EINVAL, "null batch or options");
@@ -60,6 +190,9 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
     if (o->output != DUQ_LAST && o->output != DUQ_AVG) return set_error(DUQ_EINVAL, "bad output");
     if (o->inner_variant < 0 || o->inner_variant > 3) return set_error(DUQ_EINVAL, "bad inner_variant");
     if (o->accumulate != DUQ_ACC_F64) return set_error(DUQ_EINVAL, "batches accumulate in FP64");
+    if (o->out_memspace != DUQ_HOST && o->out_memspace != DUQ_DEVICE) return set_error(DUQ_EINVAL, "bad out_memspace");
+    if (o->out_memspace == DUQ_DEVICE && (!X_out || !Lam_out))
+        return set_error(DUQ_EINVAL, "device outputs need X_out and Lam_out");
     if (!b->Q || !b->q || !b->lb || !b->ub) return set_error(DUQ_EINVAL, "null data pointer");
     const bool shared = b->kind == DUQ_BATCH_SHARED;
     const size_t es = b->dtype == DUQ_F64 ? 8 : 4;
@@ -141,6 +274,18 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
         dQ = Qd; dG = Gd; dq = qd; dg = gd; dlb = lbd; dub = ubd;
     }
 
+    // shared-Hessian batches on MFMA tiles (rho = 0, n small enough for Q in LDS)
+    if (shared && o->engine != DUQ_ENGINE_BLOCK && o->engine != DUQ_ENGINE_GRID) {
+        int bpc = 0;
+        const bool fits = o->rho == 0.0 && n_max <= kTileMaxN &&
+                          tile_occupancy(b->dtype, tile_lds_bytes(n_max), &bpc) == hipSuccess && bpc >= 1;
+        if (fits) return solve_shared_tiles(b, o, s, dQ, dG, dq, dg, dlb, dub, bpc, X_out, Lam_out, res);
+        if (o->engine == DUQ_ENGINE_TILE)
+            return set_error(DUQ_EINVAL, "the MFMA tile engine needs rho = 0 and n <= 128 (Q in LDS)");
+        (void)hipGetLastError();
+    }
+    if (o->engine == DUQ_ENGINE_TILE) return set_error(DUQ_EINVAL, "the MFMA tile engine serves shared batches");
+
     // constants: per instance from the caller, or one estimate for a shared batch
     const bool have_c = b->lam_min && b->lam_max && b->G_norm2;
     const int nc = shared ? 1 : B;
@@ -209,8 +354,9 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
     size_t off = 0;
     auto plan = [&](size_t n) { size_t r = off; off += ((n + 255) / 256) * 256; return r; };
     for (Cls& c : cls) c.o_slots = plan((size_t)c.slot * c.nblocks);
-    const size_t o_X = plan(8 * vtot);
-    const size_t o_L = plan(8 * std::max<long long>(ctot, 1));
+    const bool dev_out = o->out_memspace == DUQ_DEVICE;
+    const size_t o_X = plan(dev_out ? 0 : 8 * vtot);
+    const size_t o_L = plan(dev_out ? 0 : 8 * std::max<long long>(ctot, 1));
     const size_t o_res = plan(sizeof(BatchResultDev) * B);
     const size_t o_meta = plan((sizeof(int) * 3 + sizeof(long long) * 4) * B);
     const size_t o_c = plan(8 * 3 * nc);
@@ -260,8 +406,8 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
     L.lam_min = dev_consts ? d_c : nullptr;
     L.lam_max = dev_consts ? d_c + nc : nullptr;
     L.g2 = dev_consts ? d_c + 2 * nc : nullptr;
-    L.X = (double*)(w + o_X);
-    L.Lam = (double*)(w + o_L);
+    L.X = dev_out ? X_out : (double*)(w + o_X);
+    L.Lam = dev_out ? Lam_out : (double*)(w + o_L);
     L.res = w + o_res;
     DevParams par{};
     par.method = o->method;
@@ -316,8 +462,9 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
     std::vector<BatchResultDev> rd(B);
     if (le == hipSuccess) {
         BTRY(hipMemcpyAsync(rd.data(), w + o_res, sizeof(BatchResultDev) * B, hipMemcpyDeviceToHost, s));
-        if (X_out) BTRY(hipMemcpyAsync(X_out, w + o_X, 8 * vtot, hipMemcpyDeviceToHost, s));
-        if (Lam_out && ctot > 0) BTRY(hipMemcpyAsync(Lam_out, w + o_L, 8 * ctot, hipMemcpyDeviceToHost, s));
+        if (X_out && !dev_out) BTRY(hipMemcpyAsync(X_out, w + o_X, 8 * vtot, hipMemcpyDeviceToHost, s));
+        if (Lam_out && ctot > 0 && !dev_out)
+            BTRY(hipMemcpyAsync(Lam_out, w + o_L, 8 * ctot, hipMemcpyDeviceToHost, s));
     }
     hipError_t se = hipStreamSynchronize(s);
     float ms = 0.f;

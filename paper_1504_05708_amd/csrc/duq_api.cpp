@@ -202,6 +202,45 @@ int validate(const duq_problem* pr, const duq_options* o) {
 
 namespace duq {
 int estimate_constants(duq_handle* h, const DeviceInfo& di);
+
+// Kernel parameters from the spectral constants, the box diameter D_U and
+// the options: L_d = ||G||^2/(lam_min + rho ||G||^2) (Sec. 2 eq. Ld), step
+// 1/(2 L_d); L_in = lam_max + rho ||G||^2, sigma_in = lam_min (Sec. 3 Step 1);
+// the inner cap k_in of Sec. 5 (natural log, rounded up) unless max_inner > 0.
+int derive_params(int p, double lam_min, double lam_max, double g2, double D_U, const duq_options& o,
+                  DevParams* par) {
+    const double rho = o.rho;
+    const double denom = lam_min + rho * g2;
+    if (p > 0 && !(denom > 0.0)) return fail(DUQ_EINVAL, "lambda_min(Q) = 0 needs rho > 0 (Sec. 2, Case 2)");
+    *par = DevParams{};
+    const double Ld = p > 0 ? g2 / denom : 0.0;
+    par->alpha = Ld > 0.0 ? 1.0 / (2.0 * Ld) : 0.0;
+    par->L = lam_max + rho * g2;
+    par->sigma = std::max(lam_min, 0.0);
+    const double sqL = std::sqrt(par->L), sqs = std::sqrt(par->sigma);
+    par->beta_in = (sqL - sqs) / (sqL + sqs);
+    int k_in;
+    if (o.max_inner > 0) k_in = o.max_inner;
+    else if (par->sigma > 0.0) {
+        const double arg = par->L * D_U * D_U / o.eps_in;
+        k_in = arg > 1.0 ? (int)std::ceil(std::sqrt(par->L / par->sigma) * std::log(arg)) + 1 : 1;
+    } else {
+        k_in = (int)std::ceil(std::sqrt(2.0 * par->L * D_U * D_U / o.eps_in));
+    }
+    par->k_in_max = std::max(k_in, 1);
+    par->Kd_nonneg = lam_min > 0.0 ? 1 : 0;
+    int v = o.inner_variant;
+    if (v == DUQ_INNER_AUTO) v = par->sigma > 0.0 ? DUQ_INNER_FGM_SIGMA : DUQ_INNER_FGM;
+    par->inner_variant = v;
+    par->method = o.method;
+    par->output = o.output;
+    par->inner_rule = o.inner_rule;
+    par->max_outer = o.max_outer;
+    par->eps_out = o.eps_out;
+    par->eps_in = o.eps_in;
+    par->rho = o.rho;
+    return DUQ_OK;
+}
 }
 
 extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* stream, duq_handle** out) {
@@ -407,30 +446,20 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
             return rc;
         }
     }
-    const double rho = opts->rho;
-    const double denom = h->lam_min + rho * h->G2;
-    if (p > 0 && !(denom > 0.0)) {
+    DevParams dp;
+    rc = derive_params(p, h->lam_min, h->lam_max, h->G2, h->D_U, *opts, &dp);
+    if (rc) {
         duq_destroy(h);
-        return fail(DUQ_EINVAL, "lambda_min(Q) = 0 needs rho > 0 (Sec. 2, Case 2)");
+        return rc;
     }
-    h->Ld = p > 0 ? h->G2 / denom : 0.0;
-    h->alpha = h->Ld > 0.0 ? 1.0 / (2.0 * h->Ld) : 0.0;
-    h->L_in = h->lam_max + rho * h->G2;
-    h->sigma = std::max(h->lam_min, 0.0);
-    const double sqL = std::sqrt(h->L_in), sqs = std::sqrt(h->sigma);
-    h->beta_in = (sqL - sqs) / (sqL + sqs);
-    if (opts->max_inner > 0) h->k_in = opts->max_inner;
-    else if (h->sigma > 0.0) {
-        const double arg = h->L_in * h->D_U * h->D_U / opts->eps_in;
-        h->k_in = arg > 1.0 ? (int)std::ceil(std::sqrt(h->L_in / h->sigma) * std::log(arg)) + 1 : 1;
-    } else {
-        h->k_in = (int)std::ceil(std::sqrt(2.0 * h->L_in * h->D_U * h->D_U / opts->eps_in));
-    }
-    h->k_in = std::max(h->k_in, 1);
-    h->Kd_nonneg = h->lam_min > 0.0 ? 1 : 0;
-    int v = opts->inner_variant;
-    if (v == DUQ_INNER_AUTO) v = h->sigma > 0.0 ? DUQ_INNER_FGM_SIGMA : DUQ_INNER_FGM;
-    h->variant = v;
+    h->Ld = p > 0 ? h->G2 / (h->lam_min + opts->rho * h->G2) : 0.0;
+    h->alpha = dp.alpha;
+    h->L_in = dp.L;
+    h->sigma = dp.sigma;
+    h->beta_in = dp.beta_in;
+    h->k_in = dp.k_in_max;
+    h->Kd_nonneg = dp.Kd_nonneg;
+    h->variant = dp.inner_variant;
     *out = h;
     return DUQ_OK;
 }
@@ -651,6 +680,26 @@ int handle_outputs(duq_handle* h, double* x, double* lam) {
     if (x) HIP_TRY(hipMemcpy(x, h->W.xout, h->n * sizeof(double), hipMemcpyDeviceToHost));
     if (lam && h->p > 0) HIP_TRY(hipMemcpy(lam, h->W.lamp, h->p * sizeof(double), hipMemcpyDeviceToHost));
     return DUQ_OK;
+}
+
+// Derived solver parameters of a handle (what duq_solve passes its kernel).
+void handle_params(duq_handle* h, DevParams* par) {
+    const duq_options& o = h->opts;
+    *par = DevParams{};
+    par->method = o.method;
+    par->output = o.output;
+    par->inner_rule = o.inner_rule;
+    par->inner_variant = h->variant;
+    par->max_outer = o.max_outer;
+    par->k_in_max = h->k_in;
+    par->Kd_nonneg = h->Kd_nonneg;
+    par->eps_out = o.eps_out;
+    par->eps_in = o.eps_in;
+    par->rho = o.rho;
+    par->alpha = h->alpha;
+    par->L = h->L_in;
+    par->sigma = h->sigma;
+    par->beta_in = h->beta_in;
 }
 
 // Constants and engine of a handle, for reporting.

@@ -4,6 +4,7 @@
 
 #include "batch.h"
 #include "dfom_solver.h"
+#include "shared_tile.h"
 #include "lanczos.h"
 #include "launch.h"
 
@@ -120,6 +121,42 @@ static hipError_t launch_fn(const void* kernel, const LaunchCfg& cfg, void** arg
     return hipLaunchKernel(kernel, dim3(cfg.nblocks), dim3(cfg.nthreads), args, shmem, cfg.stream);
 }
 
+
+// Shared-Hessian tiles: four waves, one workgroup per CU (Q fills the LDS).
+template <typename T>
+__global__ void __launch_bounds__(256, 1) dfom_tile_kernel(TileArgs<T> a) {
+    extern __shared__ __align__(16) double lds[];
+    tile_solve<T>(a, lds);
+}
+
+size_t tile_lds_bytes(int n) { return (size_t)tile_lds_doubles(n) * sizeof(double); }
+
+static const void* tile_fn(int dtype) {
+    return dtype == 0 ? reinterpret_cast<const void*>(&dfom_tile_kernel<double>)
+                      : reinterpret_cast<const void*>(&dfom_tile_kernel<float>);
+}
+
+hipError_t tile_occupancy(int dtype, size_t shmem, int* blocks_per_cu) {
+    const void* f = tile_fn(dtype);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, 256, shmem);
+}
+
+hipError_t launch_tile(int dtype, int nblocks, size_t shmem, hipStream_t stream, const TileLaunch& t) {
+    LaunchCfg cfg{nblocks, 256, shmem, false, stream};
+    const void* f = tile_fn(dtype);
+    if (dtype == 0) {
+        TileArgs<double> a;
+        fill_tile_args(a, t);
+        void* args[] = {&a};
+        return launch_fn(f, cfg, args);
+    }
+    TileArgs<float> a;
+    fill_tile_args(a, t);
+    void* args[] = {&a};
+    return launch_fn(f, cfg, args);
+}
 
 size_t dfom_lds_bytes(int n, int p, int nblocks) { return solver_lds_doubles(n, p, nblocks) * sizeof(double); }
 size_t lanczos_lds_bytes(int n, int p, int nblocks, int k) {

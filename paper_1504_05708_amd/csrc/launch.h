@@ -80,6 +80,38 @@ hipError_t batch_occupancy(int dtype, bool short_class, bool serve, size_t shmem
 hipError_t launch_batch(int dtype, bool short_class, int nblocks, size_t shmem, hipStream_t stream,
                         const BatchLaunch& b);
 
+// Shared-Hessian batch on FP64 MFMA tiles of 16 instances (type-erased TileArgs).
+struct TileLaunch {
+    int B, n, p;
+    const void* Q;
+    const void* G;
+    const double *q, *g, *lb, *ub;
+    double* X;
+    double* Lam;
+    void* res;
+    double* dual;
+    double* prim;
+    DevParams par;
+    double lam_min, lam_max, g2;
+    unsigned* queue;
+};
+
+template <typename A>
+inline void fill_tile_args(A& a, const TileLaunch& t) {
+    typedef typename std::remove_const<typename std::remove_pointer<decltype(a.Q)>::type>::type T;
+    a.B = t.B; a.n = t.n; a.p = t.p;
+    a.Q = (const T*)t.Q; a.G = (const T*)t.G;
+    a.q = t.q; a.g = t.g; a.lb = t.lb; a.ub = t.ub;
+    a.X = t.X; a.Lam = t.Lam; a.res = (decltype(a.res))t.res;
+    a.dual = t.dual; a.prim = t.prim; a.par = t.par;
+    a.lam_min = t.lam_min; a.lam_max = t.lam_max; a.g2 = t.g2; a.queue = t.queue;
+}
+
+constexpr int kTileMaxN = 128;   // two row tiles of 16 per wave
+size_t tile_lds_bytes(int n);
+hipError_t tile_occupancy(int dtype, size_t shmem, int* blocks_per_cu);
+hipError_t launch_tile(int dtype, int nblocks, size_t shmem, hipStream_t stream, const TileLaunch& t);
+
 size_t dfom_lds_bytes(int n, int p, int nblocks);
 size_t lanczos_lds_bytes(int n, int p, int nblocks, int k);
 hipError_t dfom_occupancy(int dtype, int acc, int n, int nthreads, size_t shmem, int* blocks_per_cu);

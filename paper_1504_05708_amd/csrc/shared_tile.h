@@ -1,0 +1,597 @@
+// Shared-Hessian batches on the matrix cores.
+//
+// A workgroup of four waves advances a tile of 16 instances that share Q
+// (n x n), G (p x n) and the box, in lockstep.  The products of the tile are
+// dense GEMMs on FP64 MFMA (16x16x4):
+//   Q X      (n x 16)  once per inner step       (Sec. 5.1, inner gradient)
+//   G U      (p x 16)  once per outer iteration  (residual of Sec. 3 Step 2)
+//   G^T M    (n x 16)  once per outer iteration  (linear term q + G^T mu)
+// Q stays in LDS (FP64) for the whole launch; G is read through the caches.
+// Each lane owns the rows 16 (w + 4 j) + l/16 + 4 i (j < 2, i < 4) of column
+// l % 16 -- the FP64 MFMA result layout -- and keeps its rows of its
+// instance's primal vectors in registers.  The multipliers (p per instance)
+// live in device memory and are updated in the epilogue of the G U product.
+//
+// Per column the arithmetic is Algorithm DFOM with inner FOM (rho = 0) as in
+// the single-instance solver: an instance whose inner or outer loop has ended
+// is masked while the others continue, and the MFMA computes every column
+// from that column's data only, so an instance's iterates do not depend on
+// which instances share its tile.
+#pragma once
+#include "device_common.h"
+#include "internal.h"
+
+namespace duq {
+
+constexpr int kTile = 16;       // instances per workgroup
+constexpr int kTileWaves = 4;   // waves per workgroup
+constexpr int kTileK = 12;      // slots of the outer reduction record
+
+typedef double tile_v4d __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct TileArgs {
+    int B, n, p;
+    const T* Q;          // n x n, shared
+    const T* G;          // p x n, shared
+    const double* q;     // B x n
+    const double* g;     // B x p
+    const double* lb;    // n, shared
+    const double* ub;
+    double* X;           // B x n
+    double* Lam;         // B x p
+    BatchResultDev* res; // B
+    double* dual;        // B x 3p: mu, lambda (last step), running sum of theta_j r^j
+    double* prim;        // B x 2n: running sums of theta_j ubar^j and theta_j Q ubar^j
+    DevParams par;       // derived constants (shared by all instances)
+    double lam_min, lam_max, g2;
+    unsigned* queue;
+};
+
+// LDS layout, in doubles: Q (n rows, odd stride), two buffers of the B
+// operand X (kp x 16), the inner reduction (two buffers), the outer one.
+__host__ __device__ inline int tile_ldh(int n) { return n | 1; }
+__host__ __device__ inline int tile_kp(int n) { return (n + 3) & ~3; }
+__host__ __device__ inline long tile_lds_doubles(int n) {
+    return (long)n * tile_ldh(n) + 2L * tile_kp(n) * kTile + 2L * kTileWaves * kTile * 2 +
+           (long)kTileWaves * kTile * kTileK;
+}
+
+template <typename T>
+struct Tile {
+    TileArgs<T> a;
+    double* Hs;
+    double* Xs0;
+    double* Xs1;
+    double* red2;
+    double* redK;
+    int lane, w, col, grp, b;
+    bool valid;
+    // this lane's rows of its column
+    double x[2][4], xp[2][4], qx[2][4], qxp[2][4], c[2][4], lo[2][4], hi[2][4];
+
+    __device__ __forceinline__ int row(int j, int i) const { return 16 * (w + 4 * j) + grp + 4 * i; }
+
+    // Sum K per-lane values over each column (the 16 lanes of a column across
+    // the four waves), in a fixed order; every lane gets its column's sums.
+    // One workgroup barrier.
+    template <int K>
+    __device__ __forceinline__ void colsum(double (&v)[K], double* buf) const {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            v[k] += __shfl_xor(v[k], 16, 64);
+            v[k] += __shfl_xor(v[k], 32, 64);
+        }
+        if (grp == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) buf[(w * kTile + col) * K + k] = v[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            v[k] = ((buf[(0 * kTile + col) * K + k] + buf[(1 * kTile + col) * K + k]) +
+                    buf[(2 * kTile + col) * K + k]) + buf[(3 * kTile + col) * K + k];
+    }
+
+    // acc = Q Xs for this wave's two row tiles.
+    __device__ __forceinline__ void prodQ(const double* Xs, tile_v4d (&acc)[2]) const {
+        const int n = a.n, ldh = tile_ldh(n), ks = tile_kp(n) / 4;
+        const int r0 = 16 * w + (lane & 15), r1 = 16 * (w + 4) + (lane & 15);
+        const bool v0 = r0 < n, v1 = r1 < n;
+        const bool second = 16 * (w + 4) < n;   // wave-uniform
+        const double* h0 = Hs + (v0 ? r0 : 0) * ldh;
+        const double* h1 = Hs + (v1 ? r1 : 0) * ldh;
+        acc[0] = tile_v4d{0.0, 0.0, 0.0, 0.0};
+        acc[1] = tile_v4d{0.0, 0.0, 0.0, 0.0};
+        if (second) {
+#pragma unroll 6
+            for (int s = 0; s < ks; ++s) {
+                const int k = 4 * s + grp;
+                const bool kv = k < n;
+                const int kk = kv ? k : 0;
+                const double bv = Xs[k * kTile + col];
+                const double a0 = (v0 && kv) ? h0[kk] : 0.0;
+                const double a1 = (v1 && kv) ? h1[kk] : 0.0;
+                acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, acc[1], 0, 0, 0);
+            }
+        } else {
+#pragma unroll 6
+            for (int s = 0; s < ks; ++s) {
+                const int k = 4 * s + grp;
+                const bool kv = k < n;
+                const int kk = kv ? k : 0;
+                const double bv = Xs[k * kTile + col];
+                const double a0 = (v0 && kv) ? h0[kk] : 0.0;
+                acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc[0], 0, 0, 0);
+            }
+        }
+    }
+
+    // acc = G^T v over this wave's two row tiles of n; v is the p-vector at
+    // offset `voff` of this lane's instance record in `dual`.
+    __device__ __forceinline__ void prodGT(int voff, tile_v4d (&acc)[2]) const {
+        const int n = a.n, p = a.p, ks = tile_kp(p) / 4;
+        const int r0 = 16 * w + (lane & 15), r1 = 16 * (w + 4) + (lane & 15);
+        const bool v0 = r0 < n, v1 = r1 < n;
+        const bool second = 16 * (w + 4) < n;
+        const double* vb = a.dual + (long)(valid ? b : 0) * 3 * p + voff;
+        acc[0] = tile_v4d{0.0, 0.0, 0.0, 0.0};
+        acc[1] = tile_v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int s = 0; s < ks; ++s) {
+            const int k = 4 * s + grp;
+            const bool kv = k < p;
+            const long gk = (long)(kv ? k : 0) * n;
+            const double bv = (kv && valid) ? vb[kv ? k : 0] : 0.0;
+            const double a0 = (v0 && kv) ? (double)a.G[gk + (v0 ? r0 : 0)] : 0.0;
+            acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc[0], 0, 0, 0);
+            if (second) {
+                const double a1 = (v1 && kv) ? (double)a.G[gk + (v1 ? r1 : 0)] : 0.0;
+                acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, acc[1], 0, 0, 0);
+            }
+        }
+    }
+
+    // acc = G Xs for row tile rt of p.
+    __device__ __forceinline__ tile_v4d prodG(const double* Xs, int rt) const {
+        const int n = a.n, p = a.p, ks = tile_kp(n) / 4;
+        const int r = 16 * rt + (lane & 15);
+        const bool rv = r < p;
+        const T* gr = a.G + (long)(rv ? r : 0) * n;
+        tile_v4d acc = tile_v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 6
+        for (int s = 0; s < ks; ++s) {
+            const int k = 4 * s + grp;
+            const bool kv = k < n;
+            const double bv = Xs[k * kTile + col];
+            const double av = (rv && kv) ? (double)gr[kv ? k : 0] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+        return acc;
+    }
+
+    __device__ __forceinline__ void put_x(double* Xs, const double (&v)[2][4]) const {
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (row(j, i) < a.n) Xs[row(j, i) * kTile + col] = v[j][i];
+    }
+
+    __device__ __forceinline__ double gap_from(double fw, double pi2) const {
+        return a.par.sigma > 0.0 ? fmin(fw, pi2 / (2.0 * a.par.sigma)) : fw;
+    }
+
+    // c = q + G^T v for this lane's rows.
+    __device__ __forceinline__ void linear_term(int voff) {
+        tile_v4d acc[2];
+        prodGT(voff, acc);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = row(j, i);
+                c[j][i] = (valid && r < a.n) ? a.q[(long)b * a.n + r] + acc[j][i] : 0.0;
+            }
+    }
+
+    // Algorithm FOM (rho = 0) on the tile from x (Q x in qx) with the linear
+    // term c, for the lanes with `on`; the others keep their state.  On
+    // return x / qx hold ubar and Q ubar; t_out, gap_out the inner count and
+    // certificate; nan_out a non-finite certificate.
+    __device__ __forceinline__ void inner(bool on, int& sel, int& t_out, double& gap_out, bool& nan_out) {
+        const DevParams& par = a.par;
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                xp[j][i] = x[j][i];
+                qxp[j][i] = qx[j][i];
+            }
+        bool run = on;
+        int t = 0;
+        double th = 1.0;
+        t_out = 0;
+        gap_out = 0.0;
+        nan_out = false;
+        for (;;) {
+            double beta = 0.0;
+            if (t > 0) {
+                if (par.inner_variant == 3) beta = par.beta_in;
+                else if (par.inner_variant == 2) {
+                    const double thn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * th * th));
+                    beta = (th - 1.0) / thn;
+                }
+            }
+            double acc[2] = {0.0, 0.0};
+            double xn[2][4];
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    xn[j][i] = 0.0;
+                    if (row(j, i) < a.n) {
+                        const double xi = x[j][i], gr = qx[j][i] + c[j][i];
+                        const double l = lo[j][i], h = hi[j][i];
+                        // exact-gradient certificate terms at x (fw, pi^2)
+                        acc[0] += fmax(gr * (xi - l), gr * (xi - h));
+                        const bool atl = xi <= l, atu = xi >= h;
+                        double pi = gr;
+                        if (atl && atu) pi = 0.0;
+                        else if (atl) pi = fmin(gr, 0.0);
+                        else if (atu) pi = fmax(gr, 0.0);
+                        acc[1] += pi * pi;
+                        const double yi = xi + beta * (xi - xp[j][i]);
+                        const double qyi = qx[j][i] + beta * (qx[j][i] - qxp[j][i]);
+                        xn[j][i] = fmin(fmax(yi - (qyi + c[j][i]) / par.L, l), h);
+                    }
+                }
+            double* Xs = sel ? Xs1 : Xs0;
+            put_x(Xs, xn);
+            colsum<2>(acc, red2 + sel * (kTileWaves * kTile * 2));   // barrier: Xs and sums
+            const double gap = gap_from(acc[0], acc[1]);
+            if (run) {
+                if (!(gap == gap)) {
+                    nan_out = true;
+                    run = false;
+                    t_out = t;
+                    gap_out = gap;
+                } else if ((par.inner_rule == 0 && gap <= par.eps_in) || t >= par.k_in_max) {
+                    run = false;
+                    t_out = t;
+                    gap_out = gap;
+                }
+            }
+            if (!__any(run)) break;   // every wave holds all 16 columns: same decision
+            if (t > 0 && par.inner_variant == 2) th = 0.5 * (1.0 + sqrt(1.0 + 4.0 * th * th));
+            tile_v4d qn[2];
+            prodQ(Xs, qn);
+            if (run) {
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        xp[j][i] = x[j][i];
+                        qxp[j][i] = qx[j][i];
+                        x[j][i] = xn[j][i];
+                        qx[j][i] = qn[j][i];
+                    }
+            }
+            sel ^= 1;
+            ++t;
+        }
+        sel ^= 1;
+    }
+
+    __device__ __forceinline__ bool outer_ok(double F, double feas, double lnorm, double LB, double gnorm) const {
+        const double sc = fmax(1.0, fabs(F));
+        return feas <= a.par.eps_out * fmax(1.0, gnorm) && F - LB <= a.par.eps_out * sc &&
+               lnorm * feas <= a.par.eps_out * sc;
+    }
+
+    __device__ __forceinline__ void solve_tile(int tile) {
+        const DevParams& par = a.par;
+        const int n = a.n, p = a.p;
+        const int PT = (p + 15) / 16;
+        b = tile * kTile + col;
+        valid = b < a.B;
+        double* mu = a.dual + (long)(valid ? b : 0) * 3 * p;
+        double* lamp = mu + p;
+        double* rs = mu + 2 * p;
+        double* us = a.prim + (long)(valid ? b : 0) * 2 * n;
+        double* qus = us + n;
+        const double* qb = a.q + (long)(valid ? b : 0) * n;
+        const double* gb = a.g + (long)(valid ? b : 0) * p;
+
+        // x^0 = projection of 0 on the box, lambda^0 = mu^1 = 0 (Sec. 4)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = row(j, i);
+                lo[j][i] = r < n ? a.lb[r] : 0.0;
+                hi[j][i] = r < n ? a.ub[r] : 0.0;
+                x[j][i] = r < n ? fmin(fmax(0.0, lo[j][i]), hi[j][i]) : 0.0;
+                if (valid && r < n) {
+                    us[r] = 0.0;
+                    qus[r] = 0.0;
+                }
+            }
+        double gg[1] = {0.0};
+        for (int rt = w; rt < PT; rt += kTileWaves)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * rt + grp + 4 * i;
+                if (valid && r < p) {
+                    mu[r] = 0.0;
+                    lamp[r] = 0.0;
+                    rs[r] = 0.0;
+                    gg[0] += gb[r] * gb[r];
+                }
+            }
+        int sel = 0;
+        put_x(Xs0, x);
+        colsum<1>(gg, redK);
+        __syncthreads();
+        const double gnorm = sqrt(gg[0]);
+        {
+            tile_v4d acc[2];
+            prodQ(Xs0, acc);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) qx[j][i] = acc[j][i];
+        }
+        sel = 1;
+        double theta = 1.0, S = 0.0, LB = -INFINITY;
+        double Fc = 0.0, feasc = 0.0, lnc = 0.0;
+        long long inner_total = 0;
+        int k = 0, status = 1, gt = 0;
+        bool act = valid;
+        const bool last_extra = par.output == 0 && par.method == 1;
+
+        while (__any(act)) {
+            if (act) ++k;
+            // Step 1: inner solve at mu^k, warm-started from ubar^{k-1}
+            linear_term(0);
+            ++gt;
+            int t;
+            double gap;
+            bool bad;
+            inner(act, sel, t, gap, bad);
+            if (act) inner_total += t;
+            if (act && bad) {
+                status = 2;
+                act = false;
+            }
+            // Steps 2-3 fused into the epilogue of G ubar, and the averages
+            const double thk = theta;
+            const double thn = par.method == 1 ? 0.5 * (1.0 + sqrt(1.0 + 4.0 * thk * thk)) : 1.0;
+            const double beta = (thk - 1.0) / thn;
+            const double Sn = S + thk;
+            double s[11];
+#pragma unroll
+            for (int z = 0; z < 11; ++z) s[z] = 0.0;
+            double* Xs = sel ? Xs1 : Xs0;
+            put_x(Xs, x);
+            __syncthreads();
+            for (int rt = w; rt < PT; rt += kTileWaves) {
+                const tile_v4d acc = prodG(Xs, rt);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 16 * rt + grp + 4 * i;
+                    if (act && r < p) {
+                        const double ri = acc[i] + gb[r], mui = mu[r];
+                        s[2] += mui * ri;
+                        const double rp = fmax(ri, 0.0);
+                        s[4] += rp * rp;
+                        double lk = mui + par.alpha * ri;
+                        if (par.Kd_nonneg) lk = fmax(lk, 0.0);
+                        s[5] += lk * lk;
+                        const double rsn = rs[r] + thk * ri;
+                        rs[r] = rsn;
+                        const double hp = fmax(rsn / Sn, 0.0);
+                        s[6] += hp * hp;
+                        s[7] += (mui < 0.0) ? 1.0 : 0.0;
+                        s[10] += (lk < 0.0) ? 1.0 : 0.0;
+                        mu[r] = lk + beta * (lk - lamp[r]);
+                        lamp[r] = lk;
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = row(j, i);
+                    if (act && r < n) {
+                        const double ui = x[j][i], qui = qx[j][i], qi = qb[r];
+                        s[0] += ui * qui;
+                        s[1] += qi * ui;
+                        const double usn = us[r] + thk * ui, qusn = qus[r] + thk * qui;
+                        us[r] = usn;
+                        qus[r] = qusn;
+                        s[8] += usn * qusn;
+                        s[9] += qi * usn;
+                    }
+                }
+            colsum<11>(s, redK);
+            __syncthreads();
+            bool ok = false, extra = false;
+            double lnorm = 0.0;
+            if (act) {
+                const double Fu = 0.5 * s[0] + s[1];
+                const double dbar = Fu + s[2];
+                if (s[7] == 0.0) LB = fmax(LB, dbar - gap);
+                S = Sn;
+                double F, feas;
+                if (par.output == 0) {
+                    F = Fu;
+                    feas = sqrt(s[4]);
+                } else {
+                    F = 0.5 * s[8] / (S * S) + s[9] / S;
+                    feas = sqrt(s[6]);
+                }
+                lnorm = sqrt(s[5]);
+                if (!(F == F) || !(LB == LB && dbar == dbar)) {
+                    status = 2;
+                    act = false;
+                } else {
+                    ok = outer_ok(F, feas, lnorm, LB, gnorm);
+                    Fc = F;
+                    feasc = feas;
+                    lnc = lnorm;
+                    extra = ok && last_extra;
+                }
+            }
+            if (__any(extra)) {
+                // Last iterate of DFGM: ubar(lambda^k), eq. last_primal, warm-started
+                double xs[2][4], qs[2][4];
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        xs[j][i] = x[j][i];
+                        qs[j][i] = qx[j][i];
+                    }
+                linear_term(p);   // c = q + G^T lambda^k
+                ++gt;
+                int t2;
+                double gap2;
+                bool bad2;
+                inner(extra, sel, t2, gap2, bad2);
+                if (extra) inner_total += t2;
+                double s2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                double* Xs2 = sel ? Xs1 : Xs0;
+                put_x(Xs2, x);
+                __syncthreads();
+                for (int rt = w; rt < PT; rt += kTileWaves) {
+                    const tile_v4d acc = prodG(Xs2, rt);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = 16 * rt + grp + 4 * i;
+                        if (extra && r < p) {
+                            const double ri = acc[i] + gb[r];
+                            s2[2] += lamp[r] * ri;
+                            const double rp = fmax(ri, 0.0);
+                            s2[4] += rp * rp;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = row(j, i);
+                        if (extra && r < n) {
+                            s2[0] += x[j][i] * qx[j][i];
+                            s2[1] += qb[r] * x[j][i];
+                        }
+                    }
+                colsum<6>(s2, redK);
+                __syncthreads();
+                if (extra) {
+                    if (bad2) {
+                        status = 2;
+                        act = false;
+                        ok = false;
+                    } else {
+                        const double F2 = 0.5 * s2[0] + s2[1];
+                        const double d2 = F2 + s2[2];
+                        if (s[10] == 0.0) LB = fmax(LB, d2 - gap2);
+                        const double feas2 = sqrt(s2[4]);
+                        const bool ok2 = outer_ok(F2, feas2, lnorm, LB, gnorm);
+                        if (ok2) {
+                            Fc = F2;
+                            feasc = feas2;
+                        } else {
+                            ok = false;
+                            // continue from ubar^k unchanged
+#pragma unroll
+                            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) {
+                                    x[j][i] = xs[j][i];
+                                    qx[j][i] = qs[j][i];
+                                }
+                        }
+                    }
+                }
+            }
+            if (act) {
+                theta = thn;
+                if (ok) {
+                    status = 0;
+                    act = false;
+                } else if (k >= par.max_outer) {
+                    act = false;
+                }
+            }
+        }
+        (void)lnc;
+        // outputs of this lane's column
+        if (valid) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = row(j, i);
+                    if (r < n) a.X[(long)b * n + r] = par.output == 1 ? us[r] / S : x[j][i];
+                }
+            for (int rt = w; rt < PT; rt += kTileWaves)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 16 * rt + grp + 4 * i;
+                    if (r < p) a.Lam[(long)b * p + r] = lamp[r];
+                }
+            if (w == 0 && grp == 0) {
+                BatchResultDev rr;
+                rr.status = status;
+                rr.outer = k;
+                rr.inner = inner_total;
+                rr.gt_rows = (long long)gt * p;
+                rr.F = Fc;
+                rr.LB = LB;
+                rr.feas = feasc;
+                rr.lam_min = a.lam_min;
+                rr.lam_max = a.lam_max;
+                rr.G2 = a.g2;
+                a.res[b] = rr;
+            }
+        }
+        __syncthreads();
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ void tile_solve(const TileArgs<T>& args, double* lds) {
+    __shared__ int s_tile;
+    Tile<T> s;
+    s.a = args;
+    const int n = args.n;
+    s.Hs = lds;
+    s.Xs0 = lds + (long)n * tile_ldh(n);
+    s.Xs1 = s.Xs0 + tile_kp(n) * kTile;
+    s.red2 = s.Xs1 + tile_kp(n) * kTile;
+    s.redK = s.red2 + 2 * kTileWaves * kTile * 2;
+    s.lane = threadIdx.x & 63;
+    s.w = threadIdx.x >> 6;
+    s.col = s.lane & 15;
+    s.grp = s.lane >> 4;
+    // Q into LDS once (FP64); both X buffers cleared: their rows >= n stay zero
+    const int ldh = tile_ldh(n);
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) s.Hs[(e / n) * ldh + e % n] = (double)args.Q[e];
+    for (int e = threadIdx.x; e < 2 * tile_kp(n) * kTile; e += blockDim.x) s.Xs0[e] = 0.0;
+    __syncthreads();
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (int)atomicAdd(args.queue, 1u);
+        __syncthreads();
+        const int tile = s_tile;
+        __syncthreads();
+        if ((long)tile * kTile >= args.B) break;
+        s.solve_tile(tile);
+    }
+}
+
+}  // namespace duq

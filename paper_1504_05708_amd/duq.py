@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+from collections.abc import Sequence
 from ctypes import POINTER, Structure, c_char_p, c_double, c_int32, c_int64, c_void_p
 
 import numpy as np
@@ -25,7 +26,7 @@ LAST, AVG = 0, 1
 CERT, FIXED = 0, 1
 INNER_AUTO, INNER_GM, INNER_FGM, INNER_FGM_SIGMA = 0, 1, 2, 3
 ACC_F64, ACC_F32 = 0, 1
-ENGINE_AUTO, ENGINE_BLOCK, ENGINE_GRID = 0, 1, 2
+ENGINE_AUTO, ENGINE_BLOCK, ENGINE_GRID, ENGINE_TILE = 0, 1, 2, 3
 TRACE_SCALARS = 16
 
 BATCH_UNEVEN, BATCH_SHARED = 0, 1
@@ -50,7 +51,8 @@ class DuqOptions(Structure):
                 ("trace_outer", c_int32), ("eps_out", c_double), ("eps_in", c_double),
                 ("rho", c_double), ("lam_min", c_double), ("lam_max", c_double),
                 ("G_norm2", c_double), ("safety", c_double), ("switch_factor", c_double),
-                ("switch_stall", c_int32), ("serve_slice", c_int32), ("reserved", c_int32 * 6)]
+                ("switch_stall", c_int32), ("serve_slice", c_int32), ("out_memspace", c_int32),
+                ("reserved", c_int32 * 5)]
 
 
 class DuqResult(Structure):
@@ -62,6 +64,22 @@ class DuqResult(Structure):
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class Results(Sequence):
+    """Per-instance results of a batch: entry i is converted to a dict when
+    it is read, so returning a large batch costs nothing up front."""
+
+    def __init__(self, arr):
+        self._arr = arr
+
+    def __len__(self):
+        return len(self._arr)
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [self._arr[j].as_dict() for j in range(*i.indices(len(self._arr)))]
+        return self._arr[i].as_dict()
 
 
 class DuqBatch(Structure):
@@ -244,9 +262,11 @@ class Solver:
 
 
 def solve_batch_uneven(batch, constants=None, check=True, **opts):
-    """duq_solve_batch on a packed gen.UnevenBatch (host arrays).
+    """duq_solve_batch on a packed gen.UnevenBatch (host arrays or torch
+    device tensors).
 
     constants: optional (lam_min, lam_max, G_norm2) arrays of length B.
+    device_out=True keeps X, Lam in device memory (torch tensors).
     Returns (X, Lam, results) with X, Lam packed like q and g."""
     B = batch.B
     n = np.ascontiguousarray(batch.n, dtype=np.int32)
@@ -273,7 +293,8 @@ def solve_batch_uneven(batch, constants=None, check=True, **opts):
 def solve_batch_shared(Q, G, lb, ub, q, g, constants=None, check=True, **opts):
     """duq_solve_batch on B instances sharing Q, G, lb, ub; q is B x n, g is B x p.
 
-    constants: optional (lam_min, lam_max, G_norm2) scalars."""
+    constants: optional (lam_min, lam_max, G_norm2) scalars.  device_out=True
+    keeps X, Lam in device memory (torch tensors)."""
     dev = hasattr(Q, "data_ptr")
     if dev:   # torch tensors on the GPU: borrowed
         import torch
@@ -296,14 +317,21 @@ def solve_batch_shared(Q, G, lb, ub, q, g, constants=None, check=True, **opts):
 
 
 def _run_batch(b, B, nx, nl, check, opts):
+    device_out = opts.pop("device_out", False)
     o = default_options(**opts)
-    X = np.empty(max(nx, 1))
-    Lam = np.empty(max(nl, 1))
+    if device_out:   # outputs stay in device memory (torch tensors)
+        import torch
+        o.out_memspace = DEVICE
+        X = torch.empty(max(nx, 1), dtype=torch.float64, device="cuda")
+        Lam = torch.empty(max(nl, 1), dtype=torch.float64, device="cuda")
+    else:
+        X = np.empty(max(nx, 1))
+        Lam = np.empty(max(nl, 1))
     res = (DuqResult * B)()
     rc = lib().duq_solve_batch(ctypes.byref(b), ctypes.byref(o), c_void_p(None), _ptr(X), _ptr(Lam), res)
     if check and rc not in (DUQ_OK, DUQ_EMAXITER):
         raise DuqError(rc, last_error())
-    return X[:nx], Lam[:nl], [r.as_dict() for r in res]
+    return X[:nx], Lam[:nl], Results(res)
 
 
 class Server:
