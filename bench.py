@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
     ap.add_argument("--large-frac", type=float, default=0.01, help="serve: share of n=4096 requests")
     ap.add_argument("--slice", type=int, default=16, help="serve: outer iterations per round")
+    ap.add_argument("--print-source-hash", action="store_true", help="hashes of the profiled kernels' sources")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain device copy of 1 GiB (counter calibration)")
     return ap.parse_args()
@@ -75,19 +76,28 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes_each_way": x.numel() * 8, "launches": 3}))
 
 
-def source_hash() -> str:
-    """Hash of the HIP sources; counter figures are only valid for the build they came from."""
-    import glob
+def source_hash(files) -> str:
+    """Hash of the HIP sources a kernel is built from; counter figures are
+    only valid for the build they came from."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1504_05708_amd", "csrc", "*"))):
-        if f.endswith((".h", ".hip", ".cpp")):
-            h.update(os.path.basename(f).encode())
-            h.update(open(f, "rb").read())
+    for name in sorted(files):
+        path = os.path.join(ROOT, "paper_1504_05708_amd", "csrc", name)
+        h.update(name.encode())
+        h.update(open(path, "rb").read() if os.path.exists(path) else b"missing")
     return h.hexdigest()[:16]
 
 
-def measured_traffic(profile_name: str):
+# Sources of each profiled kernel (its entry file and the headers it uses).
+KERNEL_SOURCES = {
+    "dfom_kernel": ["kernels.hip", "dfom_solver.h", "device_common.h", "internal.h", "launch_util.h"],
+    "dfom_batch_kernel": ["batch_kernels.hip", "batch.h", "lanczos.h", "dfom_solver.h", "device_common.h",
+                          "internal.h", "launch_util.h"],
+    "dfom_tile_kernel": ["batch_kernels.hip", "shared_tile.h", "device_common.h", "internal.h", "launch_util.h"],
+}
+
+
+def measured_traffic(profile_name: str, kernel: str):
     """HBM bytes per launch from a committed rocprofv3 summary (FETCH_SIZE and
     WRITE_SIZE, scaled by the copy calibration), or None when the kernel
     sources changed since the counters were taken."""
@@ -99,7 +109,7 @@ def measured_traffic(profile_name: str):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_hash") != source_hash():
+    if kv.get("source_hash") != source_hash(KERNEL_SOURCES[kernel]):
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -119,6 +129,9 @@ def main():
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
               "the single large QP would shard by rows over RCCL, which is not built.", file=sys.stderr)
         sys.exit(2)
+    if a.print_source_hash:
+        print(json.dumps({k: source_hash(v) for k, v in KERNEL_SOURCES.items()}))
+        return
     if a.copy_probe:
         copy_probe()
         return
@@ -195,7 +208,7 @@ def main():
     achieved = alg_bytes / (kern_avg * 1e-3) / 1e9
     default_workload = (n == 8192 and p == 4096 and a.precision == "f64" and method == duq.DFGM
                         and output == duq.LAST and eps_in == 1e-8 and a.rho == 0.0 and a.eps_out == 1e-4)
-    traffic = measured_traffic("dfom_kernel_config1_f64.txt") if default_workload else None
+    traffic = measured_traffic("dfom_kernel_config1_f64.txt", "dfom_kernel") if default_workload else None
     F, LB, feas = res["f"], res["lb_dual"], res["feas"]
     gnorm = float(np.linalg.norm(qp.g))
     acc = {"cert_subopt_rel": (F - LB) / max(1.0, abs(F)), "feas_rel": feas / max(1.0, gnorm)}
