@@ -104,7 +104,7 @@ int solve_shared_tiles(const duq_batch* b, const duq_options* o, hipStream_t s, 
     const size_t o_L = plan(dev_out ? 0 : 8 * (size_t)B * pp);
     const size_t o_res = plan(sizeof(BatchResultDev) * (size_t)B);
     const size_t o_dual = plan(8 * 3 * (size_t)B * pp);
-    const size_t o_prim = plan(8 * 2 * (size_t)B * n);
+    const size_t o_prim = plan(8 * 4 * (size_t)B * n);
     const size_t o_q = plan(256);
     BTRY(hipMalloc(&ws.p, off));
     char* w = (char*)ws.p;

@@ -42,19 +42,21 @@ struct TileArgs {
     double* Lam;         // B x p
     BatchResultDev* res; // B
     double* dual;        // B x 3p: mu, lambda (last step), running sum of theta_j r^j
-    double* prim;        // B x 2n: running sums of theta_j ubar^j and theta_j Q ubar^j
+    double* prim;        // B x 4n: running sums of theta_j ubar^j and theta_j Q ubar^j,
+                         // ubar^k and Q ubar^k kept across the last-iterate solve
     DevParams par;       // derived constants (shared by all instances)
     double lam_min, lam_max, g2;
     unsigned* queue;
 };
 
 // LDS layout, in doubles: Q (n rows, odd stride), two buffers of the B
-// operand X (kp x 16), the inner reduction (two buffers), the outer one.
+// operand X (kp x 16), the inner reduction (two buffers), the outer one, the
+// box (lb then ub).
 __host__ __device__ inline int tile_ldh(int n) { return n | 1; }
 __host__ __device__ inline int tile_kp(int n) { return (n + 3) & ~3; }
 __host__ __device__ inline long tile_lds_doubles(int n) {
     return (long)n * tile_ldh(n) + 2L * tile_kp(n) * kTile + 2L * kTileWaves * kTile * 2 +
-           (long)kTileWaves * kTile * kTileK;
+           (long)kTileWaves * kTile * kTileK + 2L * n;
 }
 
 template <typename T>
@@ -65,10 +67,11 @@ struct Tile {
     double* Xs1;
     double* red2;
     double* redK;
+    double* box;     // LDS: lb (n) then ub (n)
     int lane, w, col, grp, b;
     bool valid;
     // this lane's rows of its column
-    double x[2][4], xp[2][4], qx[2][4], qxp[2][4], c[2][4], lo[2][4], hi[2][4];
+    double x[2][4], xp[2][4], qx[2][4], qxp[2][4], c[2][4];
 
     __device__ __forceinline__ int row(int j, int i) const { return 16 * (w + 4 * j) + grp + 4 * i; }
 
@@ -93,7 +96,12 @@ struct Tile {
                     buf[(2 * kTile + col) * K + k]) + buf[(3 * kTile + col) * K + k];
     }
 
-    // acc = Q Xs for this wave's two row tiles.
+    // The products run in batches of kB k-steps: every operand load of a
+    // batch is issued before its MFMA chain, so loads overlap instead of
+    // each MFMA waiting for its own.
+    static constexpr int kB = 8;
+
+    // acc = Q Xs for this wave's two row tiles (Q from LDS).
     __device__ __forceinline__ void prodQ(const double* Xs, tile_v4d (&acc)[2]) const {
         const int n = a.n, ldh = tile_ldh(n), ks = tile_kp(n) / 4;
         const int r0 = 16 * w + (lane & 15), r1 = 16 * (w + 4) + (lane & 15);
@@ -103,27 +111,22 @@ struct Tile {
         const double* h1 = Hs + (v1 ? r1 : 0) * ldh;
         acc[0] = tile_v4d{0.0, 0.0, 0.0, 0.0};
         acc[1] = tile_v4d{0.0, 0.0, 0.0, 0.0};
-        if (second) {
-#pragma unroll 6
-            for (int s = 0; s < ks; ++s) {
-                const int k = 4 * s + grp;
-                const bool kv = k < n;
+        for (int s0 = 0; s0 < ks; s0 += kB) {
+            double a0[kB], a1[kB], bv[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const int k = 4 * (s0 + u) + grp;
+                const bool kv = s0 + u < ks && k < n;
                 const int kk = kv ? k : 0;
-                const double bv = Xs[k * kTile + col];
-                const double a0 = (v0 && kv) ? h0[kk] : 0.0;
-                const double a1 = (v1 && kv) ? h1[kk] : 0.0;
-                acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc[0], 0, 0, 0);
-                acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, acc[1], 0, 0, 0);
+                bv[u] = kv ? Xs[kk * kTile + col] : 0.0;
+                a0[u] = (v0 && kv) ? h0[kk] : 0.0;
+                a1[u] = (second && v1 && kv) ? h1[kk] : 0.0;
             }
-        } else {
-#pragma unroll 6
-            for (int s = 0; s < ks; ++s) {
-                const int k = 4 * s + grp;
-                const bool kv = k < n;
-                const int kk = kv ? k : 0;
-                const double bv = Xs[k * kTile + col];
-                const double a0 = (v0 && kv) ? h0[kk] : 0.0;
-                acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc[0], 0, 0, 0);
+            // steps past ks carry zero operands: they add exact zeros
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], bv[u], acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], bv[u], acc[1], 0, 0, 0);
             }
         }
     }
@@ -135,40 +138,58 @@ struct Tile {
         const int r0 = 16 * w + (lane & 15), r1 = 16 * (w + 4) + (lane & 15);
         const bool v0 = r0 < n, v1 = r1 < n;
         const bool second = 16 * (w + 4) < n;
+        const int c0 = v0 ? r0 : 0, c1 = v1 ? r1 : 0;
         const double* vb = a.dual + (long)(valid ? b : 0) * 3 * p + voff;
         acc[0] = tile_v4d{0.0, 0.0, 0.0, 0.0};
         acc[1] = tile_v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-        for (int s = 0; s < ks; ++s) {
-            const int k = 4 * s + grp;
-            const bool kv = k < p;
-            const long gk = (long)(kv ? k : 0) * n;
-            const double bv = (kv && valid) ? vb[kv ? k : 0] : 0.0;
-            const double a0 = (v0 && kv) ? (double)a.G[gk + (v0 ? r0 : 0)] : 0.0;
-            acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc[0], 0, 0, 0);
-            if (second) {
-                const double a1 = (v1 && kv) ? (double)a.G[gk + (v1 ? r1 : 0)] : 0.0;
-                acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, acc[1], 0, 0, 0);
+        for (int s0 = 0; s0 < ks; s0 += kB) {
+            double a0[kB], a1[kB], bv[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const int k = 4 * (s0 + u) + grp;
+                const bool kv = s0 + u < ks && k < p;
+                const long gk = (long)(kv ? k : 0) * n;
+                bv[u] = (kv && valid) ? vb[kv ? k : 0] : 0.0;
+                a0[u] = (v0 && kv) ? (double)a.G[gk + c0] : 0.0;
+                a1[u] = (second && v1 && kv) ? (double)a.G[gk + c1] : 0.0;
+            }
+            // steps past ks carry zero operands: they add exact zeros
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], bv[u], acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], bv[u], acc[1], 0, 0, 0);
             }
         }
     }
 
-    // acc = G Xs for row tile rt of p.
-    __device__ __forceinline__ tile_v4d prodG(const double* Xs, int rt) const {
+    // acc0 = G Xs for row tile rt of p and acc1 for row tile rt + 4 (when
+    // `two`): two independent chains share the B operand.
+    __device__ __forceinline__ void prodG(const double* Xs, int rt, bool two, tile_v4d& acc0,
+                                          tile_v4d& acc1) const {
         const int n = a.n, p = a.p, ks = tile_kp(n) / 4;
-        const int r = 16 * rt + (lane & 15);
-        const bool rv = r < p;
-        const T* gr = a.G + (long)(rv ? r : 0) * n;
-        tile_v4d acc = tile_v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 6
-        for (int s = 0; s < ks; ++s) {
-            const int k = 4 * s + grp;
-            const bool kv = k < n;
-            const double bv = Xs[k * kTile + col];
-            const double av = (rv && kv) ? (double)gr[kv ? k : 0] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        const int ra = 16 * rt + (lane & 15), rb = 16 * (rt + 4) + (lane & 15);
+        const bool va = ra < p, vb2 = two && rb < p;
+        const T* ga = a.G + (long)(va ? ra : 0) * n;
+        const T* gb2 = a.G + (long)(vb2 ? rb : 0) * n;
+        acc0 = tile_v4d{0.0, 0.0, 0.0, 0.0};
+        acc1 = tile_v4d{0.0, 0.0, 0.0, 0.0};
+        for (int s0 = 0; s0 < ks; s0 += kB) {
+            double x0[kB], x1[kB], bv[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const int k = 4 * (s0 + u) + grp;
+                const bool kv = s0 + u < ks && k < n;
+                const int kk = kv ? k : 0;
+                bv[u] = kv ? Xs[kk * kTile + col] : 0.0;
+                x0[u] = (va && kv) ? (double)ga[kk] : 0.0;
+                x1[u] = (vb2 && kv) ? (double)gb2[kk] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[u], bv[u], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[u], bv[u], acc1, 0, 0, 0);
+            }
         }
-        return acc;
     }
 
     __device__ __forceinline__ void put_x(double* Xs, const double (&v)[2][4]) const {
@@ -233,7 +254,7 @@ struct Tile {
                     xn[j][i] = 0.0;
                     if (row(j, i) < a.n) {
                         const double xi = x[j][i], gr = qx[j][i] + c[j][i];
-                        const double l = lo[j][i], h = hi[j][i];
+                        const double l = box[row(j, i)], h = box[a.n + row(j, i)];
                         // exact-gradient certificate terms at x (fw, pi^2)
                         acc[0] += fmax(gr * (xi - l), gr * (xi - h));
                         const bool atl = xi <= l, atu = xi >= h;
@@ -299,8 +320,10 @@ struct Tile {
         double* mu = a.dual + (long)(valid ? b : 0) * 3 * p;
         double* lamp = mu + p;
         double* rs = mu + 2 * p;
-        double* us = a.prim + (long)(valid ? b : 0) * 2 * n;
+        double* us = a.prim + (long)(valid ? b : 0) * 4 * n;
         double* qus = us + n;
+        double* usave = us + 2 * n;
+        double* qusave = us + 3 * n;
         const double* qb = a.q + (long)(valid ? b : 0) * n;
         const double* gb = a.g + (long)(valid ? b : 0) * p;
 
@@ -310,9 +333,7 @@ struct Tile {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = row(j, i);
-                lo[j][i] = r < n ? a.lb[r] : 0.0;
-                hi[j][i] = r < n ? a.ub[r] : 0.0;
-                x[j][i] = r < n ? fmin(fmax(0.0, lo[j][i]), hi[j][i]) : 0.0;
+                x[j][i] = r < n ? fmin(fmax(0.0, box[r]), box[n + r]) : 0.0;
                 if (valid && r < n) {
                     us[r] = 0.0;
                     qus[r] = 0.0;
@@ -376,12 +397,17 @@ struct Tile {
             double* Xs = sel ? Xs1 : Xs0;
             put_x(Xs, x);
             __syncthreads();
-            for (int rt = w; rt < PT; rt += kTileWaves) {
-                const tile_v4d acc = prodG(Xs, rt);
+            for (int rt0 = w; rt0 < PT; rt0 += 2 * kTileWaves) {
+                const bool two = rt0 + kTileWaves < PT;   // wave-uniform
+                tile_v4d accs[2];
+                prodG(Xs, rt0, two, accs[0], accs[1]);
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int r = 16 * rt + grp + 4 * i;
-                    if (act && r < p) {
+                    const tile_v4d& acc = accs[hh];
+                    const int r = 16 * (rt0 + hh * kTileWaves) + grp + 4 * i;
+                    if (act && (hh == 0 || two) && r < p) {
                         const double ri = acc[i] + gb[r], mui = mu[r];
                         s[2] += mui * ri;
                         const double rp = fmax(ri, 0.0);
@@ -447,14 +473,14 @@ struct Tile {
             }
             if (__any(extra)) {
                 // Last iterate of DFGM: ubar(lambda^k), eq. last_primal, warm-started
-                double xs[2][4], qs[2][4];
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        xs[j][i] = x[j][i];
-                        qs[j][i] = qx[j][i];
-                    }
+                    for (int i = 0; i < 4; ++i)
+                        if (extra && row(j, i) < n) {
+                            usave[row(j, i)] = x[j][i];
+                            qusave[row(j, i)] = qx[j][i];
+                        }
                 linear_term(p);   // c = q + G^T lambda^k
                 ++gt;
                 int t2;
@@ -466,12 +492,17 @@ struct Tile {
                 double* Xs2 = sel ? Xs1 : Xs0;
                 put_x(Xs2, x);
                 __syncthreads();
-                for (int rt = w; rt < PT; rt += kTileWaves) {
-                    const tile_v4d acc = prodG(Xs2, rt);
+                for (int rt0 = w; rt0 < PT; rt0 += 2 * kTileWaves) {
+                    const bool two = rt0 + kTileWaves < PT;
+                    tile_v4d accs[2];
+                    prodG(Xs2, rt0, two, accs[0], accs[1]);
+#pragma unroll
+                    for (int hh = 0; hh < 2; ++hh)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const int r = 16 * rt + grp + 4 * i;
-                        if (extra && r < p) {
+                        const tile_v4d& acc = accs[hh];
+                        const int r = 16 * (rt0 + hh * kTileWaves) + grp + 4 * i;
+                        if (extra && (hh == 0 || two) && r < p) {
                             const double ri = acc[i] + gb[r];
                             s2[2] += lamp[r] * ri;
                             const double rp = fmax(ri, 0.0);
@@ -511,10 +542,11 @@ struct Tile {
 #pragma unroll
                             for (int j = 0; j < 2; ++j)
 #pragma unroll
-                                for (int i = 0; i < 4; ++i) {
-                                    x[j][i] = xs[j][i];
-                                    qx[j][i] = qs[j][i];
-                                }
+                                for (int i = 0; i < 4; ++i)
+                                    if (row(j, i) < n) {
+                                        x[j][i] = usave[row(j, i)];
+                                        qx[j][i] = qusave[row(j, i)];
+                                    }
                         }
                     }
                 }
@@ -575,6 +607,7 @@ __device__ __forceinline__ void tile_solve(const TileArgs<T>& args, double* lds)
     s.Xs1 = s.Xs0 + tile_kp(n) * kTile;
     s.red2 = s.Xs1 + tile_kp(n) * kTile;
     s.redK = s.red2 + 2 * kTileWaves * kTile * 2;
+    s.box = s.redK + kTileWaves * kTile * kTileK;
     s.lane = threadIdx.x & 63;
     s.w = threadIdx.x >> 6;
     s.col = s.lane & 15;
@@ -583,6 +616,10 @@ __device__ __forceinline__ void tile_solve(const TileArgs<T>& args, double* lds)
     const int ldh = tile_ldh(n);
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) s.Hs[(e / n) * ldh + e % n] = (double)args.Q[e];
     for (int e = threadIdx.x; e < 2 * tile_kp(n) * kTile; e += blockDim.x) s.Xs0[e] = 0.0;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        s.box[e] = args.lb[e];
+        s.box[n + e] = args.ub[e];
+    }
     __syncthreads();
     for (;;) {
         if (threadIdx.x == 0) s_tile = (int)atomicAdd(args.queue, 1u);
