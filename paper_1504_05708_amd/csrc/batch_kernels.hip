@@ -46,9 +46,9 @@ hipError_t batch_occupancy(int dtype, bool short_class, bool serve, size_t shmem
 }
 
 // Count of non-finite entries of a device array (validation of borrowed data).
-// Shared-Hessian tiles: four waves, one workgroup per CU (Q fills the LDS).
+// Shared-Hessian tiles: eight waves, one workgroup per CU (Q fills the LDS).
 template <typename T>
-__global__ void __launch_bounds__(256, 1) dfom_tile_kernel(TileArgs<T> a) {
+__global__ void __launch_bounds__(64 * kTileWaves, 1) dfom_tile_kernel(TileArgs<T> a) {
     extern __shared__ __align__(16) double lds[];
     tile_solve<T>(a, lds);
 }
@@ -64,11 +64,11 @@ hipError_t tile_occupancy(int dtype, size_t shmem, int* blocks_per_cu) {
     const void* f = tile_fn(dtype);
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, 256, shmem);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, 64 * kTileWaves, shmem);
 }
 
 hipError_t launch_tile(int dtype, int nblocks, size_t shmem, hipStream_t stream, const TileLaunch& t) {
-    LaunchCfg cfg{nblocks, 256, shmem, false, stream};
+    LaunchCfg cfg{nblocks, 64 * kTileWaves, shmem, false, stream};
     const void* f = tile_fn(dtype);
     if (dtype == 0) {
         TileArgs<double> a;

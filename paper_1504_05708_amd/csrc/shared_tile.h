@@ -1,14 +1,14 @@
 // Shared-Hessian batches on the matrix cores.
 //
-// A workgroup of four waves advances a tile of 16 instances that share Q
+// A workgroup of eight waves advances a tile of 16 instances that share Q
 // (n x n), G (p x n) and the box, in lockstep.  The products of the tile are
 // dense GEMMs on FP64 MFMA (16x16x4):
 //   Q X      (n x 16)  once per inner step       (Sec. 5.1, inner gradient)
 //   G U      (p x 16)  once per outer iteration  (residual of Sec. 3 Step 2)
 //   G^T M    (n x 16)  once per outer iteration  (linear term q + G^T mu)
 // Q stays in LDS (FP64) for the whole launch; G is read through the caches.
-// Each lane owns the rows 16 (w + 4 j) + l/16 + 4 i (j < 2, i < 4) of column
-// l % 16 -- the FP64 MFMA result layout -- and keeps its rows of its
+// Wave w owns row tile w of the n rows: lane l holds rows 16 w + l/16 + 4 i
+// (i < 4) of column l % 16 -- the FP64 MFMA result layout -- and keeps its rows of its
 // instance's primal vectors in registers.  The multipliers (p per instance)
 // live in device memory and are updated in the epilogue of the G U product.
 //
@@ -24,8 +24,9 @@
 namespace duq {
 
 constexpr int kTile = 16;       // instances per workgroup
-constexpr int kTileWaves = 4;   // waves per workgroup
-constexpr int kTileK = 12;      // slots of the outer reduction record
+constexpr int kTileWaves = 8;   // waves per workgroup (two per SIMD hide each other's stalls)
+constexpr int kTileRT = 1;      // row tiles of 16 per wave: n <= 16 * kTileWaves * kTileRT
+constexpr int kTileK = 6;       // slots of the outer reduction buffer (longer records go in chunks)
 
 typedef double tile_v4d __attribute__((ext_vector_type(4)));
 
@@ -71,13 +72,13 @@ struct Tile {
     int lane, w, col, grp, b;
     bool valid;
     // this lane's rows of its column
-    double x[2][4], xp[2][4], qx[2][4], qxp[2][4], c[2][4];
+    double x[kTileRT][4], xp[kTileRT][4], qx[kTileRT][4], qxp[kTileRT][4], c[kTileRT][4];
 
-    __device__ __forceinline__ int row(int j, int i) const { return 16 * (w + 4 * j) + grp + 4 * i; }
+    __device__ __forceinline__ int row(int j, int i) const { return 16 * (w + kTileWaves * j) + grp + 4 * i; }
 
-    // Sum K per-lane values over each column (the 16 lanes of a column across
-    // the four waves), in a fixed order; every lane gets its column's sums.
-    // One workgroup barrier.
+    // Sum K per-lane values over each column (the lanes of a column across
+    // the waves), in a fixed order; every lane gets its column's sums.  One
+    // workgroup barrier; `buf` holds kTileWaves x 16 x K doubles.
     template <int K>
     __device__ __forceinline__ void colsum(double (&v)[K], double* buf) const {
 #pragma unroll
@@ -91,9 +92,30 @@ struct Tile {
         }
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            v[k] = ((buf[(0 * kTile + col) * K + k] + buf[(1 * kTile + col) * K + k]) +
-                    buf[(2 * kTile + col) * K + k]) + buf[(3 * kTile + col) * K + k];
+        for (int k = 0; k < K; ++k) {
+            double t = buf[col * K + k];
+#pragma unroll
+            for (int ww = 1; ww < kTileWaves; ++ww) t += buf[(ww * kTile + col) * K + k];
+            v[k] = t;
+        }
+    }
+
+    // colsum for records longer than the outer buffer: chunks of kTileK with
+    // a barrier after each read, so the buffer can be reused at once.
+    template <int K>
+    __device__ __forceinline__ void colsum_long(double (&v)[K], double* buf) const {
+#pragma unroll
+        for (int k0 = 0; k0 < K; k0 += kTileK) {
+            constexpr int C = kTileK;
+            double part[C];
+#pragma unroll
+            for (int k = 0; k < C; ++k) part[k] = k0 + k < K ? v[k0 + k] : 0.0;
+            colsum<C>(part, buf);
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < C; ++k)
+                if (k0 + k < K) v[k0 + k] = part[k];
+        }
     }
 
     // The products run in batches of kB k-steps: every operand load of a
@@ -101,73 +123,77 @@ struct Tile {
     // each MFMA waiting for its own.
     static constexpr int kB = 8;
 
-    // acc = Q Xs for this wave's two row tiles (Q from LDS).
-    __device__ __forceinline__ void prodQ(const double* Xs, tile_v4d (&acc)[2]) const {
+    // acc[j] = Q Xs for this wave's row tiles (Q from LDS).
+    __device__ __forceinline__ void prodQ(const double* Xs, tile_v4d (&acc)[kTileRT]) const {
         const int n = a.n, ldh = tile_ldh(n), ks = tile_kp(n) / 4;
-        const int r0 = 16 * w + (lane & 15), r1 = 16 * (w + 4) + (lane & 15);
-        const bool v0 = r0 < n, v1 = r1 < n;
-        const bool second = 16 * (w + 4) < n;   // wave-uniform
-        const double* h0 = Hs + (v0 ? r0 : 0) * ldh;
-        const double* h1 = Hs + (v1 ? r1 : 0) * ldh;
-        acc[0] = tile_v4d{0.0, 0.0, 0.0, 0.0};
-        acc[1] = tile_v4d{0.0, 0.0, 0.0, 0.0};
+        const double* h[kTileRT];
+        bool v[kTileRT];
+#pragma unroll
+        for (int j = 0; j < kTileRT; ++j) {
+            const int r = 16 * (w + kTileWaves * j) + (lane & 15);
+            v[j] = r < n;
+            h[j] = Hs + (v[j] ? r : 0) * ldh;
+            acc[j] = tile_v4d{0.0, 0.0, 0.0, 0.0};
+        }
         for (int s0 = 0; s0 < ks; s0 += kB) {
-            double a0[kB], a1[kB], bv[kB];
+            double av[kTileRT][kB], bv[kB];
 #pragma unroll
             for (int u = 0; u < kB; ++u) {
                 const int k = 4 * (s0 + u) + grp;
                 const bool kv = s0 + u < ks && k < n;
                 const int kk = kv ? k : 0;
                 bv[u] = kv ? Xs[kk * kTile + col] : 0.0;
-                a0[u] = (v0 && kv) ? h0[kk] : 0.0;
-                a1[u] = (second && v1 && kv) ? h1[kk] : 0.0;
+#pragma unroll
+                for (int j = 0; j < kTileRT; ++j) av[j][u] = (v[j] && kv) ? h[j][kk] : 0.0;
             }
             // steps past ks carry zero operands: they add exact zeros
 #pragma unroll
-            for (int u = 0; u < kB; ++u) {
-                acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], bv[u], acc[0], 0, 0, 0);
-                acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], bv[u], acc[1], 0, 0, 0);
-            }
+            for (int u = 0; u < kB; ++u)
+#pragma unroll
+                for (int j = 0; j < kTileRT; ++j)
+                    acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j][u], bv[u], acc[j], 0, 0, 0);
         }
     }
 
-    // acc = G^T v over this wave's two row tiles of n; v is the p-vector at
+    // acc[j] = G^T v over this wave's row tiles of n; v is the p-vector at
     // offset `voff` of this lane's instance record in `dual`.
-    __device__ __forceinline__ void prodGT(int voff, tile_v4d (&acc)[2]) const {
+    __device__ __forceinline__ void prodGT(int voff, tile_v4d (&acc)[kTileRT]) const {
         const int n = a.n, p = a.p, ks = tile_kp(p) / 4;
-        const int r0 = 16 * w + (lane & 15), r1 = 16 * (w + 4) + (lane & 15);
-        const bool v0 = r0 < n, v1 = r1 < n;
-        const bool second = 16 * (w + 4) < n;
-        const int c0 = v0 ? r0 : 0, c1 = v1 ? r1 : 0;
+        int cidx[kTileRT];
+        bool v[kTileRT];
+#pragma unroll
+        for (int j = 0; j < kTileRT; ++j) {
+            const int r = 16 * (w + kTileWaves * j) + (lane & 15);
+            v[j] = r < n;
+            cidx[j] = v[j] ? r : 0;
+            acc[j] = tile_v4d{0.0, 0.0, 0.0, 0.0};
+        }
         const double* vb = a.dual + (long)(valid ? b : 0) * 3 * p + voff;
-        acc[0] = tile_v4d{0.0, 0.0, 0.0, 0.0};
-        acc[1] = tile_v4d{0.0, 0.0, 0.0, 0.0};
         for (int s0 = 0; s0 < ks; s0 += kB) {
-            double a0[kB], a1[kB], bv[kB];
+            double av[kTileRT][kB], bv[kB];
 #pragma unroll
             for (int u = 0; u < kB; ++u) {
                 const int k = 4 * (s0 + u) + grp;
                 const bool kv = s0 + u < ks && k < p;
                 const long gk = (long)(kv ? k : 0) * n;
                 bv[u] = (kv && valid) ? vb[kv ? k : 0] : 0.0;
-                a0[u] = (v0 && kv) ? (double)a.G[gk + c0] : 0.0;
-                a1[u] = (second && v1 && kv) ? (double)a.G[gk + c1] : 0.0;
-            }
-            // steps past ks carry zero operands: they add exact zeros
 #pragma unroll
-            for (int u = 0; u < kB; ++u) {
-                acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], bv[u], acc[0], 0, 0, 0);
-                acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], bv[u], acc[1], 0, 0, 0);
+                for (int j = 0; j < kTileRT; ++j) av[j][u] = (v[j] && kv) ? (double)a.G[gk + cidx[j]] : 0.0;
             }
+#pragma unroll
+            for (int u = 0; u < kB; ++u)
+#pragma unroll
+                for (int j = 0; j < kTileRT; ++j)
+                    acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j][u], bv[u], acc[j], 0, 0, 0);
         }
     }
 
-    // acc0 = G Xs for row tile rt of p and acc1 for row tile rt + 4 (when
-    // `two`): two independent chains share the B operand.
+    // acc0 = G Xs for row tile rt of p and acc1 for row tile rt + kTileWaves
+    // (when `two`): two independent chains share the B operand.
     __device__ __forceinline__ void prodG(const double* Xs, int rt, bool two, tile_v4d& acc0,
                                           tile_v4d& acc1) const {
         const int n = a.n, p = a.p, ks = tile_kp(n) / 4;
-        const int ra = 16 * rt + (lane & 15), rb = 16 * (rt + 4) + (lane & 15);
+        const int ra = 16 * rt + (lane & 15), rb = 16 * (rt + kTileWaves) + (lane & 15);
         const bool va = ra < p, vb2 = two && rb < p;
         const T* ga = a.G + (long)(va ? ra : 0) * n;
         const T* gb2 = a.G + (long)(vb2 ? rb : 0) * n;
@@ -192,9 +218,9 @@ struct Tile {
         }
     }
 
-    __device__ __forceinline__ void put_x(double* Xs, const double (&v)[2][4]) const {
+    __device__ __forceinline__ void put_x(double* Xs, const double (&v)[kTileRT][4]) const {
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < kTileRT; ++j)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 if (row(j, i) < a.n) Xs[row(j, i) * kTile + col] = v[j][i];
@@ -206,10 +232,10 @@ struct Tile {
 
     // c = q + G^T v for this lane's rows.
     __device__ __forceinline__ void linear_term(int voff) {
-        tile_v4d acc[2];
+        tile_v4d acc[kTileRT];
         prodGT(voff, acc);
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < kTileRT; ++j)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = row(j, i);
@@ -224,7 +250,7 @@ struct Tile {
     __device__ __forceinline__ void inner(bool on, int& sel, int& t_out, double& gap_out, bool& nan_out) {
         const DevParams& par = a.par;
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < kTileRT; ++j)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 xp[j][i] = x[j][i];
@@ -246,9 +272,9 @@ struct Tile {
                 }
             }
             double acc[2] = {0.0, 0.0};
-            double xn[2][4];
+            double xn[kTileRT][4];
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < kTileRT; ++j)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     xn[j][i] = 0.0;
@@ -286,11 +312,11 @@ struct Tile {
             }
             if (!__any(run)) break;   // every wave holds all 16 columns: same decision
             if (t > 0 && par.inner_variant == 2) th = 0.5 * (1.0 + sqrt(1.0 + 4.0 * th * th));
-            tile_v4d qn[2];
+            tile_v4d qn[kTileRT];
             prodQ(Xs, qn);
             if (run) {
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < kTileRT; ++j)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         xp[j][i] = x[j][i];
@@ -329,7 +355,7 @@ struct Tile {
 
         // x^0 = projection of 0 on the box, lambda^0 = mu^1 = 0 (Sec. 4)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < kTileRT; ++j)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = row(j, i);
@@ -357,10 +383,10 @@ struct Tile {
         __syncthreads();
         const double gnorm = sqrt(gg[0]);
         {
-            tile_v4d acc[2];
+            tile_v4d acc[kTileRT];
             prodQ(Xs0, acc);
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < kTileRT; ++j)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) qx[j][i] = acc[j][i];
         }
@@ -427,7 +453,7 @@ struct Tile {
                 }
             }
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < kTileRT; ++j)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int r = row(j, i);
@@ -442,8 +468,7 @@ struct Tile {
                         s[9] += qi * usn;
                     }
                 }
-            colsum<11>(s, redK);
-            __syncthreads();
+            colsum_long<11>(s, redK);
             bool ok = false, extra = false;
             double lnorm = 0.0;
             if (act) {
@@ -474,7 +499,7 @@ struct Tile {
             if (__any(extra)) {
                 // Last iterate of DFGM: ubar(lambda^k), eq. last_primal, warm-started
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < kTileRT; ++j)
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
                         if (extra && row(j, i) < n) {
@@ -511,7 +536,7 @@ struct Tile {
                     }
                 }
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < kTileRT; ++j)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int r = row(j, i);
@@ -520,8 +545,7 @@ struct Tile {
                             s2[1] += qb[r] * x[j][i];
                         }
                     }
-                colsum<6>(s2, redK);
-                __syncthreads();
+                colsum_long<6>(s2, redK);
                 if (extra) {
                     if (bad2) {
                         status = 2;
@@ -540,7 +564,7 @@ struct Tile {
                             ok = false;
                             // continue from ubar^k unchanged
 #pragma unroll
-                            for (int j = 0; j < 2; ++j)
+                            for (int j = 0; j < kTileRT; ++j)
 #pragma unroll
                                 for (int i = 0; i < 4; ++i)
                                     if (row(j, i) < n) {
@@ -565,7 +589,7 @@ struct Tile {
         // outputs of this lane's column
         if (valid) {
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < kTileRT; ++j)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int r = row(j, i);
