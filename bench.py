@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--accumulate", choices=["f64", "f32"], default="f64",
+                    help="single QP with f32 storage: FP32-accumulated products until the test passes at "
+                         "10 eps_out or stalls, then FP64 (the precision switch)")
     ap.add_argument("--method", choices=["dfgm", "dgm"], default="dfgm")
     ap.add_argument("--output", choices=["last", "avg"], default="last")
     ap.add_argument("--eps-in", type=float, default=None)
@@ -160,6 +163,9 @@ def main():
     torch.cuda.synchronize()
     opts = dict(method=method, output=output, eps_out=a.eps_out, eps_in=eps_in, rho=a.rho,
                 max_outer=200000, engine=duq.ENGINE_GRID)
+    if a.accumulate == "f32":
+        assert a.precision == "f32", "--accumulate f32 needs --precision f32"
+        opts.update(accumulate=duq.ACC_F32, switch_factor=10.0, switch_stall=20)
 
     def step():
         t = time.perf_counter()
@@ -233,8 +239,10 @@ def main():
             "workload": f"single dense QP n={n} p={p}: Q=A^T A/n+0.01I (A {2 * n}x{n} N(0,1)), G N(0,1), "
                         f"g=-(G x0)-s strictly feasible, box [-1,1], seed 1; "
                         f"{a.method.upper()}-{a.output} eps_out={a.eps_out:g} eps_in={eps_in:g} rho={a.rho:g}; "
-                        f"Q,G stored {a.precision}, FP64 arithmetic; end-to-end step = setup (Lanczos "
-                        f"constants) + solve",
+                        f"Q,G stored {a.precision}, "
+                        + ("FP32-accumulated products, then FP64 (precision switch)" if a.accumulate == "f32"
+                           else "FP64 arithmetic")
+                        + "; end-to-end step = setup (Lanczos constants) + solve",
             "n": n, "p": p, "storage": a.precision, "method": a.method, "output": a.output,
             "eps_out": a.eps_out, "eps_in": eps_in, "rho": a.rho,
         },
@@ -250,6 +258,7 @@ def main():
             "launch_ms_avg": round(kern_avg, 3),
         },
         "solve": {"outer_iters": outer, "inner_iters": inner, "gt_rows_read": gt_rows,
+                  "f64_outer_iters": res["f64_outer_iters"],
                   "f": F, "lb": LB, "feas": feas, "online_solves_per_s": round(1e3 / kern_avg, 4),
                   "setup_ms_avg": round(float(np.mean(setup_ms)), 2),
                   "event_ms_per_step": round(ev_ms / a.steps, 3),
