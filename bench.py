@@ -414,17 +414,21 @@ def bench_batch(a):
             n_gt = r["gt_rows"] / p if p else 0.0
             flops += 2.0 * n * n * (r["inner_iters"] + 1) + 2.0 * 2.0 * p * n * n_gt
         tf = flops / (kern_ms * 1e-3) / 1e12
+        tr = (measured_traffic("dfom_tile_kernel_mpc4096_f64.txt", "dfom_tile_kernel")
+              if (a.workload == "mpc" and a.precision == "f64" and B == 4096) else None)
         roof = {"bound": "mfma", "achieved": round(tf, 2), "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
-                "frac": round(tf / FP64_MFMA_PEAK_TFS, 4), "traffic": None, "kernel": "dfom_tile_kernel",
+                "frac": round(tf / FP64_MFMA_PEAK_TFS, 4), "traffic": tr, "kernel": "dfom_tile_kernel",
                 "alg_flops_per_launch": flops, "launch_ms": round(kern_ms, 3),
                 "note": "FP64 MFMA 16x16x4; Q held in LDS, G through L2; flops of masked (finished) "
                         "columns and of padding are not counted"}
     else:
+        tr = (measured_traffic("dfom_batch_kernel_uneven2000_f32.txt", "dfom_batch_kernel")
+              if (a.workload == "uneven" and a.precision == "f32" and B == 2000) else None)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
                 "kernel": "dfom_batch_kernel", "alg_bytes_per_launch": alg, "launch_ms": round(kern_ms, 3),
-                "note": "per-instance matrices are re-read from the on-die caches (MALL/L2); "
-                        "the unique HBM bytes are read once per launch"}
+                "note": "algorithmic bytes: every matrix read of every instance (768 concurrent instances "
+                        "exceed L2 and MALL, so they stream from HBM)"}
     # plain per-QP solver on a sample spread over the batch
     S = min(a.plain_sample, B)
     idx = np.linspace(0, B - 1, S).astype(int)
