@@ -62,6 +62,26 @@ __device__ __forceinline__ double xload(const double* p) {
                                                   __HIP_MEMORY_SCOPE_AGENT));
 }
 
+// sum over b = first, first + step, ... < nb of xload(base + b * stride), added
+// in that order (the same bits as a plain loop); four loads are in flight at
+// once instead of one round trip per term.
+__device__ __forceinline__ double xsum_strided(const double* base, long stride, int first, int step, int nb) {
+    double s = 0.0;
+    int b = first;
+    for (; b + 3 * step < nb; b += 4 * step) {
+        const double v0 = xload(base + (long)b * stride);
+        const double v1 = xload(base + (long)(b + step) * stride);
+        const double v2 = xload(base + (long)(b + 2 * step) * stride);
+        const double v3 = xload(base + (long)(b + 3 * step) * stride);
+        s += v0;
+        s += v1;
+        s += v2;
+        s += v3;
+    }
+    for (; b < nb; b += step) s += xload(base + (long)b * stride);
+    return s;
+}
+
 // A team is either one workgroup (size 1) or every workgroup of a
 // cooperative launch.  Grid barrier: each workgroup publishes its arrival
 // epoch in its own 128-byte line, workgroup 0 polls all of them in parallel

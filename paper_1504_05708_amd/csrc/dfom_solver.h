@@ -281,9 +281,28 @@ __device__ __forceinline__ void stage(const double* src, int len, double* dst) {
     __syncthreads();
 }
 
-// Staging of a vector written by other workgroups of the grid.
+// Staging of a vector written by other workgroups of the grid.  Each thread
+// issues up to 8 loads before it waits, so the copy costs a couple of round
+// trips to memory rather than one per element.
 __device__ __forceinline__ void stage_shared(const double* src, int len, double* dst) {
-    for (int i = threadIdx.x; i < len; i += blockDim.x) dst[i] = xload(src + i);
+    constexpr int B = 8;
+    const int step = blockDim.x;
+    int i = threadIdx.x;
+    for (; i + (B - 1) * step < len; i += B * step) {
+        double v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) v[u] = xload(src + i + u * step);
+#pragma unroll
+        for (int u = 0; u < B; ++u) dst[i + u * step] = v[u];
+    }
+    for (; i + 3 * step < len; i += 4 * step) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = xload(src + i + u * step);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) dst[i + u * step] = v[u];
+    }
+    for (; i < len; i += step) dst[i] = xload(src + i);
     __syncthreads();
 }
 

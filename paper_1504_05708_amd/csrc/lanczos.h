@@ -52,8 +52,7 @@ struct Lanczos {
         if (tm.size == 1) { __syncthreads(); return true; }
         if (tm.sync()) return false;
         for (int j = wid; j < m; j += nw) {
-            double s = 0.0;
-            for (int b = lane; b < tm.size; b += kWave) s += xload(L.part + (long)b * ncol + j);
+            double s = xsum_strided(L.part + j, ncol, lane, kWave, tm.size);
             s = wave_sum(s);
             if (lane == 0) hl[j] = s;
         }
@@ -86,8 +85,7 @@ struct Lanczos {
         if (tm.sync()) return false;
         const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
         for (int j = nlo + wid; j < nhi; j += nw) {
-            double s = 0.0;
-            for (int b = lane; b < tm.size; b += kWave) s += xload(L.gtp + (long)b * n + j);
+            double s = xsum_strided(L.gtp + j, n, lane, kWave, tm.size);
             s = wave_sum(s);
             if (lane == 0) w[j] = s;
         }
@@ -195,8 +193,7 @@ struct Lanczos {
         if (threadIdx.x == 0) xstore(L.part + (long)tm.rank * ncol + k + 1, v[0]);
         if (tm.sync()) return false;
         if (wid == 0) {
-            double t = 0.0;
-            for (int b = lane; b < tm.size; b += kWave) t += xload(L.part + (long)b * ncol + k + 1);
+            double t = xsum_strided(L.part + k + 1, ncol, lane, kWave, tm.size);
             t = wave_sum(t);
             if (lane == 0) hl[0] = t;
         }
