@@ -56,6 +56,8 @@ def parse():
                     help="single large QP (default), uneven batch, or shared-Hessian MPC batch")
     ap.add_argument("--batch", type=int, default=None, help="instances of a batch workload")
     ap.add_argument("--plain-sample", type=int, default=48)
+    ap.add_argument("--gen-workers", type=int, default=16,
+                    help="processes generating uneven instances (1: in-process, e.g. under a profiler)")
     ap.add_argument("--batch-engine", choices=["auto", "block", "tile"], default="auto",
                     help="batch kernel: tiles of 16 on MFMA (shared batches) or one workgroup per instance")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: Poisson arrivals per second")
@@ -323,7 +325,7 @@ def bench_batch(a):
     s_bytes = 4 if npdt == np.float32 else 8
     cuda = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()
     t0 = time.time()
-    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    workers = max(1, min(a.gen_workers, len(os.sched_getaffinity(0))))
     if a.workload == "uneven":
         B = a.batch or 10000
         ub = gen.uneven_batch(B=B, seed=3, dtype=npdt, workers=workers)
@@ -517,7 +519,7 @@ def bench_serve(a):
     u = rng.uniform(size=R)
     cls = np.where(u < a.large_frac, 2, np.where(u < a.large_frac + (1 - a.large_frac) / 2, 0, 1))
     n_unev = int(np.sum(cls == 0))
-    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    workers = max(1, min(a.gen_workers, len(os.sched_getaffinity(0))))
     ub = gen.uneven_batch(B=max(n_unev, 1), seed=4, dtype=npdt, workers=workers)
     systems = [gen.mpc_system(seed=40 + j) for j in range(8)]
     n_large = int(np.sum(cls == 2))
