@@ -104,3 +104,22 @@ def test_batch_rejects_bad_input():
     with pytest.raises(duq.DuqError) as e:
         duq.solve_batch_uneven(ub)
     assert e.value.code == duq.DUQ_EINVAL
+
+
+def test_device_outputs_equal_host_outputs():
+    print("[case] batch outputs in device memory", flush=True)
+    ub = gen.uneven_batch(B=9, seed=35, n_lo=20, n_hi=300, dtype=np.float64)
+    kw = dict(method=duq.DFGM, eps_out=1e-4, eps_in=1e-8, max_outer=20000)
+    X, Lam, res = duq.solve_batch_uneven(ub, **kw)
+    Xd, Ld, rd = duq.solve_batch_uneven(ub, device_out=True, **kw)
+    assert Xd.is_cuda and Ld.is_cuda
+    assert np.array_equal(Xd.cpu().numpy()[:X.size], X) and np.array_equal(Ld.cpu().numpy()[:Lam.size], Lam)
+    assert [r["outer_iters"] for r in rd] == [r["outer_iters"] for r in res]
+    sysm = gen.mpc_system(seed=2, N=10)
+    X0, Qlin, Glin = gen.mpc_batch(sysm, 20, seed=36)
+    for eng in (duq.ENGINE_TILE, duq.ENGINE_BLOCK):
+        Xh, Lh, _ = duq.solve_batch_shared(sysm.H, sysm.G, sysm.lb, sysm.ub, Qlin, Glin, engine=eng, **kw)
+        Xd, Ld, _ = duq.solve_batch_shared(sysm.H, sysm.G, sysm.lb, sysm.ub, Qlin, Glin, engine=eng,
+                                           device_out=True, **kw)
+        assert np.array_equal(Xd.cpu().numpy().reshape(Xh.shape), Xh)
+        assert np.array_equal(Ld.cpu().numpy().reshape(Lh.shape), Lh)
