@@ -591,6 +591,30 @@ def bench_serve(a):
     th.join()
     t_end = time.perf_counter()
     srv.close()
+    # plain per-QP solver (duq_setup + duq_solve per request, same options) on a
+    # sample of each class, weighted by the class counts of the stream
+    plain_s = {}
+    for k, m in (("uneven", 6), ("mpc", 12), ("large", 1)):
+        idx = [i for i in range(R) if reqs[i][0] == k][:m]
+        if not idx:
+            continue
+        sec = []
+        for i in idx:
+            d = reqs[i][1]
+            o = {kk: v for kk, v in opts.items() if kk != "serve_slice"}
+            if k == "mpc":
+                sy = systems[d["sys"]]
+                prob = (sy.H.astype(npdt), d["q"], sy.G.astype(npdt), d["g"], sy.lb, sy.ub)
+                with duq.Solver(*prob, **o) as sv:   # the system's constants, as registered systems have
+                    c = sv.constants()
+                o.update(lam_min=c["lam_min"], lam_max=c["lam_max"], G_norm2=c["G_norm2"])
+            else:
+                prob = (d["Q"], d["q"], d["G"], d["g"], d["lb"], d["ub"])
+            t = time.perf_counter()
+            with duq.Solver(*prob, **o) as sv:
+                sv.solve(check=False)
+            sec.append(time.perf_counter() - t)
+        plain_s[k] = float(np.mean(sec))
     done = [i for i in range(R) if results[i] is not None]
     lat = np.array([results[i][3]["time_ms"] for i in done])
     span = max(results[i][3]["time_ms"] * 1e-3 + sub_t[i] for i in done) if done else t_end - t_start
@@ -607,6 +631,7 @@ def bench_serve(a):
     cert = max((results[i][3]["f"] - results[i][3]["lb_dual"]) / max(1.0, abs(results[i][3]["f"])) for i in done)
     line = {
         "metric": METRIC, "value": round(len(done) / span, 2), "unit": "solves/s", "n_gpus": 1, "steps": 1,
+        "speedup_vs_plain": None,
         "warmup": 1, "ms_per_step": round(span * 1e3, 1), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"serving: Poisson arrivals {a.rate:g}/s for {a.duration:g} s (seed 4); "
@@ -620,8 +645,11 @@ def bench_serve(a):
         "solve": {"completed": len(done), "ok": ok, "max_cert_subopt_rel": cert,
                   "max_feas_abs": max(results[i][3]["feas"] for i in done)},
         "offered_per_s": round(R / a.duration, 1),
+        "plain_solves_per_s": round(len(done) / sum(plain_s.get(reqs[i][0], 0.0) for i in done), 2),
+        "plain_seconds_per_request": {k: round(v, 4) for k, v in plain_s.items()},
         "gen_seconds": round(gen_s, 1),
     }
+    line["speedup_vs_plain"] = round(line["value"] / line["plain_solves_per_s"], 1)
     print(json.dumps(line), flush=True)
 
 

@@ -32,6 +32,23 @@ struct DevBuf {
     }
 };
 
+// Events and streams released on every return path.
+struct EventH {
+    hipEvent_t e = nullptr;
+    ~EventH() {
+        if (e) (void)hipEventDestroy(e);
+    }
+};
+struct StreamH {
+    hipStream_t s = nullptr;
+    ~StreamH() {
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+    }
+};
+
 #define BTRY(expr)                                                                                 \
     do {                                                                                           \
         hipError_t _e = (expr);                                                                    \
@@ -126,12 +143,12 @@ int solve_shared_tiles(const duq_batch* b, const duq_options* o, hipStream_t s, 
     t.queue = (unsigned*)(w + o_q);
     const int tiles = (B + 15) / 16;
     const int nblocks = std::max(1, std::min(tiles, device_cus() * bpc));
-    hipEvent_t e0, e1;
-    BTRY(hipEventCreate(&e0));
-    BTRY(hipEventCreate(&e1));
-    BTRY(hipEventRecord(e0, s));
+    EventH e0, e1;
+    BTRY(hipEventCreate(&e0.e));
+    BTRY(hipEventCreate(&e1.e));
+    BTRY(hipEventRecord(e0.e, s));
     hipError_t le = launch_tile(b->dtype, nblocks, tile_lds_bytes(n), s, t);
-    BTRY(hipEventRecord(e1, s));
+    BTRY(hipEventRecord(e1.e, s));
     std::vector<BatchResultDev> rd(B);
     if (le == hipSuccess) {
         BTRY(hipMemcpyAsync(rd.data(), w + o_res, sizeof(BatchResultDev) * B, hipMemcpyDeviceToHost, s));
@@ -141,9 +158,7 @@ int solve_shared_tiles(const duq_batch* b, const duq_options* o, hipStream_t s, 
     }
     hipError_t se = hipStreamSynchronize(s);
     float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    (void)hipEventElapsedTime(&ms, e0.e, e1.e);
     BTRY(le);
     BTRY(se);
     int code = DUQ_OK;
@@ -426,18 +441,19 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
     // the two classes run concurrently: long rows on `s`, short rows on a
     // second stream joined back to `s`
     const bool both = cls[0].count > 0 && cls[1].count > 0;
-    hipStream_t s2 = s;
-    hipEvent_t fork = nullptr, join = nullptr, e0, e1;
-    BTRY(hipEventCreate(&e0));
-    BTRY(hipEventCreate(&e1));
-    BTRY(hipEventRecord(e0, s));
+    StreamH side;
+    EventH fork, join, e0, e1;
+    BTRY(hipEventCreate(&e0.e));
+    BTRY(hipEventCreate(&e1.e));
+    BTRY(hipEventRecord(e0.e, s));
     if (both) {
-        BTRY(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
-        BTRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-        BTRY(hipEventCreateWithFlags(&join, hipEventDisableTiming));
-        BTRY(hipEventRecord(fork, s));
-        BTRY(hipStreamWaitEvent(s2, fork, 0));
+        BTRY(hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking));
+        BTRY(hipEventCreateWithFlags(&fork.e, hipEventDisableTiming));
+        BTRY(hipEventCreateWithFlags(&join.e, hipEventDisableTiming));
+        BTRY(hipEventRecord(fork.e, s));
+        BTRY(hipStreamWaitEvent(side.s, fork.e, 0));
     }
+    hipStream_t s2 = both ? side.s : s;
     hipError_t le = hipSuccess;
     for (int ci = 0; ci < 2 && le == hipSuccess; ++ci) {
         const Cls& c = cls[ci];
@@ -454,11 +470,11 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
         le = launch_batch(b->dtype, c.sh, c.nblocks, c.shmem, ci == 1 ? s2 : s, Lc);
     }
     if (both) {
-        hipError_t je = hipEventRecord(join, s2);
-        if (je == hipSuccess) je = hipStreamWaitEvent(s, join, 0);
+        hipError_t je = hipEventRecord(join.e, s2);
+        if (je == hipSuccess) je = hipStreamWaitEvent(s, join.e, 0);
         if (le == hipSuccess) le = je;
     }
-    BTRY(hipEventRecord(e1, s));
+    BTRY(hipEventRecord(e1.e, s));
     std::vector<BatchResultDev> rd(B);
     if (le == hipSuccess) {
         BTRY(hipMemcpyAsync(rd.data(), w + o_res, sizeof(BatchResultDev) * B, hipMemcpyDeviceToHost, s));
@@ -468,14 +484,7 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
     }
     hipError_t se = hipStreamSynchronize(s);
     float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (both) {
-        (void)hipEventDestroy(fork);
-        (void)hipEventDestroy(join);
-        (void)hipStreamDestroy(s2);
-    }
+    (void)hipEventElapsedTime(&ms, e0.e, e1.e);
     BTRY(le);
     BTRY(se);
     int code = DUQ_OK;
