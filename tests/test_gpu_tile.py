@@ -93,3 +93,37 @@ def test_tile_engine_rejects_what_it_cannot_run():
     with pytest.raises(duq.DuqError) as e:
         duq.solve_batch_uneven(ub, engine=duq.ENGINE_TILE)
     assert e.value.code == duq.DUQ_EINVAL
+
+
+@pytest.mark.parametrize("n,p", [(37, 21), (1, 3), (13, 0), (121, 50)])
+def test_tile_ragged_generic_shapes_match_oracle(n, p):
+    """Shapes the MPC systems never produce: n not a multiple of 4 (a partial
+    last k-step), p not a multiple of 16, no constraints, n = 1, the largest n
+    whose Q fits the LDS."""
+    print(f"[case] tile generic shape n={n} p={p}", flush=True)
+    base = gen.random_dense_qp(n, max(p, 1), seed=60 + n, reg=0.1)
+    G = base.G[:p]
+    B = 19
+    qs, gs = [], []
+    for b in range(B):
+        q, g = gen.fresh_linear_terms(base.G, seed=1000 * n + b)
+        qs.append(q)
+        gs.append(g[:p])
+    Q = np.stack(qs)
+    Gl = np.stack(gs) if p else np.zeros((B, 0))
+    qp0 = gen.QP(base.Q, Q[0], G, Gl[0], base.lb, base.ub)
+    c = dfom.problem_constants(qp0.Q, qp0.G, qp0.lb, qp0.ub, 0.0, 1e-6)
+    consts = (c.lam_min, c.lam_max, c.G_norm2 if p else 1.0)
+    X, Lam, res = duq.solve_batch_shared(base.Q, G if p else np.zeros((0, n)), base.lb, base.ub, Q, Gl,
+                                         constants=consts, engine=duq.ENGINE_TILE, method=duq.DFGM,
+                                         eps_out=1e-4, eps_in=1e-8, max_outer=20000)
+    for b in (0, 7, 18):
+        qp = gen.QP(base.Q, Q[b], G, Gl[b], base.lb, base.ub)
+        ref = dfom.dfom_solve(qp, dfom.Options(method=dfom.DFGM, eps_out=1e-4, eps_in=1e-8, max_outer=20000,
+                                               lam_min=c.lam_min, lam_max=c.lam_max, G_norm2=c.G_norm2))
+        r = res[b]
+        assert r["status"] == duq.DUQ_OK and ref.status == 0, (b, r)
+        assert r["outer_iters"] == ref.outer_iters and r["inner_iters"] == ref.inner_iters, (b, r, ref.outer_iters)
+        np.testing.assert_allclose(X[b], ref.x, rtol=0, atol=1e-7)
+        if p:
+            np.testing.assert_allclose(Lam[b], ref.lam, rtol=0, atol=1e-7 * max(1.0, np.abs(ref.lam).max()))
