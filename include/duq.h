@@ -169,6 +169,8 @@ int duq_get_constants(duq_handle *h, double *lam_min, double *lam_max,
  *   at voff[i] of q / lb / ub, g_i at coff[i] of g.
  * DUQ_BATCH_SHARED: B QPs sharing Q (n x n), G (p x n), lb, ub; q is B x n
  *   and g is B x p (row b belongs to instance b); voff/coff are unused.
+ * HOST data are checked (finite, lb <= ub) and copied; DEVICE data are
+ *   borrowed for the call and not scanned (the caller vouches for them).
  * lam_min / lam_max / G_norm2: per-instance constants (B each) or NULL to
  *   estimate them on the device (one value each for SHARED).               */
 enum { DUQ_BATCH_UNEVEN = 0, DUQ_BATCH_SHARED = 1 };
@@ -210,7 +212,9 @@ int duq_solve_batch(const duq_batch *batch, const duq_options *opts, void *strea
  * A server owns a device arena of hbm_budget_bytes (0 = 4 GiB), one HIP
  * stream and one host thread.  The thread works in rounds:
  *   1. admit pending requests in arrival order while their device footprint
- *      (matrices, vectors, solver state) fits the arena, and upload them;
+ *      (matrices, vectors, solver state) fits the arena, and upload them
+ *      (a large request's solver workspace is allocated beside the arena,
+ *      its estimated size counted against the budget);
  *   2. run one launch of the batch kernel over every admitted request with
  *      n <= DUQ_SERVE_BATCH_NMAX; each runs a slice of outer iterations
  *      worth about opts.serve_slice iterations at n = 256,

@@ -296,7 +296,7 @@ void admit(duq_server* s) {
             r->mem = m;
             const int rc = place(s, r);
             if (rc) {
-                finish(s, r, rc, "admission failed");
+                finish(s, r, rc, std::string("admission failed: ") + duq_last_error());
                 continue;
             }
             r->state = ST_ACTIVE;
