@@ -123,3 +123,35 @@ def test_device_outputs_equal_host_outputs():
                                            device_out=True, **kw)
         assert np.array_equal(Xd.cpu().numpy().reshape(Xh.shape), Xh)
         assert np.array_equal(Ld.cpu().numpy().reshape(Lh.shape), Lh)
+
+
+@pytest.mark.parametrize("method,output,rho", [(duq.DFGM, duq.LAST, 1.0), (duq.DGM, duq.AVG, 0.5),
+                                               (duq.DFGM, duq.AVG, 0.0)])
+def test_uneven_batch_other_options_match_oracle(method, output, rho):
+    """The per-instance batch kernel with the augmented Lagrangian (rho > 0)
+    and the averaged output, against the oracle instance by instance."""
+    print(f"[case] uneven batch method={method} output={output} rho={rho}", flush=True)
+    ub = gen.uneven_batch(B=8, seed=37, n_lo=10, n_hi=140, dtype=np.float64)
+    consts = [exact_constants(ub.instance(i)) for i in range(ub.B)]
+    C = [np.array([c[j] for c in consts]) for j in range(3)]
+    eps_in = 1e-8 if method == duq.DFGM else 1e-6
+    X, Lam, res = duq.solve_batch_uneven(ub, constants=C, method=method, output=output, rho=rho, eps_out=1e-4,
+                                         eps_in=eps_in, max_outer=20000)
+    for i in range(ub.B):
+        qp = ub.instance(i)
+        lmin, lmax, g2 = consts[i]
+        ref = dfom.dfom_solve(qp, dfom.Options(method=dfom.DFGM if method == duq.DFGM else dfom.DGM,
+                                               output=dfom.LAST if output == duq.LAST else dfom.AVG, rho=rho,
+                                               eps_out=1e-4, eps_in=eps_in, max_outer=20000,
+                                               lam_min=lmin, lam_max=lmax, G_norm2=g2))
+        r = res[i]
+        assert r["status"] == (duq.DUQ_OK if ref.status == 0 else duq.DUQ_EMAXITER), (i, r, ref.status)
+        if ref.outer_iters <= 300:
+            assert r["outer_iters"] == ref.outer_iters and r["inner_iters"] == ref.inner_iters, (i, r, ref.outer_iters)
+            np.testing.assert_allclose(X[ub.voff[i]:ub.voff[i] + qp.n], ref.x, rtol=0, atol=1e-7)
+        else:
+            # long runs whose warm-started inner certificates sit at eps_in: a
+            # rounding-level difference can move a stop decision by one step
+            assert abs(r["outer_iters"] - ref.outer_iters) <= 2, (i, r["outer_iters"], ref.outer_iters)
+            assert abs(r["inner_iters"] - ref.inner_iters) <= 0.01 * ref.inner_iters, (i, r, ref.inner_iters)
+            np.testing.assert_allclose(X[ub.voff[i]:ub.voff[i] + qp.n], ref.x, rtol=0, atol=1e-5)
