@@ -161,6 +161,15 @@ def test_grid_medium_parity(dtype):
     run_trace_case(qp, duq.DFGM, duq.LAST, K=30, engine=duq.ENGINE_GRID, dtype=dtype)
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_grid_unaligned_rows_parity(dtype):
+    """Odd n on the grid engine: rows are not 16-byte aligned, so the products
+    take the scalar path (same summation order) across every workgroup."""
+    print(f"[case] grid n=2049 dtype={np.dtype(dtype).name}", flush=True)
+    qp = gen.config1(n=2049, p=1023, seed=16)
+    run_trace_case(qp, duq.DFGM, duq.LAST, K=12, engine=duq.ENGINE_GRID, dtype=dtype)
+
+
 def test_fp32_storage_block_parity():
     print("[case] fp32 storage block", flush=True)
     qp = gen.random_dense_qp(301, 150, seed=5)
