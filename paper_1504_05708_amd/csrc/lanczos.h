@@ -11,6 +11,39 @@
 
 namespace duq {
 
+// xsum_strided for C columns at once: column c (c < nc) sums
+// base + c * cstep + b * stride over the same b sequence, each column in
+// exactly the order of xsum_strided, with 4 C loads in flight.
+template <int C>
+__device__ __forceinline__ void xsum_strided_cols(const double* base, long stride, long cstep, int nc, int first,
+                                                  int step, int nb, double (&s)[C]) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) s[c] = 0.0;
+    int b = first;
+    for (; b + 3 * step < nb; b += 4 * step) {
+        double v[C][4];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            if (c < nc) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[c][u] = xload(base + c * cstep + (long)(b + u * step) * stride);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            if (c < nc) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) s[c] += v[c][u];
+            }
+        }
+    }
+    for (; b < nb; b += step) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (c < nc) s[c] += xload(base + c * cstep + (long)b * stride);
+    }
+}
+
 template <typename T, bool SHORT>
 struct Lanczos {
     DevProblem<T> P;
@@ -40,21 +73,53 @@ struct Lanczos {
         const int n = P.n;
         const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
         const int ncol = k + 2;
-        for (int j = wid; j < m; j += nw) {
-            double s = 0.0;
-            for (int i = nlo + lane; i < nhi; i += kWave) s += vget(L.V + (long)j * n + i) * wget(w, i);
-            s = wave_sum(s);
-            if (lane == 0) {
-                if (tm.size == 1) hl[j] = s;
-                else xstore(L.part + (long)tm.rank * ncol + j, s);
+        // Wave wid owns the columns j = wid (mod nw) and takes C of them per
+        // trip, so C loads per lane are in flight; each column is summed in the
+        // same order whatever C is.
+        constexpr int C = 4;
+        for (int j0 = wid; j0 < m; j0 += C * nw) {
+            double s[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) s[c] = 0.0;
+            // opaque lane index: keeps the column addresses from being hoisted
+            // out of the Lanczos loop (they would stay live and spill)
+            int ln = lane;
+            asm volatile("" : "+v"(ln));
+            for (int i = nlo + ln; i < nhi; i += kWave) {
+                const double wi = wget(w, i);
+                double v[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    if (j0 + c * nw < m) v[c] = vget(L.V + (long)(j0 + c * nw) * n + i);
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    if (j0 + c * nw < m) s[c] += v[c] * wi;
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int j = j0 + c * nw;
+                if (j < m) {
+                    const double t = wave_sum(s[c]);
+                    if (lane == 0) {
+                        if (tm.size == 1) hl[j] = t;
+                        else xstore(L.part + (long)tm.rank * ncol + j, t);
+                    }
+                }
             }
         }
         if (tm.size == 1) { __syncthreads(); return true; }
         if (tm.sync()) return false;
-        for (int j = wid; j < m; j += nw) {
-            double s = xsum_strided(L.part + j, ncol, lane, kWave, tm.size);
-            s = wave_sum(s);
-            if (lane == 0) hl[j] = s;
+        for (int j0 = wid; j0 < m; j0 += C * nw) {
+            const int nc = min(C, (m - 1 - j0) / nw + 1);
+            double s[C];
+            xsum_strided_cols<C>(L.part + j0, ncol, (long)nw, nc, lane, kWave, tm.size, s);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                if (c < nc) {
+                    const double t = wave_sum(s[c]);
+                    if (lane == 0) hl[j0 + c * nw] = t;
+                }
+            }
         }
         __syncthreads();
         // the next writer of part must not overtake readers: barrier
@@ -84,10 +149,18 @@ struct Lanczos {
         gemvT_rows<T, double, true>(P.G, n, plo, phi, n, vl, L.gtp + (long)tm.rank * n, nullptr, true, tl);
         if (tm.sync()) return false;
         const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-        for (int j = nlo + wid; j < nhi; j += nw) {
-            double s = xsum_strided(L.gtp + j, n, lane, kWave, tm.size);
-            s = wave_sum(s);
-            if (lane == 0) w[j] = s;
+        constexpr int C = 4;
+        for (int j0 = nlo + wid; j0 < nhi; j0 += C * nw) {
+            const int nc = min(C, (nhi - 1 - j0) / nw + 1);
+            double s[C];
+            xsum_strided_cols<C>(L.gtp + j0, n, (long)nw, nc, lane, kWave, tm.size, s);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                if (c < nc) {
+                    const double t = wave_sum(s[c]);
+                    if (lane == 0) w[j0 + c * nw] = t;
+                }
+            }
         }
         __syncthreads();
         return true;
@@ -132,7 +205,15 @@ struct Lanczos {
                 aj += hl[j];
                 for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x) {
                     double s = L.w[i];
-                    for (int q = 0; q <= j; ++q) s -= hl[q] * vget(L.V + (long)q * n + i);
+                    int q = 0;
+                    for (; q + 8 <= j + 1; q += 8) {   // 8 basis entries in flight
+                        double v[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) v[u] = vget(L.V + (long)(q + u) * n + i);
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) s -= hl[q + u] * v[u];
+                    }
+                    for (; q <= j; ++q) s -= hl[q] * vget(L.V + (long)q * n + i);
                     L.w[i] = s;
                 }
                 __syncthreads();
