@@ -212,39 +212,63 @@ __device__ __forceinline__ int gemvT_rows(const T* A, long ld, int rlo, int rhi,
             return nz;
         }
     }
+    // Long rows: threads over 16-byte column vectors; thread t owns the vectors
+    // t + k * blockDim.x.  On a grid team (streamed, NT) a thread takes KC of
+    // them (16 columns) per pass, two rows per trip, so 2 KC loads are in
+    // flight instead of 2.  Every column is summed over the rows in ascending
+    // order, skipping zero weights, whatever KC is.
+    constexpr int KC = NT ? 16 / V : 1;
     const int nv = vec ? ncols / V : 0;
-    for (int cv = threadIdx.x; cv < nv; cv += blockDim.x) {
-        Acc acc[V];
+    const int bd = blockDim.x;
+    for (int c0 = threadIdx.x; c0 < nv; c0 += KC * bd) {
+        // opaque copy: keeps the KC column offsets from being hoisted out of
+        // the solver's loops (they would stay live and spill)
+        int cb = c0;
+        asm volatile("" : "+v"(cb));
+        const bool full = cb + (KC - 1) * bd < nv;
+        Acc acc[KC][V];
 #pragma unroll
-        for (int e = 0; e < V; ++e) acc[e] = 0;
+        for (int k = 0; k < KC; ++k)
+#pragma unroll
+            for (int e = 0; e < V; ++e) acc[k][e] = 0;
+        auto rows = [&](int r, int nr) {   // rows r .. r + nr - 1 (nr = 1 or 2)
+            VT a[2][KC];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                if (q < nr && vl[r + q - rlo] != 0.0) {
+                    const VT* row = reinterpret_cast<const VT*>(A + (long)(r + q) * ld) + cb;
+#pragma unroll
+                    for (int k = 0; k < KC; ++k)
+                        if (full || cb + k * bd < nv) a[q][k] = vload<T, NT>(row + k * bd);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const double vq = q < nr ? vl[r + q - rlo] : 0.0;
+                if (q < nr && vq != 0.0) {
+#pragma unroll
+                    for (int k = 0; k < KC; ++k)
+                        if (full || cb + k * bd < nv) {
+#pragma unroll
+                            for (int e = 0; e < V; ++e) acc[k][e] += (Acc)a[q][k][e] * (Acc)vq;
+                        }
+                }
+            }
+        };
         int r = rlo;
-        // two rows per trip keeps two loads in flight per thread
-        for (; r + 1 < rhi; r += 2) {
-            const double v0 = vl[r - rlo], v1 = vl[r - rlo + 1];
-            if (v0 != 0.0) {
-                VT a = vload<T, NT>(reinterpret_cast<const VT*>(A + (long)r * ld) + cv);
+        for (; r + 1 < rhi; r += 2) rows(r, 2);
+        if (r < rhi) rows(r, 1);
 #pragma unroll
-                for (int e = 0; e < V; ++e) acc[e] += (Acc)a[e] * (Acc)v0;
+        for (int k = 0; k < KC; ++k) {
+            const int cv = cb + k * bd;
+            if (cv < nv) {
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const int j = cv * V + e;
+                    const double val = (double)acc[k][e] + (add ? add[j] : 0.0);
+                    if (shared_dst) xstore(dst + j, val); else dst[j] = val;
+                }
             }
-            if (v1 != 0.0) {
-                VT a = vload<T, NT>(reinterpret_cast<const VT*>(A + (long)(r + 1) * ld) + cv);
-#pragma unroll
-                for (int e = 0; e < V; ++e) acc[e] += (Acc)a[e] * (Acc)v1;
-            }
-        }
-        if (r < rhi) {
-            const double v0 = vl[r - rlo];
-            if (v0 != 0.0) {
-                VT a = vload<T, NT>(reinterpret_cast<const VT*>(A + (long)r * ld) + cv);
-#pragma unroll
-                for (int e = 0; e < V; ++e) acc[e] += (Acc)a[e] * (Acc)v0;
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-            const int j = cv * V + e;
-            const double val = (double)acc[e] + (add ? add[j] : 0.0);
-            if (shared_dst) xstore(dst + j, val); else dst[j] = val;
         }
     }
     for (int j = nv * V + threadIdx.x; j < ncols; j += blockDim.x) {
