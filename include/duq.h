@@ -135,9 +135,24 @@ void duq_default_options(duq_options *o);
 
 /* Validate the problem (Sec. 2), move/borrow it to the device, derive the
  * constants (a1) and allocate the workspace.  On success *out owns all
- * device memory of the solve.  Errors: DUQ_EINVAL, DUQ_ENOMEM, DUQ_EDEVICE. */
+ * device memory of the solve.  Errors: DUQ_EINVAL, DUQ_ENOMEM, DUQ_EDEVICE.
+ * Size limit: every workgroup stages the whole iterate x in LDS (FP64), so n
+ * is bounded by the LDS of one workgroup less the engine's scratch: on the
+ * grid engine n <= 18 234 for 0 < p <= 256 with 160 KiB of LDS (one less per
+ * further 256 rows of G); the block engine also holds the p multipliers.  A
+ * larger n is DUQ_EINVAL (before any data is read or copied), and
+ * duq_last_error() states the exact bound; duq_max_n gives it in advance. */
 int duq_setup(const duq_problem *prob, const duq_options *opts, void *stream,
               duq_handle **out);
+
+/* Largest n that duq_setup accepts for a problem with p rows of G on
+ * `engine` (DUQ_ENGINE_BLOCK or DUQ_ENGINE_GRID; AUTO is answered for GRID,
+ * which AUTO uses above n = 1536) on the current device; the bound is the
+ * LDS of one workgroup, which holds the staged iterate x (Sec. 5.1 products,
+ * one double per variable) and the engine's reduction scratch.  Writes
+ * *n_max.  Errors: DUQ_EINVAL (null n_max, p < 0, other engine),
+ * DUQ_EDEVICE (no device). */
+int duq_max_n(int32_t p, int32_t engine, int32_t *n_max);
 
 /* Run Algorithm DFOM (Sec. 3) to the outer test.  x0 (n) warm-starts the
  * inner solver and lam0 (p) the multipliers (both host, may be NULL:

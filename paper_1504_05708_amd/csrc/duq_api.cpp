@@ -35,7 +35,7 @@ int fail(int code, const std::string& msg) {
 
 struct DeviceInfo {
     int cus = 0;
-    size_t lds_max = 0;
+    size_t lds_max = 0;   // dynamic LDS one workgroup may use (static LDS taken off)
 };
 
 int device_info(DeviceInfo* di) {
@@ -49,10 +49,32 @@ int device_info(DeviceInfo* di) {
     if (prop.maxSharedMemoryPerMultiProcessor > di->lds_max && prop.maxSharedMemoryPerMultiProcessor <= 160 * 1024)
         di->lds_max = prop.maxSharedMemoryPerMultiProcessor;
 #endif
+    const size_t st = dfom_static_lds_bytes();
+    di->lds_max = di->lds_max > st ? di->lds_max - st : 0;
     return DUQ_OK;
 }
 
 size_t esize(int dtype) { return dtype == DUQ_F64 ? 8 : 4; }
+
+// Launch shape of the single-QP solver: one workgroup (BLOCK) or one per CU
+// (GRID, at most one per variable).
+int solver_blocks(const DeviceInfo& di, int n, int engine) {
+    return engine == DUQ_ENGINE_BLOCK ? 1 : std::max(1, std::min(di.cus, n));
+}
+
+// Largest n whose LDS-staged iterate fits one workgroup for p rows of G (the
+// LDS use grows by one double per variable).  GRID assumes n >= CUs, which
+// holds near the bound.
+long solver_max_n(const DeviceInfo& di, int p, int engine) {
+    const size_t base = dfom_lds_bytes(0, p, engine == DUQ_ENGINE_BLOCK ? 1 : di.cus);
+    return base < di.lds_max ? (long)((di.lds_max - base) / sizeof(double)) : 0;
+}
+
+int too_large(const DeviceInfo& di, int n, int p, int engine) {
+    return fail(DUQ_EINVAL, "n = " + std::to_string(n) + " too large for the LDS-staged products: n <= " +
+                                std::to_string(solver_max_n(di, p, engine)) + " for p = " + std::to_string(p) +
+                                " on this engine (" + std::to_string(di.lds_max) + " bytes of dynamic LDS per workgroup)");
+}
 
 bool finite_all(const double* a, long len) {
     for (long i = 0; i < len; ++i)
@@ -243,6 +265,20 @@ int derive_params(int p, double lam_min, double lam_max, double g2, double D_U, 
 }
 }
 
+extern "C" int duq_max_n(int32_t p, int32_t engine, int32_t* n_max) {
+    if (!n_max) return fail(DUQ_EINVAL, "null n_max");
+    *n_max = 0;
+    if (p < 0) return fail(DUQ_EINVAL, "p < 0");
+    if (engine == DUQ_ENGINE_AUTO) engine = DUQ_ENGINE_GRID;
+    if (engine != DUQ_ENGINE_BLOCK && engine != DUQ_ENGINE_GRID)
+        return fail(DUQ_EINVAL, "duq_max_n: engine must be AUTO, BLOCK or GRID");
+    DeviceInfo di;
+    int rc = device_info(&di);
+    if (rc) return rc;
+    *n_max = (int32_t)std::min<long>(solver_max_n(di, p, engine), INT32_MAX);
+    return DUQ_OK;
+}
+
 extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* stream, duq_handle** out) {
     if (!out) return fail(DUQ_EINVAL, "null output handle");
     *out = nullptr;
@@ -252,6 +288,9 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
     const long nn = (long)n * n, pn = (long)p * n;
     DeviceInfo di;
     if ((rc = device_info(&di))) return rc;
+    int engine = opts->engine;
+    if (engine == DUQ_ENGINE_AUTO) engine = (n <= 1536) ? DUQ_ENGINE_BLOCK : DUQ_ENGINE_GRID;
+    if (dfom_lds_bytes(n, p, solver_blocks(di, n, engine)) > di.lds_max) return too_large(di, n, p, engine);
 
     duq_handle* h = new (std::nothrow) duq_handle();
     if (!h) return fail(DUQ_ENOMEM, "host allocation");
@@ -355,8 +394,6 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
     }
 
     // engine and launch shape
-    int engine = opts->engine;
-    if (engine == DUQ_ENGINE_AUTO) engine = (n <= 1536) ? DUQ_ENGINE_BLOCK : DUQ_ENGINE_GRID;
     h->engine = engine;
     const int acc_first = opts->accumulate;
     if (engine == DUQ_ENGINE_BLOCK) {
@@ -372,10 +409,9 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
     }
     h->cfg.stream = h->stream;
     h->cfg.shmem = dfom_lds_bytes(n, p, h->cfg.nblocks);
-    if (h->cfg.shmem > di.lds_max) {
+    if (h->cfg.shmem > di.lds_max) {   // checked before any data moved; kept as a guard
         duq_destroy(h);
-        return fail(DUQ_EINVAL, "n too large for the LDS-staged products of this build (n + p/blocks <= " +
-                                    std::to_string(di.lds_max / 8) + ")");
+        return too_large(di, n, p, engine);
     }
     if (h->cfg.cooperative) {
         for (int acc = 0; acc <= (dtype == DUQ_F32 ? 1 : 0); ++acc) {

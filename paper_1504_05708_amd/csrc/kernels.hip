@@ -92,6 +92,25 @@ static const void* dfom_fn(int dtype, int acc, int n) {
     return sh ? dfom_fn_t<true>(dtype, acc) : dfom_fn_t<false>(dtype, acc);
 }
 
+size_t dfom_static_lds_bytes() {
+    static size_t bytes = [] {
+        const void* fns[] = {dfom_fn_t<true>(0, 0), dfom_fn_t<true>(1, 0), dfom_fn_t<true>(1, 1),
+                             dfom_fn_t<false>(0, 0), dfom_fn_t<false>(1, 0), dfom_fn_t<false>(1, 1),
+                             reinterpret_cast<const void*>(&lanczos_kernel<double, true>),
+                             reinterpret_cast<const void*>(&lanczos_kernel<double, false>),
+                             reinterpret_cast<const void*>(&lanczos_kernel<float, true>),
+                             reinterpret_cast<const void*>(&lanczos_kernel<float, false>)};
+        size_t m = 0;
+        for (const void* f : fns) {
+            hipFuncAttributes a;
+            // unknown: reserve a small margin rather than none
+            m = std::max(m, hipFuncGetAttributes(&a, f) == hipSuccess ? (size_t)a.sharedSizeBytes : (size_t)256);
+        }
+        return m;
+    }();
+    return bytes;
+}
+
 hipError_t dfom_occupancy(int dtype, int acc, int n, int nthreads, size_t shmem, int* blocks_per_cu) {
     const void* f = dfom_fn(dtype, acc, n);
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);

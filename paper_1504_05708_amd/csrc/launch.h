@@ -113,6 +113,9 @@ hipError_t tile_occupancy(int dtype, size_t shmem, int* blocks_per_cu);
 hipError_t launch_tile(int dtype, int nblocks, size_t shmem, hipStream_t stream, const TileLaunch& t);
 
 size_t dfom_lds_bytes(int n, int p, int nblocks);
+// Static LDS of the solver and Lanczos kernels (largest instantiation); the
+// dynamic LDS of a launch may use what is left of the workgroup's LDS.
+size_t dfom_static_lds_bytes();
 size_t lanczos_lds_bytes(int n, int p, int nblocks, int k);
 hipError_t dfom_occupancy(int dtype, int acc, int n, int nthreads, size_t shmem, int* blocks_per_cu);
 hipError_t launch_dfom(int dtype, int acc, const LaunchCfg& cfg, const GenericProblem& gp,

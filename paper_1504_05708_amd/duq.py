@@ -33,7 +33,7 @@ BATCH_UNEVEN, BATCH_SHARED = 0, 1
 
 SERVE_BATCH_NMAX = 1536
 
-EXPORTS = ["duq_default_options", "duq_setup", "duq_solve", "duq_get_trace", "duq_get_constants",
+EXPORTS = ["duq_default_options", "duq_setup", "duq_max_n", "duq_solve", "duq_get_trace", "duq_get_constants",
            "duq_destroy", "duq_last_error", "duq_strerror", "duq_solve_batch", "duq_server_create",
            "duq_register_shared", "duq_submit", "duq_poll", "duq_server_destroy"]
 
@@ -118,6 +118,8 @@ def lib() -> ctypes.CDLL:
     L.duq_setup.restype = c_int32
     L.duq_solve.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(DuqResult)]
     L.duq_solve.restype = c_int32
+    L.duq_max_n.argtypes = [c_int32, c_int32, POINTER(c_int32)]
+    L.duq_max_n.restype = c_int32
     L.duq_get_trace.argtypes = [c_void_p, c_void_p, c_int32, POINTER(c_int32)]
     L.duq_get_trace.restype = c_int32
     L.duq_get_constants.argtypes = [c_void_p] + [POINTER(c_double)] * 6
@@ -147,6 +149,16 @@ def lib() -> ctypes.CDLL:
 
 def last_error() -> str:
     return lib().duq_last_error().decode()
+
+
+def max_n(p: int, engine: int = 2) -> int:
+    """duq_max_n: largest n duq_setup accepts for p rows of G on `engine`
+    (default DUQ_ENGINE_GRID) on the current device."""
+    v = c_int32()
+    rc = lib().duq_max_n(p, engine, ctypes.byref(v))
+    if rc != DUQ_OK:
+        raise DuqError(rc, last_error())
+    return v.value
 
 
 def default_options(**kw) -> DuqOptions:

@@ -97,6 +97,31 @@ def fresh_linear_terms(G: np.ndarray, seed, s_lo: float = 0.1, s_hi: float = 1.0
     return q, -(G @ x0) - s
 
 
+def separable_terms(n: int, seed=7, box: float = 1.0):
+    """Diagonal QP with one dense constraint row, drawn so that the row is
+    active: d ~ U(1, 2) (Q = diag(d)), a ~ N(0, 1), q = -d * (0.8 sign(a) + 0.1 z)
+    with z ~ N(0, 1), and b = a^T x0 + s with x0 ~ U(-1/2, 1/2)^n, s ~ U(0.1, 1)
+    (x0 strictly feasible); the row is a^T u - b <= 0, box [-box, box].
+    Draw order d, a, z, x0, s.  Returns (d, q, a, b, lb, ub); Q is never formed
+    here, so n can be as large as the device allows."""
+    rng = _rng(seed)
+    d = rng.uniform(1.0, 2.0, n)
+    a = rng.standard_normal(n)
+    z = rng.standard_normal(n)
+    q = -d * (0.8 * np.sign(a) + 0.1 * z)
+    x0 = rng.uniform(-0.5, 0.5, n)
+    s = rng.uniform(0.1, 1.0)
+    b = float(a @ x0 + s)
+    return d, q, a, b, np.full(n, -box), np.full(n, box)
+
+
+def separable_qp(n: int, seed=7) -> QP:
+    """separable_terms as a dense QP (small n)."""
+    d, q, a, b, lb, ub = separable_terms(n, seed)
+    return QP(np.diag(d), q, a[None, :].copy(), np.array([-b]), lb, ub,
+              dict(kind="separable", n=n, p=1, seed=seed))
+
+
 def config0() -> QP:
     """Small dense QP: n=50, p=25, reg 0.1, seed 0."""
     return random_dense_qp(50, 25, seed=0, reg=0.1)

@@ -192,6 +192,45 @@ def test_config1_full_size_first_iterations():
     run_trace_case(qp, duq.DFGM, duq.LAST, K=2, engine=duq.ENGINE_GRID)
 
 
+def test_grid_maximum_size():
+    # The largest n the grid engine accepts (every workgroup stages x in LDS):
+    # a diagonal QP with one dense active row, pinned by its closed form (the
+    # multiplier by bisection); n + 1 is rejected with the bound in the message.
+    import torch
+    import separable
+    n = duq.max_n(1, duq.ENGINE_GRID)
+    print(f"[case] grid maximum size n={n} p=1", flush=True)
+    assert 8192 < n < (1 << 20)
+    d, q, a, b, lb, ub = gen.separable_terms(n, seed=7)
+    dev = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()
+    Q = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    Q.diagonal().copy_(dev(d))
+    kw = dict(engine=duq.ENGINE_GRID, method=duq.DFGM, eps_out=1e-4, eps_in=1e-8,
+              lam_min=float(d.min()), lam_max=float(d.max()), G_norm2=float(a @ a))
+    with duq.Solver(Q, dev(q), dev(a[None, :]), dev(np.array([-b])), dev(lb), dev(ub), **kw) as s:
+        x, lam, res = s.solve()
+    x = x.cpu().numpy() if hasattr(x, "cpu") else np.asarray(x)
+    assert res["engine"] == duq.ENGINE_GRID and res["status"] == duq.DUQ_OK
+    u, m, F = separable.solve(d, q, a, b, lb, ub)
+    dF, lower, dist, lag_gap = separable.error_bounds(x, d, q, a, b, lb, ub)
+    scale = max(1.0, abs(F))
+    assert np.all(x >= lb) and np.all(x <= ub)
+    assert a @ x - b <= 1e-4 * max(1.0, abs(b))             # feasibility test of the outer loop
+    assert dF <= 1.1e-4 * scale and dF >= lower - 1e-9 * scale  # F - LB test; weak duality
+    assert np.linalg.norm(x - u) <= dist + 1e-9 and dist <= 1e-2 * np.linalg.norm(u)
+    del Q
+    torch.cuda.empty_cache()
+    n1 = n + 1
+    d, q, a, b, lb, ub = gen.separable_terms(n1, seed=7)
+    Q = torch.zeros((n1, n1), dtype=torch.float64, device="cuda")
+    Q.diagonal().copy_(dev(d))
+    with pytest.raises(duq.DuqError) as e:
+        duq.Solver(Q, dev(q), dev(a[None, :]), dev(np.array([-b])), dev(lb), dev(ub), **kw)
+    assert e.value.code == duq.DUQ_EINVAL and f"n <= {n} " in str(e.value)
+    del Q
+    torch.cuda.empty_cache()
+
+
 # ----------------------------------------------------------------------------
 # constants (Lanczos) and robustness
 # ----------------------------------------------------------------------------

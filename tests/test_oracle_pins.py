@@ -130,6 +130,24 @@ def test_single_active_row_closed_form():
     np.testing.assert_allclose(r.lam, sol[n:], rtol=1e-4)
 
 
+def test_separable_one_row_closed_form():
+    # diagonal Q, one dense active row: optimum by bisection on the multiplier
+    import separable
+    qp = gen.separable_qp(48, seed=7)
+    d, q, a, b = np.diag(qp.Q).copy(), qp.q, qp.G[0], -qp.g[0]
+    u, m, F = separable.solve(d, q, a, b, qp.lb, qp.ub)
+    assert m > 0.0 and abs(a @ u - b) < 1e-12          # the row is active
+    r = dfom_solve(qp, Options(method=DFGM, eps_out=1e-10, eps_in=1e-15, max_outer=200000))
+    assert r.status == dfom.STATUS_OK
+    np.testing.assert_allclose(r.x, u, atol=1e-6)
+    np.testing.assert_allclose(r.lam, [m], rtol=1e-5)
+    # the bounds the large-n GPU test relies on hold for a loose solve too
+    r = dfom_solve(qp, Options(method=DFGM, eps_out=1e-4, eps_in=1e-8))
+    dF, lower, dist, lag_gap = separable.error_bounds(r.x, d, q, a, b, qp.lb, qp.ub)
+    assert lag_gap >= -1e-12 and dF >= lower - 1e-12
+    assert np.linalg.norm(r.x - u) <= dist + 1e-9
+
+
 # ----------------------------------------------------------------------------
 # P3: KKT and an independent solver at the config-0 size
 # ----------------------------------------------------------------------------
