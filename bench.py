@@ -131,7 +131,7 @@ def reference_fstar(key):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
+        print(f"bench.py: runs on one GPU only (asked for --gpus {a.gpus}); "
               "the single large QP would shard by rows over RCCL, which is not built.", file=sys.stderr)
         sys.exit(2)
     if a.print_source_hash:
