@@ -43,6 +43,10 @@ extern "C" {
 #define DUQ_ENUMERIC    -5   /* NaN/Inf produced during the iteration             */
 #define DUQ_EAGAIN      -6   /* request not finished yet (duq_poll)               */
 #define DUQ_ENOTFOUND   -7   /* unknown ticket or id                              */
+#define DUQ_EINFEASIBLE -8   /* no point of the box satisfies G u + g <= 0: the
+                                multipliers returned are a certificate mu >= 0 with
+                                min over the box of mu^T (G u + g) > 0; x is the
+                                last iterate (rho = 0; not on the TILE engine)     */
 
 /* ---- enumerations ------------------------------------------------------ */
 enum { DUQ_F64 = 0, DUQ_F32 = 1, DUQ_BF16 = 2 };            /* storage of Q, G   */
@@ -112,7 +116,7 @@ typedef struct duq_options {
  * with LB a certified lower bound on F* (weak duality minus the inner
  * certificate).                                                              */
 typedef struct duq_result {
-    int32_t status;         /* DUQ_OK, DUQ_EMAXITER, DUQ_ENUMERIC                */
+    int32_t status;         /* DUQ_OK, DUQ_EMAXITER, DUQ_ENUMERIC, DUQ_EINFEASIBLE */
     int32_t outer_iters;
     int64_t inner_iters;    /* total inner FOM steps (products with Q)           */
     int64_t gt_rows;        /* rows of G touched by G^T v products (sparsity)    */
@@ -158,8 +162,13 @@ int duq_max_n(int32_t p, int32_t engine, int32_t *n_max);
  * inner solver and lam0 (p) the multipliers (both host, may be NULL:
  * x0 = projection of 0 onto the box, lam0 = 0, Sec. 4).  x_out (n) and
  * lam_out (p) are host buffers (may be NULL).  Returns the result status
- * (DUQ_OK, DUQ_EMAXITER with the last iterate written, DUQ_ENUMERIC) or an
- * error code.                                                               */
+ * (DUQ_OK, DUQ_EMAXITER with the last iterate written, DUQ_ENUMERIC,
+ * DUQ_EINFEASIBLE with the certificate in lam_out) or an error code.  With
+ * rho = 0, before the inner solve of outer iterations k = 1, 9, 17, ... the
+ * multipliers mu^k (when all >= 0) are tested as a certificate of
+ * infeasibility; the paper assumes a finite
+ * optimal multiplier (Sec. 2), i.e. a feasible problem, and this test ends
+ * the run early when there is none.                                         */
 int duq_solve(duq_handle *h, const double *x0, const double *lam0,
               double *x_out, double *lam_out, duq_result *res);
 
@@ -218,8 +227,9 @@ typedef struct duq_batch {
  * (device buffers) directly and nothing crosses PCIe but `res`.  X_out (sum n_i, or B x n) and
  * Lam_out (sum p_i, or B x p) are host buffers laid out like q and g; res has
  * B entries (time_ms is the batch's device time).  Returns DUQ_OK when every
- * instance passed its outer test, DUQ_EMAXITER / DUQ_ENUMERIC when one did
- * not (see res[i].status), or an error code.                                */
+ * instance passed its outer test, DUQ_EMAXITER / DUQ_ENUMERIC /
+ * DUQ_EINFEASIBLE (BLOCK engine) when one did not (see res[i].status), or an
+ * error code.                                                               */
 int duq_solve_batch(const duq_batch *batch, const duq_options *opts, void *stream,
                     double *X_out, double *Lam_out, duq_result *res);
 
@@ -279,7 +289,8 @@ int duq_submit(duq_server *s, const duq_request *req, uint64_t *ticket);
 /* DUQ_EAGAIN while the request is queued or running.  Once it has finished,
  * writes x_out (n), lam_out (p) and res (any may be NULL; res->time_ms is the
  * latency from duq_submit to completion), forgets the ticket and returns the
- * request's status (DUQ_OK, DUQ_EMAXITER, DUQ_ENUMERIC or an error code).
+ * request's status (DUQ_OK, DUQ_EMAXITER, DUQ_ENUMERIC, DUQ_EINFEASIBLE or an
+ * error code).
  * DUQ_ENOTFOUND for a ticket that is unknown or already collected.          */
 int duq_poll(duq_server *s, uint64_t ticket, double *x_out, double *lam_out, duq_result *res);
 

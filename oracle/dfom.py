@@ -44,6 +44,11 @@ design notes):
     passes the test, one more inner solve at lambda^k, warm-started from
     ubar^k, is tested and returned if it passes; otherwise the iteration
     continues from ubar^k unchanged (the extra solve only raises LB).
+  * Infeasible constraints (outside the paper, which assumes a finite
+    optimal multiplier, Sec. 2): with rho = 0, before each inner solve a
+    mu^k >= 0 is tested as a certificate that no u in U has G u + g <= 0
+    (infeasibility_certificate); the run then ends with mu^k as the
+    multipliers and the warm start as x.
 """
 from __future__ import annotations
 
@@ -60,6 +65,12 @@ INNER_AUTO, INNER_GM, INNER_FGM, INNER_FGM_SIGMA = 0, 1, 2, 3
 
 STATUS_OK = 0
 STATUS_MAXITER = 1
+STATUS_INFEASIBLE = 2
+
+# Relative margin of the infeasibility certificate (see infeasibility_certificate)
+# and the outer iterations at which it is tested: k = 1, 1 + INFEAS_EVERY, ...
+INFEAS_MARGIN = 1e-6
+INFEAS_EVERY = 8
 
 
 @dataclass
@@ -302,6 +313,22 @@ def _outer_test(Q, q, G, g, x, lam, LB, eps, gnorm):
     return ok, Fx, feas
 
 
+def infeasibility_certificate(G, g, lb, ub, mu):
+    """v = min over the box U of mu^T (G u + g), and the scale of its terms.
+
+    The paper assumes a finite optimal multiplier exists (Sec. 2, strong
+    duality).  When no point of U satisfies G u + g <= 0 the dual is unbounded
+    above and the multipliers grow without bound; a mu >= 0 with v > 0 proves
+    it: every u in U has mu^T (G u + g) >= v > 0, so some row is violated.
+    The box minimum is separable: sum_j min(lb_j w_j, ub_j w_j), w = G^T mu.
+    Returns (v, scale) with scale = sum |mu_i g_i| + sum |w_j| max(|lb_j|, |ub_j|);
+    the run stops when v > INFEAS_MARGIN * scale."""
+    w = G.T @ mu
+    v = float(mu @ g + np.sum(np.minimum(lb * w, ub * w)))
+    scale = float(np.sum(np.abs(mu * g)) + np.sum(np.abs(w) * np.maximum(np.abs(lb), np.abs(ub))))
+    return v, scale
+
+
 def dfom_solve(qp, opts: Options, consts: Optional[Constants] = None,
                x_start=None, lam_start=None) -> Result:
     """Inexact (augmented) dual first-order method DFOM(d_rho, K_d)."""
@@ -329,6 +356,15 @@ def dfom_solve(qp, opts: Options, consts: Optional[Constants] = None,
     last = None
 
     for k in range(1, opts.max_outer + 1):
+        # Before step 1 (rho = 0, mu^k >= 0): a Farkas-type certificate that
+        # no feasible point exists ends the run with mu^k as the certificate.
+        if rho == 0.0 and p > 0 and k % INFEAS_EVERY == 1 and np.all(mu >= 0.0):
+            v, scale = infeasibility_certificate(G, g, lb, ub, mu)
+            if v > INFEAS_MARGIN * scale:
+                Fx = objective(Q, q, x_warm)
+                feas = float(np.linalg.norm(np.maximum(G @ x_warm + g, 0.0)))
+                return Result(x_warm.copy(), mu.copy(), Fx, LB, feas, STATUS_INFEASIBLE,
+                              k, inner_total, c, log)
         # Step 1: ubar^k approximately minimises L_rho(., mu^k) over U
         u, t, gap = fom_inner(Q, q, G, g, lb, ub, mu, rho, c, x_warm,
                               opts.eps_in, opts.inner_rule, opts.inner_variant)

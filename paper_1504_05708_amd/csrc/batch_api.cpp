@@ -68,7 +68,10 @@ bool all_finite(const T* a, long long len) {
 
 namespace {
 
-int to_status(int s) { return s == 0 ? DUQ_OK : s == 2 ? DUQ_ENUMERIC : s == 4 ? DUQ_EINVAL : DUQ_EMAXITER; }
+int to_status(int s) {
+    return s == 0 ? DUQ_OK : s == 2 ? DUQ_ENUMERIC : s == 4 ? DUQ_EINVAL : s == kStInfeasible ? DUQ_EINFEASIBLE
+                                                                                               : DUQ_EMAXITER;
+}
 
 // Shared-Hessian batch on the MFMA tile kernel: constants and derived
 // parameters from the single-QP setup of the shared data (Lanczos estimate
@@ -490,10 +493,7 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
     int code = DUQ_OK;
     for (int i = 0; i < B; ++i) {
         const BatchResultDev& r = rd[i];
-        int st = r.status == 0 ? DUQ_OK
-                 : r.status == 2 ? DUQ_ENUMERIC
-                 : r.status == 4 ? DUQ_EINVAL
-                                 : DUQ_EMAXITER;
+        const int st = to_status(r.status);
         if (st != DUQ_OK && code == DUQ_OK) code = st;
         if (res) {
             duq_result& q = res[i];

@@ -572,9 +572,33 @@ struct Dfom {
         }
     }
 
-    __device__ __forceinline__ int inner(int& cur, const double* mu, double& gap) {
+    // Inner solve at mu.  farkas (rho = 0): first test mu as a certificate of
+    // infeasibility and return -3 if it is one.  The method assumes a finite
+    // optimal multiplier exists (Sec. 2); a mu >= 0 with
+    //   v = min over the box of mu^T (G u + g) = mu^T g + sum_j min(lb_j w_j, ub_j w_j),
+    // w = G^T mu = c - q, above kInfeasMargin times the sum of the magnitudes
+    // of its terms proves that no u in the box has G u + g <= 0.  The test
+    // takes one team reduction; it runs at every kInfeasEvery-th outer
+    // iteration, outside the inner loop.
+    __device__ __forceinline__ int inner(int& cur, const double* mu, double& gap, bool farkas) {
         if (par.rho > 0.0) return inner_rhop(cur, mu, gap);
         if (!gemvT(mu, P.q, W.c)) return -1;   // c = q + G^T mu (Sec. 5.1)
+        if (farkas && P.p > 0) {
+            double e[3] = {0.0, 0.0, 0.0};   // v, scale, #(mu < 0)
+            for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x) {
+                const double w = W.c[i] - P.q[i], lo = P.lb[i], hi = P.ub[i];
+                e[0] += fmin(lo * w, hi * w);
+                e[1] += fabs(w) * fmax(fabs(lo), fabs(hi));
+            }
+            for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) {
+                const double m = mu[i], mg = m * P.g[i];
+                e[0] += mg;
+                e[1] += fabs(mg);
+                e[2] += m < 0.0 ? 1.0 : 0.0;
+            }
+            if (!allreduce<3>(e)) return -1;
+            if (e[2] == 0.0 && e[0] > kInfeasMargin * e[1]) return -3;
+        }
         return inner_rho0(cur, W.c, gap);
     }
 
@@ -672,9 +696,19 @@ struct Dfom {
             ++k;
             // Step 1: inner solve at mu^k, warm-started from ubar^{k-1}
             double gap = 0.0;
-            const int t = inner(cur, W.mu, gap);
+            const int t = inner(cur, W.mu, gap, k % kInfeasEvery == 1);
             if (t == -1) return;
             if (t == -2) { status = 2; break; }
+            if (t == -3) {
+                // mu^k certifies infeasibility: it is returned as the multiplier,
+                // the warm start ubar^{k-1} as the iterate
+                for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) W.lamp[i] = W.mu[i];
+                __syncthreads();
+                status = kStInfeasible;
+                ans_cur = cur;
+                ans_avg = false;
+                break;
+            }
             inner_total += t;
             residual(cur);
             // Steps 2-3 and averaging on owned rows / variables
@@ -761,7 +795,7 @@ struct Dfom {
                 __syncthreads();
                 int c2 = cur;
                 double gap2 = 0.0;
-                const int t2 = inner(c2, W.lamp, gap2);
+                const int t2 = inner(c2, W.lamp, gap2, false);
                 if (t2 == -1) return;
                 if (t2 == -2) { status = 2; break; }
                 inner_total += t2;

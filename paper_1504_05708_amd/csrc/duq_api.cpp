@@ -179,6 +179,7 @@ const char* duq_strerror(int code) {
         case DUQ_ENUMERIC: return "non-finite value in the iteration";
         case DUQ_EAGAIN: return "not ready";
         case DUQ_ENOTFOUND: return "not found";
+        case DUQ_EINFEASIBLE: return "infeasible constraints (certificate returned)";
         default: return "unknown";
     }
 }
@@ -630,7 +631,7 @@ extern "C" int duq_solve(duq_handle* h, const double* x0, const double* lam0, do
         HIP_TRY(hipStreamSynchronize(h->stream));
         if (bar_err) return fail(DUQ_EDEVICE, "grid barrier timeout (a workgroup did not arrive)");
         k_phase1 = st.k;
-        if (st.status != 2 && st.k < o.max_outer) {
+        if (st.status != 2 && st.status != kStInfeasible && st.k < o.max_outer) {
             DevParams p2 = par;
             p2.resume = 1;
             HIP_TRY(hipMemsetAsync(h->W.bar, 0, bar_words(h->cfg.nblocks) * sizeof(unsigned), h->stream));
@@ -650,7 +651,10 @@ extern "C" int duq_solve(duq_handle* h, const double* x0, const double* lam0, do
     HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
     if (bar_err) return fail(DUQ_EDEVICE, "grid barrier timeout (a workgroup did not arrive)");
     h->last_records = st.n_trace;
-    int code = st.status == 0 ? DUQ_OK : (st.status == 2 ? DUQ_ENUMERIC : DUQ_EMAXITER);
+    int code = st.status == 0                ? DUQ_OK
+               : st.status == 2             ? DUQ_ENUMERIC
+               : st.status == kStInfeasible ? DUQ_EINFEASIBLE
+                                            : DUQ_EMAXITER;
     if (res) {
         std::memset(res, 0, sizeof(*res));
         res->status = code;
@@ -670,6 +674,7 @@ extern "C" int duq_solve(duq_handle* h, const double* x0, const double* lam0, do
     }
     if (code == DUQ_ENUMERIC) g_err = "non-finite value during the iteration";
     if (code == DUQ_EMAXITER) g_err = "max_outer reached";
+    if (code == DUQ_EINFEASIBLE) g_err = "the constraints have no solution in the box (certificate returned as the multipliers)";
     return code;
 }
 

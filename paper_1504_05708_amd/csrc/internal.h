@@ -12,6 +12,13 @@ constexpr int kBarErr = 32;
 constexpr int kBarFlag = 64;
 constexpr long bar_words(int nblocks) { return (long)kBarFlag + 32L * (nblocks + 1); }
 
+// Solver status of a run that found a certificate of infeasibility, the
+// relative margin that certificate must clear and the outer iterations at
+// which it is tested, k = 1, 1 + kInfeasEvery, ... (see Dfom::inner_rho0).
+constexpr int kStInfeasible = 5;
+constexpr double kInfeasMargin = 1e-6;
+constexpr int kInfeasEvery = 8;
+
 // Scalars of one trace record.
 constexpr int kTraceScalars = 16;
 
@@ -58,7 +65,7 @@ struct DevParams {
 // Scalar solver state kept in device memory between launches and the
 // final result of a solve.
 struct DevState {
-    int status;        // 0 running/ok, 1 maxiter, 2 numeric, 3 barrier timeout
+    int status;        // 0 ok, 1 max outer, 2 numeric, 3 phase-1 stall, 5 infeasible
     int done;          // outer test passed
     int k;             // outer iterations completed
     int cur;           // index of the warm-start buffer
@@ -99,12 +106,12 @@ struct DevWork {
     const double* x0;  // optional warm start (device)
     const double* lam0;
     DevState* st;
-    unsigned* bar;     // [0] arrival count, [1] generation, [2] error flag
+    unsigned* bar;     // grid-barrier words (kBarErr: error flag)
 };
 
 // Per-instance result of a batched solve.
 struct BatchResultDev {
-    int status;          // 0 ok, 1 max outer, 2 numeric, 4 invalid constants
+    int status;          // 0 ok, 1 max outer, 2 numeric, 4 invalid constants, 5 infeasible
     int outer;
     long long inner;
     long long gt_rows;

@@ -125,7 +125,11 @@ struct Req {
 };
 
 int to_code(int status) {
-    return status == 0 ? DUQ_OK : status == 2 ? DUQ_ENUMERIC : status == 4 ? DUQ_EINVAL : DUQ_EMAXITER;
+    return status == 0 ? DUQ_OK
+           : status == 2 ? DUQ_ENUMERIC
+           : status == 4 ? DUQ_EINVAL
+           : status == kStInfeasible ? DUQ_EINFEASIBLE
+                                     : DUQ_EMAXITER;
 }
 
 template <typename T>

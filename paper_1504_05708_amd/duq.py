@@ -19,6 +19,9 @@ LIB_PATH = os.path.join(HERE, "libduq.so")
 
 DUQ_OK, DUQ_EINVAL, DUQ_ENOMEM, DUQ_EDEVICE, DUQ_EMAXITER, DUQ_ENUMERIC, DUQ_EAGAIN, DUQ_ENOTFOUND = \
     0, -1, -2, -3, -4, -5, -6, -7
+DUQ_EINFEASIBLE = -8
+# outcomes of a solve that still write x and the multipliers
+SOLVE_OUTCOMES = (DUQ_OK, DUQ_EMAXITER, DUQ_EINFEASIBLE)
 F64, F32, BF16 = 0, 1, 2
 HOST, DEVICE = 0, 1
 DGM, DFGM = 0, 1
@@ -231,7 +234,7 @@ class Solver:
         l0a = None if lam0 is None else np.ascontiguousarray(lam0, dtype=np.float64)
         rc = lib().duq_solve(self._h, _ptr(x0a), _ptr(l0a), _ptr(x), _ptr(lam) if self.p else None,
                              ctypes.byref(res))
-        if check and rc not in (DUQ_OK, DUQ_EMAXITER):
+        if check and rc not in SOLVE_OUTCOMES:
             raise DuqError(rc, last_error())
         return x, lam, res.as_dict()
 
@@ -341,7 +344,7 @@ def _run_batch(b, B, nx, nl, check, opts):
         Lam = np.empty(max(nl, 1))
     res = (DuqResult * B)()
     rc = lib().duq_solve_batch(ctypes.byref(b), ctypes.byref(o), c_void_p(None), _ptr(X), _ptr(Lam), res)
-    if check and rc not in (DUQ_OK, DUQ_EMAXITER):
+    if check and rc not in SOLVE_OUTCOMES:
         raise DuqError(rc, last_error())
     return X[:nx], Lam[:nl], Results(res)
 

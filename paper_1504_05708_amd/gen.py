@@ -122,6 +122,27 @@ def separable_qp(n: int, seed=7) -> QP:
               dict(kind="separable", n=n, p=1, seed=seed))
 
 
+def infeasible_qp(kind: str, seed=1, n: int = 5) -> QP:
+    """Small strongly convex QP whose constraints have no solution in the box
+    [-1, 1]^n.  kind "pair": rows a and -a with g = (0.3, 0.2) (their sum
+    reads 0.5 <= 0) plus a slack row; kind "triple": rows b1, b2, -(b1 + b2)
+    with g = (0.1, 0.2, 0.3) (their sum reads 0.6 <= 0).  Q = A^T A / n + I/2
+    with A ~ N(0,1)^{n x n}, q ~ N(0, 1).  Draw order A, q, then the rows."""
+    rng = _rng(seed)
+    A = rng.standard_normal((n, n))
+    Q = A.T @ A / n + 0.5 * np.eye(n)
+    q = rng.standard_normal(n)
+    if kind == "pair":
+        a = rng.standard_normal(n)
+        G = np.stack([a, -a, rng.standard_normal(n)])
+        g = np.array([0.3, 0.2, -5.0])
+    else:
+        B = rng.standard_normal((2, n))
+        G = np.stack([B[0], B[1], -(B[0] + B[1])])
+        g = np.array([0.1, 0.2, 0.3])
+    return QP(Q, q, G, g, -np.ones(n), np.ones(n), dict(kind="infeasible_" + kind, n=n, p=3, seed=seed))
+
+
 def config0() -> QP:
     """Small dense QP: n=50, p=25, reg 0.1, seed 0."""
     return random_dense_qp(50, 25, seed=0, reg=0.1)
@@ -266,6 +287,18 @@ class UnevenBatch:
         sc = slice(self.coff[i], self.coff[i] + p)
         return QP(Q, self.q[sl].copy(), G, self.g[sc].copy(),
                   self.lb[sl].copy(), self.ub[sl].copy(), dict(kind="uneven", index=i))
+
+
+def pack_uneven(qps, dtype=np.float64) -> "UnevenBatch":
+    """Pack a list of QPs into an UnevenBatch (instances in list order)."""
+    n = np.array([qp.n for qp in qps], dtype=np.int32)
+    p = np.array([qp.p for qp in qps], dtype=np.int32)
+    off = lambda sizes: np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    n64, p64 = n.astype(np.int64), p.astype(np.int64)
+    cat = lambda parts, dt=np.float64: (np.concatenate(parts).astype(dt) if parts else np.zeros(0, dt))
+    return UnevenBatch(n, p, cat([qp.Q.ravel() for qp in qps], dtype), cat([qp.G.ravel() for qp in qps], dtype),
+                       cat([qp.q for qp in qps]), cat([qp.g for qp in qps]), cat([qp.lb for qp in qps]),
+                       cat([qp.ub for qp in qps]), off(n64 * n64), off(p64 * n64), off(n64), off(p64))
 
 
 def _uneven_chunk(args):

@@ -45,6 +45,33 @@ def test_uneven_batch_matches_oracle_per_instance(dtype):
         np.testing.assert_allclose(lam, ref.lam, rtol=0, atol=1e-7 * max(1, np.abs(ref.lam).max()))
 
 
+def test_uneven_batch_with_infeasible_instances():
+    # infeasible instances end with their certificate; the others are unaffected
+    print("[case] uneven batch with infeasible instances", flush=True)
+    qps = [gen.random_dense_qp(12, 6, seed=60), gen.infeasible_qp("pair", 1),
+           gen.random_dense_qp(20, 9, seed=61), gen.infeasible_qp("triple", 3)]
+    ub = gen.pack_uneven(qps)
+    consts = [exact_constants(qp) for qp in qps]
+    C = [np.array([c[j] for c in consts]) for j in range(3)]
+    opts = dict(method=duq.DFGM, eps_out=1e-4, eps_in=1e-8, max_outer=20000)
+    X, Lam, res = duq.solve_batch_uneven(ub, constants=C, **opts)
+    codes = {dfom.STATUS_OK: duq.DUQ_OK, dfom.STATUS_MAXITER: duq.DUQ_EMAXITER,
+             dfom.STATUS_INFEASIBLE: duq.DUQ_EINFEASIBLE}
+    for i, qp in enumerate(qps):
+        lmin, lmax, g2 = consts[i]
+        ref = dfom.dfom_solve(qp, dfom.Options(lam_min=lmin, lam_max=lmax, G_norm2=g2, **opts))
+        r = res[i]
+        want = codes[ref.status]
+        assert (ref.status == dfom.STATUS_INFEASIBLE) == (i % 2 == 1), (i, ref.status)
+        assert r["status"] == want, (i, r)
+        assert r["outer_iters"] == ref.outer_iters and r["inner_iters"] == ref.inner_iters, i
+        x = X[ub.voff[i]:ub.voff[i] + qp.n]
+        lam = Lam[ub.coff[i]:ub.coff[i] + qp.p]
+        np.testing.assert_allclose(x, ref.x, rtol=0, atol=1e-7)
+        np.testing.assert_allclose(lam, ref.lam, rtol=0, atol=1e-7 * max(1, np.abs(ref.lam).max()))
+    assert [res[i]["status"] for i in range(4)].count(duq.DUQ_EINFEASIBLE) == 2
+
+
 def test_uneven_batch_estimated_constants_accuracy():
     print("[case] uneven batch with in-kernel Lanczos", flush=True)
     ub = gen.uneven_batch(B=16, seed=32, n_lo=20, n_hi=300, dtype=np.float32)

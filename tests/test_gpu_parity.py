@@ -231,6 +231,27 @@ def test_grid_maximum_size():
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("engine", [duq.ENGINE_BLOCK, duq.ENGINE_GRID])
+@pytest.mark.parametrize("kind,seed,method", [("pair", 1, duq.DFGM), ("pair", 2, duq.DGM),
+                                              ("triple", 3, duq.DFGM), ("triple", 3, duq.DGM)])
+def test_infeasible_certificate_parity(engine, kind, seed, method):
+    # same iteration, same certificate (the multipliers) and iterate as the oracle
+    print(f"[case] infeasible {kind} seed={seed} method={method} engine={engine}", flush=True)
+    qp = gen.infeasible_qp(kind, seed)
+    c = consts_of(qp)
+    opts = dict(method=method, eps_out=1e-6, eps_in=1e-10, max_outer=100000)
+    ref = dfom.dfom_solve(qp, dfom.Options(**opts), consts=c)
+    assert ref.status == dfom.STATUS_INFEASIBLE
+    with gpu_solver(qp, c, engine=engine, **opts) as s:
+        x, lam, res = s.solve()
+    assert res["status"] == duq.DUQ_EINFEASIBLE
+    assert res["outer_iters"] == ref.outer_iters and res["inner_iters"] == ref.inner_iters
+    close(lam, ref.lam, what="certificate")
+    close(x, ref.x, what="x")
+    w = qp.G.T @ lam
+    assert np.all(lam >= 0.0) and lam @ qp.g + np.sum(np.minimum(qp.lb * w, qp.ub * w)) > 0.0
+
+
 # ----------------------------------------------------------------------------
 # constants (Lanczos) and robustness
 # ----------------------------------------------------------------------------

@@ -141,7 +141,7 @@ def test_poll_states_and_errors():
         small.close()
 
 
-def test_infeasible_request_reaches_max_outer():
+def test_infeasible_request_is_certified():
     print("[case] serve infeasible request", flush=True)
     qp = gen.random_dense_qp(40, 20, seed=47)
     # G u + g <= 0 with a row and its negative both strictly violated on the box
@@ -151,5 +151,8 @@ def test_infeasible_request_reaches_max_outer():
     opts = dict(OPTS, max_outer=300)
     with duq.Server(1 << 26, **opts) as s:
         rc, x, lam, r = s.wait(s.submit(Q=qp.Q, q=qp.q, G=G, g=g, lb=qp.lb, ub=qp.ub), timeout=120)
-    assert rc == duq.DUQ_EMAXITER and r["outer_iters"] == 300
-    assert r["feas"] > 1.0
+    # ends before max_outer with a certificate: mu >= 0, min over the box of
+    # mu^T (G u + g) > 0 (the box minimum of a linear function, coordinatewise)
+    assert rc == duq.DUQ_EINFEASIBLE and r["outer_iters"] < 300
+    w = G.T @ lam
+    assert np.all(lam >= 0.0) and lam @ g + np.sum(np.minimum(qp.lb * w, qp.ub * w)) > 0.0

@@ -148,6 +148,38 @@ def test_separable_one_row_closed_form():
     assert np.linalg.norm(r.x - u) <= dist + 1e-9
 
 
+@pytest.mark.parametrize("kind,seed", [("pair", 1), ("pair", 2), ("triple", 3)])
+@pytest.mark.parametrize("method", [DGM, DFGM])
+def test_infeasible_qp_certificate(kind, seed, method):
+    # the returned multiplier must be a Farkas certificate: mu >= 0 and
+    # mu^T (G u + g) > 0 at every vertex of the box (so on all of it: linear)
+    qp = gen.infeasible_qp(kind, seed)
+    r = dfom_solve(qp, Options(method=method, eps_out=1e-6, eps_in=1e-10, max_outer=100000))
+    assert r.status == dfom.STATUS_INFEASIBLE
+    mu = r.lam
+    assert np.all(mu >= 0.0) and mu.sum() > 0.0
+    n = qp.n
+    verts = np.array(np.meshgrid(*[[-1.0, 1.0]] * n)).reshape(n, -1).T
+    vals = (verts @ qp.G.T + qp.g) @ mu
+    assert vals.min() > 0.0
+
+
+def test_feasible_qps_never_certified_infeasible():
+    for seed in range(6):
+        for method in (DGM, DFGM):
+            qp = tiny_qp(6, 5, seed)
+            r = dfom_solve(qp, Options(method=method, eps_out=1e-6, eps_in=1e-10, max_outer=20000))
+            assert r.status != dfom.STATUS_INFEASIBLE
+    # a feasible set with empty interior (two opposite rows meeting): not certified
+    rng = np.random.default_rng(9)
+    n = 4
+    a = rng.standard_normal(n)
+    qp = gen.QP(np.eye(n), rng.standard_normal(n), np.stack([a, -a]), np.array([0.0, 0.0]),
+                -np.ones(n), np.ones(n))
+    r = dfom_solve(qp, Options(method=DGM, eps_out=1e-5, eps_in=1e-10, max_outer=20000))
+    assert r.status != dfom.STATUS_INFEASIBLE
+
+
 # ----------------------------------------------------------------------------
 # P3: KKT and an independent solver at the config-0 size
 # ----------------------------------------------------------------------------
