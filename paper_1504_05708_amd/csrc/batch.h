@@ -197,7 +197,6 @@ __device__ __forceinline__ void batch_solve(const BatchArgs<T>& a, double* lds) 
             lz.red = red + a.lanczos_alloc + 2;
             lz.tl = tl;
             lz.use_gtg = 0;
-            lz.pp = 0;
             lz.run();
             __syncthreads();
             lmin = LW.out[0] / a.safety;

@@ -514,7 +514,7 @@ int estimate_constants(duq_handle* h, const DeviceInfo& di) {
         L.V = c.take<double>((size_t)(k + 1) * n);
         L.w = c.take<double>(n);
         L.r = c.take<double>(std::max(p, 1));
-        L.part = c.take<double>((size_t)nb * (k + 2) * 2);   // two alternating buffers
+        L.part = c.take<double>((size_t)nb * (k + 2));
         L.gtp = c.take<double>(nb > 1 ? (size_t)nb * n : 1);
         L.ab = c.take<double>(2 * (size_t)k + 2);
         L.out = c.take<double>(4);

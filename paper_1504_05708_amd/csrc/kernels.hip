@@ -49,7 +49,6 @@ __global__ void __launch_bounds__(512) lanczos_kernel(DevProblem<T> P, LanczosWo
     s.L = L;
     s.k = k;
     s.use_gtg = use_gtg;
-    s.pp = 0;
     s.tm.rank = blockIdx.x;
     s.tm.size = gridDim.x;
     s.tm.bar = L.bar;

@@ -51,7 +51,6 @@ struct Lanczos {
     Team tm;
     int k;
     int use_gtg;
-    int pp;          // which of the two partial-sum buffers the next reduction writes
     int nlo, nhi, plo, phi;
     double* xl;
     double* vl;
@@ -103,7 +102,7 @@ struct Lanczos {
                     const double t = wave_sum(s[c]);
                     if (lane == 0) {
                         if (tm.size == 1) hl[j] = t;
-                        else xstore(part() + (long)tm.rank * ncol + j, t);
+                        else xstore(L.part + (long)tm.rank * ncol + j, t);
                     }
                 }
             }
@@ -113,7 +112,7 @@ struct Lanczos {
         for (int j0 = wid; j0 < m; j0 += C * nw) {
             const int nc = min(C, (m - 1 - j0) / nw + 1);
             double s[C];
-            xsum_strided_cols<C>(part() + j0, ncol, (long)nw, nc, lane, kWave, tm.size, s);
+            xsum_strided_cols<C>(L.part + j0, ncol, (long)nw, nc, lane, kWave, tm.size, s);
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 if (c < nc) {
@@ -123,15 +122,10 @@ struct Lanczos {
             }
         }
         __syncthreads();
-        pp ^= 1;   // the next reduction writes the other buffer: no barrier for late readers
+        // the next writer of part must not overtake readers: barrier
+        if (tm.sync()) return false;
         return true;
     }
-
-    // Partial sums of the team reductions alternate between two buffers of
-    // size * (k + 2): a workgroup that has read this reduction's sums may write
-    // the next one's while others still read (a third reduction is behind a
-    // barrier that every reader has passed).
-    __device__ __forceinline__ double* part() const { return L.part + (long)pp * tm.size * (k + 2); }
 
     __device__ __forceinline__ bool apply(const double* v, double* w) {
         const int n = P.n;
@@ -277,15 +271,15 @@ struct Lanczos {
             __syncthreads();
             return true;
         }
-        if (threadIdx.x == 0) xstore(part() + (long)tm.rank * ncol + k + 1, v[0]);
+        if (threadIdx.x == 0) xstore(L.part + (long)tm.rank * ncol + k + 1, v[0]);
         if (tm.sync()) return false;
         if (wid == 0) {
-            double t = xsum_strided(part() + k + 1, ncol, lane, kWave, tm.size);
+            double t = xsum_strided(L.part + k + 1, ncol, lane, kWave, tm.size);
             t = wave_sum(t);
             if (lane == 0) hl[0] = t;
         }
         __syncthreads();
-        pp ^= 1;
+        if (tm.sync()) return false;
         return true;
     }
 };
