@@ -293,7 +293,7 @@ def pack_uneven(qps, dtype=np.float64) -> "UnevenBatch":
     """Pack a list of QPs into an UnevenBatch (instances in list order)."""
     n = np.array([qp.n for qp in qps], dtype=np.int32)
     p = np.array([qp.p for qp in qps], dtype=np.int32)
-    off = lambda sizes: np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    off = lambda sizes: np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)[:len(sizes)]
     n64, p64 = n.astype(np.int64), p.astype(np.int64)
     cat = lambda parts, dt=np.float64: (np.concatenate(parts).astype(dt) if parts else np.zeros(0, dt))
     return UnevenBatch(n, p, cat([qp.Q.ravel() for qp in qps], dtype), cat([qp.G.ravel() for qp in qps], dtype),

@@ -131,6 +131,10 @@ def test_batch_rejects_bad_input():
     with pytest.raises(duq.DuqError) as e:
         duq.solve_batch_uneven(ub)
     assert e.value.code == duq.DUQ_EINVAL
+    # an empty batch is an argument error, not an empty success
+    with pytest.raises(duq.DuqError) as e:
+        duq.solve_batch_uneven(gen.pack_uneven([]))
+    assert e.value.code == duq.DUQ_EINVAL
 
 
 def test_device_outputs_equal_host_outputs():
