@@ -46,7 +46,7 @@ extern "C" {
 #define DUQ_EINFEASIBLE -8   /* no point of the box satisfies G u + g <= 0: the
                                 multipliers returned are a certificate mu >= 0 with
                                 min over the box of mu^T (G u + g) > 0; x is the
-                                last iterate (rho = 0; not on the TILE engine)     */
+                                last iterate (rho = 0)                             */
 
 /* ---- enumerations ------------------------------------------------------ */
 enum { DUQ_F64 = 0, DUQ_F32 = 1, DUQ_BF16 = 2 };            /* storage of Q, G   */
@@ -228,8 +228,7 @@ typedef struct duq_batch {
  * Lam_out (sum p_i, or B x p) are host buffers laid out like q and g; res has
  * B entries (time_ms is the batch's device time).  Returns DUQ_OK when every
  * instance passed its outer test, DUQ_EMAXITER / DUQ_ENUMERIC /
- * DUQ_EINFEASIBLE (BLOCK engine) when one did not (see res[i].status), or an
- * error code.                                                               */
+ * DUQ_EINFEASIBLE when one did not (see res[i].status), or an error code.   */
 int duq_solve_batch(const duq_batch *batch, const duq_options *opts, void *stream,
                     double *X_out, double *Lam_out, duq_result *res);
 

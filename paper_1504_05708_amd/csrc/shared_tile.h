@@ -395,14 +395,52 @@ struct Tile {
         double Fc = 0.0, feasc = 0.0, lnc = 0.0;
         long long inner_total = 0;
         int k = 0, status = 1, gt = 0;
+        int it = 0;             // loop trips (uniform); equals k of every active lane
+        bool infeas = false;    // mu^k certified infeasibility: it is the output
         bool act = valid;
         const bool last_extra = par.output == 0 && par.method == 1;
 
         while (__any(act)) {
             if (act) ++k;
+            ++it;
             // Step 1: inner solve at mu^k, warm-started from ubar^{k-1}
             linear_term(0);
             ++gt;
+            if (p > 0 && it > 1 && it % kInfeasEvery == 1) {
+                // certificate of infeasibility at mu^k (as in the per-instance
+                // solver): v = mu^T g + sum_j min(lb_j w_j, ub_j w_j), w = c - q.
+                // k = 1 is skipped: mu^1 = lambda^0 = 0 here, where v = 0 cannot
+                // certify, so the outcome is that of testing it.
+                double e[3] = {0.0, 0.0, 0.0};   // v, scale, #(mu < 0)
+#pragma unroll
+                for (int j = 0; j < kTileRT; ++j)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = row(j, i);
+                        if (act && r < n) {
+                            const double wv = c[j][i] - qb[r], lo = box[r], hi = box[n + r];
+                            e[0] += fmin(lo * wv, hi * wv);
+                            e[1] += fabs(wv) * fmax(fabs(lo), fabs(hi));
+                        }
+                    }
+                for (int rt = w; rt < PT; rt += kTileWaves)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = 16 * rt + grp + 4 * i;
+                        if (act && r < p) {
+                            const double m = mu[r], mg = m * gb[r];
+                            e[0] += mg;
+                            e[1] += fabs(mg);
+                            e[2] += m < 0.0 ? 1.0 : 0.0;
+                        }
+                    }
+                colsum_long<3>(e, redK);
+                if (act && e[2] == 0.0 && e[0] > kInfeasMargin * e[1]) {
+                    status = kStInfeasible;
+                    infeas = true;
+                    act = false;
+                }
+            }
             int t;
             double gap;
             bool bad;
@@ -593,13 +631,13 @@ struct Tile {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int r = row(j, i);
-                    if (r < n) a.X[(long)b * n + r] = par.output == 1 ? us[r] / S : x[j][i];
+                    if (r < n) a.X[(long)b * n + r] = (par.output == 1 && !infeas) ? us[r] / S : x[j][i];
                 }
             for (int rt = w; rt < PT; rt += kTileWaves)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int r = 16 * rt + grp + 4 * i;
-                    if (r < p) a.Lam[(long)b * p + r] = lamp[r];
+                    if (r < p) a.Lam[(long)b * p + r] = infeas ? mu[r] : lamp[r];
                 }
             if (w == 0 && grp == 0) {
                 BatchResultDev rr;

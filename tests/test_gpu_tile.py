@@ -127,3 +127,33 @@ def test_tile_ragged_generic_shapes_match_oracle(n, p):
         np.testing.assert_allclose(X[b], ref.x, rtol=0, atol=1e-7)
         if p:
             np.testing.assert_allclose(Lam[b], ref.lam, rtol=0, atol=1e-7 * max(1.0, np.abs(ref.lam).max()))
+
+
+@pytest.mark.parametrize("method", [duq.DFGM, duq.DGM])
+def test_tile_infeasible_instances_certified(method):
+    # a shared system whose per-instance g makes every other instance infeasible:
+    # those end with the oracle's certificate and iterate, the others are solved
+    print(f"[case] tile infeasible instances method={method}", flush=True)
+    base = gen.infeasible_qp("pair", 1)
+    B = 19
+    rng = np.random.default_rng(78)
+    Qlin = rng.standard_normal((B, base.n))
+    Glin = np.tile(base.g, (B, 1))
+    Glin[0::2, :2] = -Glin[0::2, :2]          # even instances: a u <= 0.3, -a u <= 0.2 (feasible)
+    c = dfom.problem_constants(base.Q, base.G, base.lb, base.ub, 0.0, 1e-6)
+    opts = dict(method=method, eps_out=1e-4, eps_in=1e-8 if method == duq.DFGM else 1e-6, max_outer=20000)
+    X, Lam, res = duq.solve_batch_shared(base.Q, base.G, base.lb, base.ub, Qlin, Glin,
+                                         constants=(c.lam_min, c.lam_max, c.G_norm2), engine=duq.ENGINE_TILE, **opts)
+    codes = {dfom.STATUS_OK: duq.DUQ_OK, dfom.STATUS_MAXITER: duq.DUQ_EMAXITER,
+             dfom.STATUS_INFEASIBLE: duq.DUQ_EINFEASIBLE}
+    for b in range(B):
+        qp = gen.QP(base.Q, Qlin[b], base.G, Glin[b], base.lb, base.ub)
+        ref = dfom.dfom_solve(qp, dfom.Options(method=dfom.DFGM if method == duq.DFGM else dfom.DGM,
+                                               lam_min=c.lam_min, lam_max=c.lam_max, G_norm2=c.G_norm2,
+                                               eps_out=opts["eps_out"], eps_in=opts["eps_in"], max_outer=20000))
+        assert (ref.status == dfom.STATUS_INFEASIBLE) == (b % 2 == 1), (b, ref.status)
+        r = res[b]
+        assert r["status"] == codes[ref.status] and r["engine"] == duq.ENGINE_TILE, (b, r)
+        assert r["outer_iters"] == ref.outer_iters and r["inner_iters"] == ref.inner_iters, (b, r, ref.outer_iters)
+        np.testing.assert_allclose(X[b], ref.x, rtol=0, atol=1e-7)
+        np.testing.assert_allclose(Lam[b], ref.lam, rtol=0, atol=1e-7 * max(1.0, np.abs(ref.lam).max()))
