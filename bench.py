@@ -214,9 +214,11 @@ def main():
         g_products = outer + (1 if (method == duq.DFGM and output == duq.LAST) else 0)
     alg_bytes = q_products * nn + g_products * pn + gt_rows * n * s_bytes
     achieved = alg_bytes / (kern_avg * 1e-3) / 1e9
-    default_workload = (n == 8192 and p == 4096 and a.precision == "f64" and method == duq.DFGM
-                        and output == duq.LAST and eps_in == 1e-8 and a.rho == 0.0 and a.eps_out == 1e-4)
-    traffic = measured_traffic("dfom_kernel_config1_f64.txt", "dfom_kernel") if default_workload else None
+    # the profiled configurations: the default large QP with FP64 or FP32 storage
+    profiled = (n == 8192 and p == 4096 and a.precision in ("f64", "f32") and a.accumulate == "f64"
+                and method == duq.DFGM and output == duq.LAST and eps_in == 1e-8 and a.rho == 0.0
+                and a.eps_out == 1e-4)
+    traffic = measured_traffic(f"dfom_kernel_config1_{a.precision}.txt", "dfom_kernel") if profiled else None
     F, LB, feas = res["f"], res["lb_dual"], res["feas"]
     gnorm = float(np.linalg.norm(qp.g))
     acc = {"cert_subopt_rel": (F - LB) / max(1.0, abs(F)), "feas_rel": feas / max(1.0, gnorm)}
