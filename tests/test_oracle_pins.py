@@ -420,6 +420,98 @@ def test_constants_formulas():
         assert c.k_in_max == kin
 
 
+# ----------------------------------------------------------------------------
+# The k_in cap of Sec. 5 against Lemma lemma_sublin_dfg
+# ----------------------------------------------------------------------------
+
+def _lemma_bound(k, L, sigma, R2, variant):
+    """Right side of eq. bound_gen_dfg1 after k steps of FOM (R2 = R^2)."""
+    if variant == dfom.INNER_FGM_SIGMA:
+        return (1.0 - math.sqrt(sigma / L)) ** (k - 1) * L * R2
+    return 2.0 * L * R2 / (k + 1) ** 2          # FGM: p(beta_k) = 2
+
+
+def _lemma_k_min(L, sigma, R2, eps, variant):
+    """Smallest k for which the lemma's bound is <= eps, by direct search."""
+    k = 1
+    while _lemma_bound(k, L, sigma, R2, variant) > eps:
+        k += 1
+    return k
+
+
+@pytest.mark.parametrize("strong", [True, False])
+@pytest.mark.parametrize("eps_in", [1e-2, 1e-6])
+def test_k_in_cap_reaches_inner_accuracy(strong, eps_in):
+    # Sec. 5: after k_in steps of FOM on L(., mu) from any box point the inner
+    # problem is solved to eps_in (eq. duquad_in); the true gap comes from the
+    # exact box-QP minimiser.  Starts at box vertices (distance up to D_U).
+    n, p = 6, 4
+    qp = tiny_qp(n, p, 111, reg=0.3 if strong else 0.0)
+    if not strong:                                  # a singular Hessian: sigma_in = 0
+        w, V = np.linalg.eigh(qp.Q)
+        w[0] = 0.0
+        Q = (V * w) @ V.T
+        qp = gen.QP(0.5 * (Q + Q.T), qp.q, qp.G, qp.g, qp.lb, qp.ub)
+    lam_min = None if strong else 0.0
+    # the inner Hessian is Q whatever mu is (rho = 0): the constants of the
+    # inner problem do not involve G (and L_d, undefined for sigma = 0, is not used)
+    c = problem_constants(qp.Q, np.zeros((0, n)), qp.lb, qp.ub, 0.0, eps_in, lam_min=lam_min)
+    assert (c.sigma_in > 0.0) == strong
+    variant = dfom.INNER_FGM_SIGMA if strong else dfom.INNER_FGM
+    rng = np.random.default_rng(112)
+    for trial in range(5):
+        mu = np.abs(rng.standard_normal(p)) * (0.5 + trial)
+        x0 = np.where(rng.random(n) < 0.5, qp.lb, qp.ub)            # a vertex of U
+        u, t, _ = fom_inner(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub, mu, 0.0, c, x0, eps_in,
+                            rule=FIXED, variant=variant)
+        assert t == c.k_in_max
+        _, phi_star = box_qp_exact(qp.Q, qp.q + qp.G.T @ mu, qp.lb, qp.ub)
+        phi_star += float(mu @ qp.g)
+        true_gap = lagrangian(qp.Q, qp.q, qp.G, qp.g, u, mu, 0.0) - phi_star
+        assert -1e-12 <= true_gap <= eps_in
+
+
+@pytest.mark.parametrize("kappa,ratio", [(1.5, 10.0), (32.0, 1e6), (32.0, 1e12), (400.0, 1e9), (4.0, 1.6)])
+def test_k_in_cap_brackets_lemma_minimum(kappa, ratio):
+    # k_in of Sec. 5 is an upper estimate of the smallest k at which the bound of
+    # Lemma lemma_sublin_dfg (with R <= D_U) reaches eps_in, and not a loose one:
+    # sqrt(L/sigma) log(x) exceeds log(x) / -log(1 - sqrt(sigma/L)) by at most
+    # log(x)/2 + log(x) sqrt(sigma/L)/12.  ratio = L D_U^2 / eps_in.  A wrong log
+    # base, a missing square root, L and sigma swapped or D_U in place of D_U^2
+    # fall outside the bracket; at kappa = 4, ratio = 1.6 the bracket is a point
+    # (k_in = 2), which also fixes the trailing +1.
+    n = 4
+    lb, ub = -np.ones(n), np.ones(n)
+    D2 = float(np.sum((ub - lb) ** 2))
+    sigma = 1.0
+    L = kappa * sigma
+    Q = np.diag(np.linspace(sigma, L, n))
+    eps = L * D2 / ratio
+    c = problem_constants(Q, np.zeros((0, n)), lb, ub, 0.0, eps)
+    assert c.L_in == L and c.sigma_in == sigma
+    kmin = _lemma_k_min(L, sigma, D2, eps, dfom.INNER_FGM_SIGMA)
+    lx = math.log(ratio)
+    slack = math.ceil(lx * (0.5 + math.sqrt(sigma / L) / 12.0)) + 1
+    assert kmin <= c.k_in_max <= kmin + slack, (kmin, c.k_in_max, slack)
+    if (kappa, ratio) == (4.0, 1.6):
+        assert kmin == c.k_in_max == 2
+
+
+@pytest.mark.parametrize("ratio", [3.0, 1e4, 1e10])
+def test_k_in_cap_sublinear_brackets_lemma_minimum(ratio):
+    # sigma_in = 0: the FGM bound 2 L R^2/(k+1)^2 <= eps gives the smallest k;
+    # Sec. 5's sqrt(2 L D_U^2/eps_in), rounded up, is that k or the next one.
+    n = 3
+    lb, ub = -np.ones(n), 2.0 * np.ones(n)
+    D2 = float(np.sum((ub - lb) ** 2))
+    Q = np.diag([0.0, 1.0, 2.5])
+    eps = 2.5 * D2 / ratio
+    c = problem_constants(Q, np.zeros((0, n)), lb, ub, 0.0, eps)
+    assert c.sigma_in == 0.0 and c.L_in == 2.5
+    kmin = _lemma_k_min(c.L_in, 0.0, D2, eps, dfom.INNER_FGM)
+    assert c.k_in_max in (kmin, kmin + 1), (kmin, c.k_in_max)
+
+
 def test_inner_zero_steps_when_warm_start_is_optimal():
     qp = tiny_qp(5, 0, 91)
     xs, _ = box_qp_exact(qp.Q, qp.q, qp.lb, qp.ub)
