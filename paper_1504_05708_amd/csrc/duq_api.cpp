@@ -13,6 +13,7 @@
 #include "../../include/duq.h"
 #include "internal.h"
 #include "launch.h"
+#include "workspace.h"
 
 using namespace duq;
 
@@ -89,20 +90,6 @@ bool finite_all_t(const T* a, long len) {
     return true;
 }
 
-// Bump allocator over one device allocation (256-byte aligned slices).
-struct Carve {
-    char* base = nullptr;
-    size_t off = 0;
-    size_t need = 0;
-    template <typename T>
-    T* take(size_t count) {
-        const size_t bytes = ((count * sizeof(T) + 255) / 256) * 256 + 256;
-        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
-        off += bytes;
-        return p;
-    }
-};
-
 }  // namespace
 
 namespace duq {
@@ -111,6 +98,13 @@ int device_cus() {
     DeviceInfo di;
     if (device_info(&di) != DUQ_OK) return 1;
     return std::max(1, di.cus);
+}
+int device_shape(int* cus, size_t* lds_max) {
+    DeviceInfo di;
+    if (int rc = device_info(&di)) return rc;
+    *cus = di.cus;
+    *lds_max = di.lds_max;
+    return DUQ_OK;
 }
 }  // namespace duq
 
@@ -195,9 +189,9 @@ void duq_destroy(duq_handle* h) {
 
 }  // extern "C"
 
-namespace {
+namespace duq {
 
-int validate(const duq_problem* pr, const duq_options* o) {
+int validate_problem(const duq_problem* pr, const duq_options* o) {
     if (!pr || !o) return fail(DUQ_EINVAL, "null problem or options");
     if (pr->n <= 0) return fail(DUQ_EINVAL, "n must be positive");
     if (pr->p < 0) return fail(DUQ_EINVAL, "p must be non-negative");
@@ -221,7 +215,7 @@ int validate(const duq_problem* pr, const duq_options* o) {
     return DUQ_OK;
 }
 
-}  // namespace
+}  // namespace duq
 
 namespace duq {
 int estimate_constants(duq_handle* h, const DeviceInfo& di);
@@ -283,7 +277,7 @@ extern "C" int duq_max_n(int32_t p, int32_t engine, int32_t* n_max) {
 extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* stream, duq_handle** out) {
     if (!out) return fail(DUQ_EINVAL, "null output handle");
     *out = nullptr;
-    int rc = validate(pr, opts);
+    int rc = validate_problem(pr, opts);
     if (rc) return rc;
     const int n = pr->n, p = pr->p, dtype = pr->dtype;
     const long nn = (long)n * n, pn = (long)p * n;
@@ -307,8 +301,10 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
         std::memcpy(lb.data(), pr->lb, n * sizeof(double));
         std::memcpy(ub.data(), pr->ub, n * sizeof(double));
     } else {
-        if (hipMemcpy(lb.data(), pr->lb, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
-            hipMemcpy(ub.data(), pr->ub, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+        // stream-ordered: the caller may have queued the upload of lb/ub on `stream`
+        if (hipMemcpyAsync(lb.data(), pr->lb, n * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+            hipMemcpyAsync(ub.data(), pr->ub, n * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+            hipStreamSynchronize(h->stream) != hipSuccess) {
             duq_destroy(h);
             return fail(DUQ_EINVAL, "lb/ub are not readable device pointers");
         }
@@ -428,31 +424,7 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
     // workspace
     const int nb = h->cfg.nblocks;
     const int trace = opts->trace_outer;
-    auto carve = [&](Carve& c) {
-        for (int i = 0; i < 3; ++i) h->W.xb[i] = c.take<double>(n);
-        for (int i = 0; i < 3; ++i) h->W.qb[i] = c.take<double>(n);
-        h->W.c = c.take<double>(n);
-        h->W.us = c.take<double>(n);
-        h->W.qus = c.take<double>(n);
-        h->W.usave = c.take<double>(n);
-        h->W.qusave = c.take<double>(n);
-        h->W.xout = c.take<double>(n);
-        const int pp = std::max(p, 1);
-        h->W.r = c.take<double>(pp);
-        h->W.rs = c.take<double>(pp);
-        h->W.lamp = c.take<double>(pp);
-        h->W.mu = c.take<double>(pp);
-        h->W.wv = c.take<double>(pp);
-        h->W.gsave = c.take<double>(pp);
-        for (int i = 0; i < 3; ++i) h->W.gx[i] = c.take<double>(pp);
-        h->W.part = c.take<double>((size_t)2 * nb * kNP);
-        h->W.gtp = c.take<double>(nb > 1 ? (size_t)nb * n : 1);
-        h->W.trace = c.take<double>(trace > 0 ? (size_t)trace * (kTraceScalars + 2 * p + n) : 1);
-        h->W.st = c.take<DevState>(1);
-        h->W.bar = c.take<unsigned>(bar_words(nb));
-        h->xstage = c.take<double>(n);
-        h->lstage = c.take<double>(pp);
-    };
+    auto carve = [&](Carve& c) { carve_solver(c, n, p, nb, trace, &h->W, &h->xstage, &h->lstage); };
     Carve c0;
     carve(c0);
     if (hipMalloc(&h->ws, c0.off) != hipSuccess) {

@@ -246,6 +246,10 @@ int place(duq_server* s, Req* r) {
     in.p = p;
     if (e != hipSuccess) return set_error(DUQ_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
     if (r->large) {
+        // the uploads above must have landed before duq_setup reads lb, ub and
+        // scans the data
+        if ((e = hipStreamSynchronize(s->stream)) != hipSuccess)
+            return set_error(DUQ_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
         duq_problem pr{n, p, r->dtype, DUQ_DEVICE, in.Q, p ? in.G : nullptr, q, p ? g : nullptr, in.lb, in.ub};
         duq_options o = s->opts;
         o.trace_outer = 0;
@@ -308,6 +312,16 @@ void admit(duq_server* s) {
             large_active += r->large ? 1 : 0;
         }
     }
+}
+
+// Every constant a request carries into a slice must be finite and positive
+// (lambda_min may be 0 only with rho > 0, Sec. 2 Case 2; ||G||^2 is 0 only
+// without rows).
+bool constants_ok(const ServeInst& in, double rho) {
+    const bool lmin_ok = std::isfinite(in.lam_min) && (in.lam_min > 0.0 || (rho > 0.0 && in.lam_min >= 0.0));
+    const bool lmax_ok = std::isfinite(in.lam_max) && in.lam_max > 0.0;
+    const bool g2_ok = std::isfinite(in.g2) && (in.p == 0 || in.g2 > 0.0);
+    return lmin_ok && lmax_ok && g2_ok;
 }
 
 int ensure_meta(duq_server* s, size_t bytes) {
@@ -439,6 +453,7 @@ int round(duq_server* s) {
 
     // retire
     std::vector<Req*> done;
+    std::vector<Req*> bad;
     for (Group& gr : grp) {
         const BatchResultDev* rr = (const BatchResultDev*)(s->hmeta + gr.o_res);
         for (size_t j = 0; j < gr.r.size(); ++j) {
@@ -462,6 +477,13 @@ int round(duq_server* s) {
                 r->inst.lam_min = x.lam_min;
                 r->inst.lam_max = x.lam_max;
                 r->inst.g2 = x.G2;
+                if (!constants_ok(r->inst, s->opts.rho)) {
+                    // the next slice would run with these constants: end the
+                    // request instead (its state is not resumed)
+                    r->code = DUQ_EDEVICE;
+                    r->err = "invalid constants carried from the first slice";
+                    bad.push_back(r);
+                }
                 continue;
             }
             r->x.resize(r->n);
@@ -471,6 +493,8 @@ int round(duq_server* s) {
             if (e != hipSuccess) return set_error(DUQ_EDEVICE, "result copy");
             done.push_back(r);
             r->code = to_code(x.status);
+            if (x.status == 4)
+                r->err = "the constants of the request (estimated or given) are not finite and positive";
         }
     }
     for (Req* r : large) {
@@ -501,10 +525,14 @@ int round(duq_server* s) {
         r->code = to_code(st.status);
         done.push_back(r);
     }
-    if (!done.empty()) {
+    if (!done.empty() || !bad.empty()) {
         std::lock_guard<std::mutex> lk(s->mu);
         for (Req* r : done) {
-            finish(s, r, r->code, r->code ? "request did not pass its outer test" : "");
+            finish(s, r, r->code, !r->err.empty() ? r->err : r->code ? "request did not pass its outer test" : "");
+            s->active.erase(std::find(s->active.begin(), s->active.end(), r));
+        }
+        for (Req* r : bad) {
+            finish(s, r, r->code, r->err);
             s->active.erase(std::find(s->active.begin(), s->active.end(), r));
         }
     }

@@ -45,15 +45,27 @@ def test_served_requests_match_oracle():
         out = _serve(s, own, sid, Qlin, Glin)
     for i, qp in enumerate(own):
         rc, x, lam, r = out[i]
+        assert rc == duq.DUQ_OK, (i, r)
+        # the constants the request ran with (estimated in its first slice) lie on
+        # the safe side of the true spectrum, and near it
+        ev = np.linalg.eigvalsh(qp.Q)
+        g2 = np.linalg.norm(qp.G, 2) ** 2
+        assert 0.0 < r["lam_min"] <= ev[0] * (1 + 1e-9) and r["lam_min"] >= ev[0] / 1.5, (i, r, ev[0])
+        assert ev[-1] <= r["lam_max"] <= 1.05 * ev[-1], (i, r, ev[-1])
+        assert g2 <= r["G_norm2"] <= 1.05 * g2, (i, r, g2)
         ref = dfom.dfom_solve(qp, dfom.Options(method=dfom.DFGM, eps_out=1e-4, eps_in=1e-8, max_outer=20000,
                                                lam_min=r["lam_min"], lam_max=r["lam_max"], G_norm2=r["G_norm2"]))
-        assert rc == duq.DUQ_OK and ref.status == 0, (i, r)
+        assert ref.status == 0, (i, r)
         assert r["outer_iters"] == ref.outer_iters and r["inner_iters"] == ref.inner_iters, (i, r, ref.outer_iters)
         np.testing.assert_allclose(x, ref.x, rtol=0, atol=1e-7)
         np.testing.assert_allclose(lam, ref.lam, rtol=0, atol=1e-7 * max(1, np.abs(ref.lam).max()))
         assert r["time_ms"] > 0
+    ev = np.linalg.eigvalsh(sysm.H)
+    g2 = np.linalg.norm(sysm.G, 2) ** 2
     for b in range(len(Qlin)):
         rc, x, lam, r = out[ub.B + b]
+        # a registered system's constants (estimated once at registration)
+        assert 0.0 < r["lam_min"] <= ev[0] * (1 + 1e-9) and ev[-1] <= r["lam_max"] and g2 <= r["G_norm2"], (b, r)
         qp = gen.QP(sysm.H, Qlin[b], sysm.G, Glin[b], sysm.lb, sysm.ub)
         ref = dfom.dfom_solve(qp, dfom.Options(method=dfom.DFGM, eps_out=1e-4, eps_in=1e-8, max_outer=20000,
                                                lam_min=r["lam_min"], lam_max=r["lam_max"], G_norm2=r["G_norm2"]))
