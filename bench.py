@@ -14,7 +14,10 @@ Workload (one step = one end-to-end solve of the large single QP):
 Prints one JSON line.  `roofline` covers the dominant kernel (the
 persistent DFOM kernel, one launch per solve): algorithmic matrix bytes per
 launch / its HIP-event duration on the stream it runs on.  `cpu_baseline`
-times the FP64 NumPy oracle on a bounded sample of the same solve.
+times the FP64 NumPy oracle on a bounded sample of the same solve.  The
+default run adds `batched`: the shared-Hessian MPC batch (B = 4096) and the
+uneven batch (B = 10 000) measured in the same process, each with its own
+steps, roofline, plain per-QP rate, oracle check and CPU baseline.
 """
 from __future__ import annotations
 
@@ -51,6 +54,8 @@ def parse():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--p", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="single workload: leave out the batched sub-results (MPC B=4096, uneven B=10000)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--workload", choices=["single", "uneven", "mpc", "serve"], default="single",
                     help="single large QP (default), uneven batch, or shared-Hessian MPC batch")
@@ -237,7 +242,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if a.precision == "f64" else "f32-storage/f64",
         "data": "synthetic",
         "config": {
             "workload": f"single dense QP n={n} p={p}: Q=A^T A/n+0.01I (A {2 * n}x{n} N(0,1)), G N(0,1), "
@@ -273,6 +278,22 @@ def main():
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(qp if a.precision == "f64" else qp.rounded(np.float32), consts, res,
                                             method, output, eps_in, a)
+    if not a.no_batched:
+        # the batched forms on the same GPU in the same run: the shared-Hessian
+        # MPC batch (4096 instances, MFMA tiles) and the uneven batch (10 000
+        # independent QPs, FP32 storage), each with its own roofline, plain
+        # per-QP rate, oracle check and CPU baseline
+        del Qd, Gd
+        torch.cuda.empty_cache()
+        line["batched"] = {}
+        for key, wl, B, st, wu, prec in (("mpc_shared_B4096", "mpc", 4096, 20, 5, "f64"),
+                                         ("uneven_B10000", "uneven", 10000, 2, 1, "f32")):
+            print(f"[bench] batched {key}", file=sys.stderr, flush=True)
+            r = batch_result(a, wl, B, st, wu, prec, not a.no_cpu)
+            for k in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
+                r.pop(k, None)
+            line["batched"][key] = r
+            torch.cuda.empty_cache()
     print(json.dumps(line), flush=True)
 
 
@@ -310,26 +331,37 @@ def cpu_baseline(qp, consts, res, method, output, eps_in, a):
 
 
 def bench_batch(a):
+    """--workload uneven|mpc: one JSON line for a batched form."""
+    line = batch_result(a, a.workload, a.batch, a.steps, a.warmup, a.precision, not a.no_cpu)
+    print(json.dumps(line), flush=True)
+
+
+def batch_result(a, workload, B, steps, warmup, precision, with_cpu, oracle_sample=None):
     """Batched forms: one duq_solve_batch over the whole batch per step, against
     the plain per-QP GPU solver (duq_setup + duq_solve per instance, constants
-    passed so it does not re-estimate them) on a sample of the same instances."""
+    passed so it does not re-estimate them) on a sample of the same instances.
+    `value` counts the instances that passed their outer test only.  A seeded
+    sample is checked against the oracle: suboptimality against the oracle's
+    interior-point optimum, feasibility, and the distance to the oracle's DFOM
+    solution of the same instance (same constants)."""
     import torch
     from paper_1504_05708_amd import duq, gen
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     duq.lib()
     method = duq.DFGM if a.method == "dfgm" else duq.DGM
+    output = duq.LAST if a.output == "last" else duq.AVG
     eps_in = a.eps_in if a.eps_in is not None else (1e-8 if method == duq.DFGM else 1e-6)
-    opts = dict(method=method, output=duq.LAST if a.output == "last" else duq.AVG, eps_out=a.eps_out,
+    opts = dict(method=method, output=output, eps_out=a.eps_out,
                 eps_in=eps_in, rho=a.rho, max_outer=200000,
                 engine={"auto": duq.ENGINE_AUTO, "block": duq.ENGINE_BLOCK, "tile": duq.ENGINE_TILE}[a.batch_engine])
-    npdt = np.float32 if a.precision == "f32" else np.float64
+    npdt = np.float32 if precision == "f32" else np.float64
     s_bytes = 4 if npdt == np.float32 else 8
     cuda = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()
     t0 = time.time()
     workers = max(1, min(a.gen_workers, len(os.sched_getaffinity(0))))
-    if a.workload == "uneven":
-        B = a.batch or 10000
+    if workload == "uneven":
+        B = B or 10000
         ub = gen.uneven_batch(B=B, seed=3, dtype=npdt, workers=workers)
         gen_s = time.time() - t0
         dev = gen.UnevenBatch(ub.n, ub.p, cuda(ub.Q), cuda(ub.G), cuda(ub.q), cuda(ub.g), cuda(ub.lb),
@@ -350,11 +382,14 @@ def bench_batch(a):
                 return sv.solve()[2]
 
         def instance(i):
-            return ub.instance(i)
+            return ub.instance(i)      # the stored (rounded) data, promoted to FP64
+
+        def x_of(X, i):
+            return X[int(ub.voff[i]):int(ub.voff[i]) + int(ns[i])]
         desc = (f"uneven batch of {B} independent dense QPs, n~U{{20..512}}, p=n//2, "
-                f"Q=A^T A/n+0.1I, box [-1,1], seed 3; Q,G stored {a.precision}")
+                f"Q=A^T A/n+0.1I, box [-1,1], seed 3; Q,G stored {precision}")
     else:
-        B = a.batch or 4096
+        B = B or 4096
         sysm = gen.mpc_system(seed=2)
         X0, Ql, Gl = gen.mpc_batch(sysm, B, seed=20)
         gen_s = time.time() - t0
@@ -376,38 +411,41 @@ def bench_batch(a):
         def instance(i):
             qp = gen.mpc_instance(sysm, X0[i])
             return qp if npdt == np.float64 else qp.rounded(npdt)
+
+        def x_of(X, i):
+            return X[i]
         desc = (f"shared-Hessian batch of {B} condensed MPC QPs (nx=12, nu=4, N=30: n=120, p=720, "
-                f"|u|<=1, |x_k|<=5), x0~U(-1,1)^12, seed 2/20; H,G stored {a.precision}")
+                f"|u|<=1, |x_k|<=5), x0~U(-1,1)^12, seed 2/20; H,G stored {precision}")
     torch.cuda.synchronize()
     # end-to-end call: constants estimated, outputs copied to the host
     t = time.perf_counter()
     _, _, res0 = run_batch(None, device_out=False)
     e2e_s = time.perf_counter() - t
     sys_consts = None
-    if a.workload == "mpc":
+    if workload == "mpc":
         sys_consts = (res0[0]["lam_min"], res0[0]["lam_max"], res0[0]["G_norm2"])
-    for _ in range(a.warmup):
+    for _ in range(warmup):
         run_batch(sys_consts)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    for _ in range(a.steps):
+    for _ in range(steps):
         X, L, res = run_batch(sys_consts)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t
     kern_ms = res[0]["time_ms"]
     ok = sum(r["status"] == duq.DUQ_OK for r in res)
-    value = B * a.steps / wall
+    value = ok * steps / wall
     engine = res[0]["engine"]
     # algorithmic matrix bytes of one launch, per instance: every Q product
     # (inner steps + warm start), the G product of each outer iteration and of
     # the extra last-iterate solve, the rows read by G^T mu, and the Lanczos
     # estimate (k steps on Q and on G^T G) unless the constants were shared
-    extra = 1 if (method == duq.DFGM and a.output == "last") else 0
+    extra = 1 if (method == duq.DFGM and output == duq.LAST) else 0
     alg = 0.0
     for i, r in enumerate(res):
         n, p = float(ns[i]), float(ps[i])
         k = min(96, n)
-        lz = (k * n * n + 2 * k * p * n) if a.workload == "uneven" else 0.0
+        lz = (k * n * n + 2 * k * p * n) if workload == "uneven" else 0.0
         alg += ((r["inner_iters"] + 1) * n * n + (r["outer_iters"] + extra) * p * n + r["gt_rows"] * n + lz) * s_bytes
     achieved = alg / (kern_ms * 1e-3) / 1e9
     if engine == duq.ENGINE_TILE:
@@ -419,15 +457,15 @@ def bench_batch(a):
             flops += 2.0 * n * n * (r["inner_iters"] + 1) + 2.0 * 2.0 * p * n * n_gt
         tf = flops / (kern_ms * 1e-3) / 1e12
         tr = (measured_traffic("dfom_tile_kernel_mpc4096_f64.txt", "dfom_tile_kernel")
-              if (a.workload == "mpc" and a.precision == "f64" and B == 4096) else None)
+              if (workload == "mpc" and precision == "f64" and B == 4096) else None)
         roof = {"bound": "mfma", "achieved": round(tf, 2), "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
                 "frac": round(tf / FP64_MFMA_PEAK_TFS, 4), "traffic": tr, "kernel": "dfom_tile_kernel",
                 "alg_flops_per_launch": flops, "launch_ms": round(kern_ms, 3),
                 "note": "FP64 MFMA 16x16x4; Q held in LDS, G through L2; flops of masked (finished) "
                         "columns and of padding are not counted"}
     else:
-        tr = (measured_traffic("dfom_batch_kernel_uneven2000_f32.txt", "dfom_batch_kernel")
-              if (a.workload == "uneven" and a.precision == "f32" and B == 2000) else None)
+        tr = (measured_traffic(f"dfom_batch_kernel_uneven{B}_{precision}.txt", "dfom_batch_kernel")
+              if workload == "uneven" else None)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
                 "kernel": "dfom_batch_kernel", "alg_bytes_per_launch": alg, "launch_ms": round(kern_ms, 3),
@@ -440,56 +478,86 @@ def bench_batch(a):
     plain_one(int(idx[0]), consts[0])
     torch.cuda.synchronize()
     t = time.perf_counter()
+    plain_ok = 0
     for i, c in zip(idx, consts):
-        plain_one(int(i), c)
+        plain_ok += plain_one(int(i), c)["status"] == duq.DUQ_OK
     torch.cuda.synchronize()
     plain_wall = time.perf_counter() - t
     # plain rate over the whole batch: the sample's mean time per solve, weighted
-    # by the work of the sampled instances relative to the batch
+    # by the work of the sampled instances relative to the batch, counting the
+    # share of instances that pass
     w_all = float(np.sum(ns * ns + ps * ns))
     w_s = float(np.sum(ns[idx] * ns[idx] + ps[idx] * ns[idx]))
-    plain_rate = B / (plain_wall * (w_all / w_s))
+    plain_rate = (plain_ok / S) * B / (plain_wall * (w_all / w_s))
     feas_rel = max(r["feas"] for r in res)
     cert = max((r["f"] - r["lb_dual"]) / max(1.0, abs(r["f"])) for r in res)
-    line = {
-        "metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": round(1e3 * wall / a.steps, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": round(1e3 * wall / steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if precision == "f64" else "f32-storage/f64",
+        "data": "synthetic",
         "config": {"workload": desc + f"; {a.method.upper()}-{a.output} eps_out={a.eps_out:g} eps_in={eps_in:g}; "
                                f"one persistent launch per batch ({'MFMA tiles of 16 instances' if engine == duq.ENGINE_TILE else 'one workgroup per instance'}); "
-                               f"inputs and outputs in HBM"
+                               f"inputs and outputs in HBM; value counts the instances that passed their "
+                               f"outer test"
                                + ("; system constants estimated once (end_to_end_solves_per_s includes the "
-                                  "estimate and the host copy of the outputs)" if a.workload == "mpc" else ""),
-                   "B": B, "storage": a.precision},
+                                  "estimate and the host copy of the outputs)" if workload == "mpc" else ""),
+                   "B": B, "storage": precision},
         "plain_solves_per_s": round(plain_rate, 3),
         "speedup_vs_plain": round(value / plain_rate, 1),
         "roofline": roof,
-        "end_to_end_solves_per_s": round(B / e2e_s, 2),
-        "kernel_solves_per_s": round(B / (kern_ms * 1e-3), 1),
-        "solve": {"instances_ok": ok, "max_cert_subopt_rel": cert, "max_feas_abs": feas_rel,
+        "end_to_end_solves_per_s": round(ok / e2e_s, 2),
+        "kernel_solves_per_s": round(ok / (kern_ms * 1e-3), 1),
+        "solve": {"instances_ok": ok, "instances_failed": B - ok,
+                  "failed_status": sorted({int(r["status"]) for r in res if r["status"] != duq.DUQ_OK}),
+                  "max_cert_subopt_rel": cert, "max_feas_abs": feas_rel,
                   "outer_mean": float(np.mean([r["outer_iters"] for r in res])),
                   "inner_mean": float(np.mean([r["inner_iters"] for r in res]))},
         "gen_seconds": round(gen_s, 1),
     }
-    if not a.no_cpu:
+    if with_cpu:
         from oracle import dfom
+        from oracle.ipm import ipm_qp
+        # accuracy against the oracle on a seeded sample: the interior-point
+        # optimum f* and the oracle's own DFOM solution with the same constants
+        rs = np.random.default_rng(7)
+        m = oracle_sample or (6 if workload == "uneven" else 8)
+        sel = np.sort(rs.choice(B, size=min(m, B), replace=False))
+        Xh = X.cpu().numpy() if hasattr(X, "cpu") else X
+        sub, feas_o, dx, fo_rel = [], [], [], []
+        for i in sel:
+            qp = instance(int(i))
+            x = np.asarray(x_of(Xh, int(i)), float)
+            _, fstar, _ = ipm_qp(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub)
+            F = float(0.5 * x @ qp.Q @ x + qp.q @ x)
+            sub.append(abs(F - fstar) / max(1.0, abs(fstar)))
+            feas_o.append(float(np.linalg.norm(np.maximum(qp.G @ x + qp.g, 0.0))) / max(1.0, np.linalg.norm(qp.g)))
+            ref = dfom.dfom_solve(qp, dfom.Options(method=method, output=output, eps_out=a.eps_out, eps_in=eps_in,
+                                                   rho=a.rho, max_outer=200000, lam_min=res[i]["lam_min"],
+                                                   lam_max=res[i]["lam_max"], G_norm2=res[i]["G_norm2"]))
+            dx.append(float(np.max(np.abs(x - ref.x))))
+            fo_rel.append(abs(F - ref.F) / max(1.0, abs(ref.F)))
+        out["vs_oracle"] = {"instances": [int(i) for i in sel], "max_subopt_rel_vs_ipm": max(sub),
+                            "max_feas_rel": max(feas_o), "max_abs_x_minus_oracle_dfom": max(dx),
+                            "max_rel_F_minus_oracle_dfom": max(fo_rel)}
+        # the oracle's throughput on the host cores (a baseline, not a target)
         t = time.perf_counter()
         done = 0
         for i, c in zip(idx, consts):
             qp = instance(int(i))
-            dfom.dfom_solve(qp, dfom.Options(method=method, eps_out=a.eps_out, eps_in=eps_in, rho=a.rho,
-                                             max_outer=200000, lam_min=c["lam_min"], lam_max=c["lam_max"],
-                                             G_norm2=c["G_norm2"]))
+            dfom.dfom_solve(qp, dfom.Options(method=method, output=output, eps_out=a.eps_out, eps_in=eps_in,
+                                             rho=a.rho, max_outer=200000, lam_min=c["lam_min"],
+                                             lam_max=c["lam_max"], G_norm2=c["G_norm2"]))
             done += 1
             if time.perf_counter() - t > a.cpu_seconds:
                 break
         cs = time.perf_counter() - t
         w_done = float(np.sum(ns[idx[:done]] ** 2 + ps[idx[:done]] * ns[idx[:done]]))
-        line["cpu_baseline"] = {"value": round(B / (cs * w_all / w_done), 4), "unit": "solves/s",
-                                "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
-                                "sample": f"{done} instances of the batch solved by the oracle in {cs:.1f} s, "
-                                          f"scaled by matrix work to all {B}"}
-    print(json.dumps(line), flush=True)
+        out["cpu_baseline"] = {"value": round(B / (cs * w_all / w_done), 4), "unit": "solves/s",
+                               "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
+                               "sample": f"{done} instances of the batch solved by the oracle in {cs:.1f} s, "
+                                         f"scaled by matrix work to all {B}"}
+    return out
 
 
 def bench_serve(a):
@@ -632,10 +700,10 @@ def bench_serve(a):
                      "outer_mean": round(float(np.mean([results[i][3]["outer_iters"] for i in ki])), 1)}
     cert = max((results[i][3]["f"] - results[i][3]["lb_dual"]) / max(1.0, abs(results[i][3]["f"])) for i in done)
     line = {
-        "metric": METRIC, "value": round(len(done) / span, 2), "unit": "solves/s", "n_gpus": 1, "steps": 1,
+        "metric": METRIC, "value": round(ok / span, 2), "unit": "solves/s", "n_gpus": 1, "steps": 1,
         "speedup_vs_plain": None,
         "warmup": 1, "ms_per_step": round(span * 1e3, 1), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64" if a.precision == "f64" else "f32-storage/f64", "data": "synthetic",
         "config": {"workload": f"serving: Poisson arrivals {a.rate:g}/s for {a.duration:g} s (seed 4); "
                                f"{a.large_frac:.0%} dense n=4096 p=2048 (pool of 8, fresh q,g), rest half uneven "
                                f"n~U{{20..512}} and half MPC on 8 registered systems (seeds 40..47, fresh x0); "
@@ -644,7 +712,7 @@ def bench_serve(a):
                    "requests": R, "hbm_budget_bytes": budget},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
                        "by_class": by},
-        "solve": {"completed": len(done), "ok": ok, "max_cert_subopt_rel": cert,
+        "solve": {"completed": len(done), "ok": ok, "failed": len(done) - ok, "max_cert_subopt_rel": cert,
                   "max_feas_abs": max(results[i][3]["feas"] for i in done)},
         "offered_per_s": round(R / a.duration, 1),
         "plain_solves_per_s": round(len(done) / sum(plain_s.get(reqs[i][0], 0.0) for i in done), 2),
