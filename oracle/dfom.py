@@ -49,6 +49,13 @@ design notes):
     mu^k >= 0 is tested as a certificate that no u in U has G u + g <= 0
     (infeasibility_certificate); the run then ends with mu^k as the
     multipliers and the warm start as x.
+  * Equality rows (K = {0}, Sec. 2) and the user form lbar <= Gbar u + gbar
+    <= ubar: stack_rows turns the user form into rows of G u + g in
+    K = R^m_- x {0}^e (an equality where lbar = ubar, else one inequality per
+    finite side); `eq` marks the equality rows.  Their multipliers are free
+    (K_d = R there), their distance to K is |r| and, with rho > 0, they add
+    rho G_eq^T G_eq to the inner Hessian: sigma_in = lambda_min(Q + rho
+    G_eq^T G_eq) (Sec. 3, Step 1, the K = {0} case).
 """
 from __future__ import annotations
 
@@ -125,10 +132,15 @@ class Result:
 
 def problem_constants(Q, G, lb, ub, rho: float, eps_in: float,
                       lam_min=None, lam_max=None, G_norm2=None,
-                      max_inner: int = 0) -> Constants:
+                      max_inner: int = 0, eq=None, sigma_in=None) -> Constants:
     """L_d, the outer step 1/(2 L_d), the inner L and sigma, beta, D_U, k_in.
 
-    Spectral quantities default to exact dense eigen/singular values."""
+    Spectral quantities default to exact dense eigen/singular values.  With
+    rho > 0 and equality rows (eq), sigma_in = lambda_min(Q + rho G_eq^T G_eq)
+    (Sec. 3, Step 1) unless given."""
+    if sigma_in is None and rho > 0.0 and eq is not None and np.any(eq):
+        Ge = G[np.asarray(eq, bool)]
+        sigma_in = float(np.linalg.eigvalsh(Q + rho * (Ge.T @ Ge))[0])
     if lam_min is None or lam_max is None:
         ev = np.linalg.eigvalsh(Q)
         lam_min = float(ev[0]) if lam_min is None else lam_min
@@ -144,7 +156,7 @@ def problem_constants(Q, G, lb, ub, rho: float, eps_in: float,
         Ld = G_norm2 / denom                       # eq. Ld
     alpha = 0.0 if Ld == 0.0 else 1.0 / (2.0 * Ld)  # Algorithm DFOM step 2
     L_in = lam_max + rho * G_norm2                  # Sec. 3, Step 1
-    sigma_in = max(lam_min, 0.0)
+    sigma_in = max(lam_min if sigma_in is None else sigma_in, 0.0)
     sqL, sqs = math.sqrt(L_in), math.sqrt(sigma_in)
     beta_in = (sqL - sqs) / (sqL + sqs)             # FGM_sigma, Sec. 2.1
     D_U = float(np.linalg.norm(ub - lb))
@@ -169,35 +181,78 @@ def objective(Q, q, u) -> float:
     return float(0.5 * u @ (Q @ u) + q @ u)
 
 
-def slack(G, g, u, lam, rho: float) -> np.ndarray:
+def _ineq(G, eq):
+    """Boolean mask of the inequality rows (K_i = R_-); eq marks K_i = {0}."""
+    return np.ones(G.shape[0], bool) if eq is None else ~np.asarray(eq, bool)
+
+
+def proj_K(v, eq=None) -> np.ndarray:
+    """Projection onto K = R^m_- x {0}^e (rows in place)."""
+    return np.where(_ineq(np.zeros((len(v), 0)), eq), np.minimum(v, 0.0), 0.0)
+
+
+def dist_K(v, eq=None) -> float:
+    """Distance of v to K: ||v - [v]_K||."""
+    return float(np.linalg.norm(v - proj_K(v, eq)))
+
+
+def slack(G, g, u, lam, rho: float, eq=None) -> np.ndarray:
     """s(u, lambda): [G u + g + lambda/rho]_K for rho > 0, 0 for rho = 0 (Sec. 2)."""
     if rho > 0.0:
-        return np.minimum(G @ u + g + lam / rho, 0.0)   # projection onto R^p_-
+        return proj_K(G @ u + g + lam / rho, eq)
     return np.zeros(G.shape[0])
 
 
-def lagrangian(Q, q, G, g, u, lam, rho: float) -> float:
-    """L_rho(u, lambda) of eq. auglag1 with K = R^p_- (dist_K(v) = ||[v]_+||)."""
+def lagrangian(Q, q, G, g, u, lam, rho: float, eq=None) -> float:
+    """L_rho(u, lambda) of eq. auglag1 (dist_K(v) = ||[v]_+|| on rows in R_-,
+    |v| on rows in {0})."""
     r = G @ u + g
     if rho > 0.0:
-        v = np.maximum(r + lam / rho, 0.0)
-        return objective(Q, q, u) + 0.5 * rho * float(v @ v) - float(lam @ lam) / (2.0 * rho)
+        d = dist_K(r + lam / rho, eq)
+        return objective(Q, q, u) + 0.5 * rho * d * d - float(lam @ lam) / (2.0 * rho)
     return objective(Q, q, u) + float(lam @ r)
 
 
-def dual_gradient(G, g, u, lam, rho: float) -> np.ndarray:
+def dual_gradient(G, g, u, lam, rho: float, eq=None) -> np.ndarray:
     """bar-nabla d_rho(lambda) = G u + g - s(u, lambda) (eq. inexact_framework)."""
-    return G @ u + g - slack(G, g, u, lam, rho)
+    return G @ u + g - slack(G, g, u, lam, rho, eq)
 
 
-def inner_gradient(Q, q, G, g, u, mu, rho: float) -> np.ndarray:
+def inner_gradient(Q, q, G, g, u, mu, rho: float, eq=None) -> np.ndarray:
     """Gradient in u of L_rho(u, mu).
 
-    rho = 0: Q u + q + G^T mu.  rho > 0: Q u + q + G^T [mu + rho (G u + g)]_+
-    (derivative of (rho/2) ||[G u + g + mu/rho]_+||^2)."""
+    rho = 0: Q u + q + G^T mu.  rho > 0: Q u + q + G^T w with
+    w = mu + rho (G u + g) - rho s (the derivative of (rho/2) dist_K(G u + g +
+    mu/rho)^2): [mu + rho (G u + g)]_+ on rows in R_-, mu + rho (G u + g) on
+    rows in {0}."""
     if rho > 0.0:
-        return Q @ u + q + G.T @ np.maximum(mu + rho * (G @ u + g), 0.0)
+        v = mu + rho * (G @ u + g)
+        w = np.where(_ineq(G, eq), np.maximum(v, 0.0), v)
+        return Q @ u + q + G.T @ w
     return Q @ u + q + G.T @ mu
+
+
+def stack_rows(G, g, rlo, rhi):
+    """The user form rlo <= G u + g <= rhi (Sec. 2; -inf / +inf for an absent
+    side) as rows of Gs u + gs in K = R^m_- x {0}^e: an equality row
+    G_i u + g_i - rhi_i = 0 where rlo_i = rhi_i, else G_i u + g_i - rhi_i <= 0
+    for a finite rhi_i and -G_i u - g_i + rlo_i <= 0 for a finite rlo_i.
+    Returns (Gs, gs, eq, src, sign): row j of the stack is sign_j times row
+    src_j of G.  The order is: for each i in turn, its upper (or equality)
+    row, then its lower row."""
+    rows, off, eq, src, sign = [], [], [], [], []
+    for i in range(G.shape[0]):
+        lo, hi = float(rlo[i]), float(rhi[i])
+        if lo == hi:
+            rows.append(G[i]); off.append(g[i] - hi); eq.append(True); src.append(i); sign.append(1.0)
+            continue
+        if math.isfinite(hi):
+            rows.append(G[i]); off.append(g[i] - hi); eq.append(False); src.append(i); sign.append(1.0)
+        if math.isfinite(lo):
+            rows.append(-G[i]); off.append(lo - g[i]); eq.append(False); src.append(i); sign.append(-1.0)
+    n = G.shape[1]
+    Gs = np.array(rows, float).reshape(-1, n)
+    return (Gs, np.array(off, float), np.array(eq, bool), np.array(src, int), np.array(sign, float))
 
 
 # ----------------------------------------------------------------------------
@@ -254,7 +309,7 @@ def _inner_beta_schedule(variant: int, sigma: float, beta_in: float):
 
 
 def fom_inner(Q, q, G, g, lb, ub, mu, rho: float, c: Constants, x0,
-              eps_in: float, rule: int = CERT, variant: int = INNER_AUTO):
+              eps_in: float, rule: int = CERT, variant: int = INNER_AUTO, eq=None):
     """Approximate u(mu) by Algorithm FOM(L_rho(., mu), U) from x^0 = y^1 = x0.
 
     Returns (x, steps, gap) with gap the certificate value of x."""
@@ -262,7 +317,7 @@ def fom_inner(Q, q, G, g, lb, ub, mu, rho: float, c: Constants, x0,
     betas = _inner_beta_schedule(variant, sigma, c.beta_in)
 
     def grad(u):
-        return inner_gradient(Q, q, G, g, u, mu, rho)
+        return inner_gradient(Q, q, G, g, u, mu, rho, eq)
 
     def done(gap, t):
         return (rule == CERT and gap <= eps_in) or t >= k_max
@@ -304,9 +359,9 @@ def fom_inner(Q, q, G, g, lb, ub, mu, rho: float, c: Constants, x0,
 # Algorithm DFOM (Sec. 3) with last / averaged primal output (Sec. 4)
 # ----------------------------------------------------------------------------
 
-def _outer_test(Q, q, G, g, x, lam, LB, eps, gnorm):
+def _outer_test(Q, q, G, g, x, lam, LB, eps, gnorm, eq=None):
     Fx = objective(Q, q, x)
-    feas = float(np.linalg.norm(np.maximum(G @ x + g, 0.0)))
+    feas = dist_K(G @ x + g, eq)
     scale = max(1.0, abs(Fx))
     ok = (feas <= eps * max(1.0, gnorm) and Fx - LB <= eps * scale
           and float(np.linalg.norm(lam)) * feas <= eps * scale)
@@ -317,9 +372,10 @@ def infeasibility_certificate(G, g, lb, ub, mu):
     """v = min over the box U of mu^T (G u + g), and the scale of its terms.
 
     The paper assumes a finite optimal multiplier exists (Sec. 2, strong
-    duality).  When no point of U satisfies G u + g <= 0 the dual is unbounded
-    above and the multipliers grow without bound; a mu >= 0 with v > 0 proves
-    it: every u in U has mu^T (G u + g) >= v > 0, so some row is violated.
+    duality).  When no point of U satisfies G u + g in K the dual is unbounded
+    above and the multipliers grow without bound; a mu with mu_i >= 0 on the
+    inequality rows (any sign on equality rows) and v > 0 proves it: every u
+    in U has mu^T (G u + g) >= v > 0, while a feasible u would give <= 0.
     The box minimum is separable: sum_j min(lb_j w_j, ub_j w_j), w = G^T mu.
     Returns (v, scale) with scale = sum |mu_i g_i| + sum |w_j| max(|lb_j|, |ub_j|);
     the run stops when v > INFEAS_MARGIN * scale."""
@@ -331,17 +387,28 @@ def infeasibility_certificate(G, g, lb, ub, mu):
 
 def dfom_solve(qp, opts: Options, consts: Optional[Constants] = None,
                x_start=None, lam_start=None) -> Result:
-    """Inexact (augmented) dual first-order method DFOM(d_rho, K_d)."""
+    """Inexact (augmented) dual first-order method DFOM(d_rho, K_d).
+
+    qp.eq (optional) marks equality rows (K_i = {0}); the others are
+    inequalities (K_i = R_-)."""
     Q, q, G, g, lb, ub = qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub
+    eq = getattr(qp, "eq", None)
+    if eq is not None and not np.any(eq):
+        eq = None
     rho = float(opts.rho)
     c = consts or problem_constants(Q, G, lb, ub, rho, opts.eps_in,
                                     opts.lam_min, opts.lam_max, opts.G_norm2,
-                                    opts.max_inner)
+                                    opts.max_inner, eq=eq)
     p = G.shape[0]
     gnorm = float(np.linalg.norm(g))
+    ineq = _ineq(G, eq)
 
     def proj_Kd(v):
-        return np.maximum(v, 0.0) if c.Kd_nonneg else v
+        # K_d = R_+ on inequality rows when Q > 0 (after eq. dual_pr), R elsewhere
+        return np.where(ineq, np.maximum(v, 0.0), v) if c.Kd_nonneg else v
+
+    def in_Kd(v):
+        return bool(np.all(v[ineq] >= 0.0))
 
     lam = proj_Kd(np.zeros(p) if lam_start is None else np.asarray(lam_start, float))
     lam_prev = lam.copy()                          # lambda^{-1} = lambda^0
@@ -358,20 +425,20 @@ def dfom_solve(qp, opts: Options, consts: Optional[Constants] = None,
     for k in range(1, opts.max_outer + 1):
         # Before step 1 (rho = 0, mu^k >= 0): a Farkas-type certificate that
         # no feasible point exists ends the run with mu^k as the certificate.
-        if rho == 0.0 and p > 0 and k % INFEAS_EVERY == 1 and np.all(mu >= 0.0):
+        if rho == 0.0 and p > 0 and k % INFEAS_EVERY == 1 and in_Kd(mu):
             v, scale = infeasibility_certificate(G, g, lb, ub, mu)
             if v > INFEAS_MARGIN * scale:
                 Fx = objective(Q, q, x_warm)
-                feas = float(np.linalg.norm(np.maximum(G @ x_warm + g, 0.0)))
+                feas = dist_K(G @ x_warm + g, eq)
                 return Result(x_warm.copy(), mu.copy(), Fx, LB, feas, STATUS_INFEASIBLE,
                               k, inner_total, c, log)
         # Step 1: ubar^k approximately minimises L_rho(., mu^k) over U
         u, t, gap = fom_inner(Q, q, G, g, lb, ub, mu, rho, c, x_warm,
-                              opts.eps_in, opts.inner_rule, opts.inner_variant)
+                              opts.eps_in, opts.inner_rule, opts.inner_variant, eq)
         inner_total += t
-        dg = dual_gradient(G, g, u, mu, rho)
-        dbar = lagrangian(Q, q, G, g, u, mu, rho)
-        if rho > 0.0 or np.all(mu >= 0.0):         # weak duality holds at mu^k
+        dg = dual_gradient(G, g, u, mu, rho, eq)
+        dbar = lagrangian(Q, q, G, g, u, mu, rho, eq)
+        if rho > 0.0 or in_Kd(mu):                 # weak duality holds at mu^k
             LB = max(LB, dbar - gap)
         # Step 2: projected inexact dual gradient step
         lam_k = proj_Kd(mu + c.alpha * dg)
@@ -387,7 +454,7 @@ def dfom_solve(qp, opts: Options, consts: Optional[Constants] = None,
         u_sum = u_sum + theta * u
         u_hat = u_sum / S
         cand = u if opts.output == LAST else u_hat
-        ok, Fx, feas = _outer_test(Q, q, G, g, cand, lam_k, LB, opts.eps_out, gnorm)
+        ok, Fx, feas = _outer_test(Q, q, G, g, cand, lam_k, LB, opts.eps_out, gnorm, eq)
         entry = dict(k=k, t=t, gap=gap, dbar=dbar, LB=LB, theta=theta, S=S,
                      F=Fx, feas=feas, lam_norm=float(np.linalg.norm(lam_k)), passed=ok)
         if k <= opts.log_vectors:
@@ -396,11 +463,11 @@ def dfom_solve(qp, opts: Options, consts: Optional[Constants] = None,
         if ok and opts.output == LAST and opts.method == DFGM:
             # last primal iterate u(lambda^k), eq. last_primal
             u2, t2, gap2 = fom_inner(Q, q, G, g, lb, ub, lam_k, rho, c, u,
-                                     opts.eps_in, opts.inner_rule, opts.inner_variant)
+                                     opts.eps_in, opts.inner_rule, opts.inner_variant, eq)
             inner_total += t2
-            if rho > 0.0 or np.all(lam_k >= 0.0):
-                LB = max(LB, lagrangian(Q, q, G, g, u2, lam_k, rho) - gap2)
-            ok, Fx, feas = _outer_test(Q, q, G, g, u2, lam_k, LB, opts.eps_out, gnorm)
+            if rho > 0.0 or in_Kd(lam_k):
+                LB = max(LB, lagrangian(Q, q, G, g, u2, lam_k, rho, eq) - gap2)
+            ok, Fx, feas = _outer_test(Q, q, G, g, u2, lam_k, LB, opts.eps_out, gnorm, eq)
             entry.update(extra_t=t2, extra_gap=gap2, LB=LB, F2=Fx, feas2=feas, passed2=ok)
             result_x = u2
         log.append(entry)

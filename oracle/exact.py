@@ -50,17 +50,21 @@ def _eq_qp(Q, q, G, g, lb, ub, state, active):
     return x, sol[m:]
 
 
-def brute_force_qp(Q, q, G, g, lb, ub, tol: float = 1e-9):
+def brute_force_qp(Q, q, G, g, lb, ub, tol: float = 1e-9, eq=None):
     """Exact (x*, F*, lambda*) of min F s.t. Gx+g <= 0, lb <= x <= ub (n <= 8).
 
-    lambda* is recovered from the stationarity equations on the active rows
-    (least squares; unique under LICQ)."""
+    eq (optional) marks rows that are equalities (G_i x + g_i = 0): they are
+    active in every face.  lambda* is recovered from the stationarity
+    equations on the active rows (least squares; unique under LICQ)."""
     n, p = Q.shape[0], G.shape[0]
     if n > 8 or p > 8:
         raise ValueError("brute force is for n, p <= 8")
+    eqm = np.zeros(p, bool) if eq is None else np.asarray(eq, bool)
     best = None
     for state in itertools.product((-1, 0, 1), repeat=n):
         for act in itertools.product((0, 1), repeat=p):
+            if any(eqm[j] and not act[j] for j in range(p)):
+                continue
             active = tuple(j for j in range(p) if act[j])
             r = _eq_qp(Q, q, G, g, lb, ub, state, active)
             if r is None:
@@ -68,7 +72,9 @@ def brute_force_qp(Q, q, G, g, lb, ub, tol: float = 1e-9):
             x, _ = r
             if np.any(x < lb - tol) or np.any(x > ub + tol):
                 continue
-            if p and np.any(G @ x + g > tol):
+            if p and np.any((G @ x + g)[~eqm] > tol):
+                continue
+            if p and np.any(np.abs(G @ x + g)[eqm] > tol):
                 continue
             f = 0.5 * x @ Q @ x + q @ x
             if best is None or f < best[1] - 1e-13:
@@ -78,7 +84,7 @@ def brute_force_qp(Q, q, G, g, lb, ub, tol: float = 1e-9):
     x, f = best
     # multipliers of the active rows from stationarity on the free coordinates
     lam = np.zeros(p)
-    act = np.where(G @ x + g > -1e-8)[0] if p else np.zeros(0, int)
+    act = np.where((G @ x + g > -1e-8) | eqm)[0] if p else np.zeros(0, int)
     free = (x > lb + 1e-8) & (x < ub - 1e-8)
     if len(act):
         grad = Q @ x + q

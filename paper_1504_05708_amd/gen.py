@@ -30,7 +30,12 @@ import numpy as np
 
 @dataclass
 class QP:
-    """One QP in the form of Sec. 2 with inequality constraints."""
+    """One QP in the form of Sec. 2.
+
+    Constraints: G u + g <= 0 when rlo/rhi are None; otherwise the user form
+    rlo <= G u + g <= rhi (row-wise, -inf / +inf for an absent side, rlo = rhi
+    an equality).  `eq` marks rows of G u + g that are equalities (K_i = {0})
+    for a problem already written in cone form."""
     Q: np.ndarray          # (n, n) float64, symmetric
     q: np.ndarray          # (n,)
     G: np.ndarray          # (p, n)
@@ -38,6 +43,9 @@ class QP:
     lb: np.ndarray         # (n,)
     ub: np.ndarray         # (n,)
     meta: dict = field(default_factory=dict)
+    rlo: Optional[np.ndarray] = None
+    rhi: Optional[np.ndarray] = None
+    eq: Optional[np.ndarray] = None
 
     @property
     def n(self) -> int:
@@ -53,8 +61,10 @@ class QP:
         The FP32 storage path solves exactly this problem."""
         Q = self.Q.astype(dtype).astype(np.float64)
         G = self.G.astype(dtype).astype(np.float64)
+        cp = lambda v: None if v is None else v.copy()
         return QP(Q, self.q.copy(), G, self.g.copy(), self.lb.copy(),
-                  self.ub.copy(), dict(self.meta, storage=np.dtype(dtype).name))
+                  self.ub.copy(), dict(self.meta, storage=np.dtype(dtype).name),
+                  cp(self.rlo), cp(self.rhi), cp(self.eq))
 
 
 def _rng(seed) -> np.random.Generator:
@@ -141,6 +151,52 @@ def infeasible_qp(kind: str, seed=1, n: int = 5) -> QP:
         G = np.stack([B[0], B[1], -(B[0] + B[1])])
         g = np.array([0.1, 0.2, 0.3])
     return QP(Q, q, G, g, -np.ones(n), np.ones(n), dict(kind="infeasible_" + kind, n=n, p=3, seed=seed))
+
+
+def random_eq_qp(n: int, p: int, seed=0, rank: Optional[int] = None, reg: float = 0.0,
+                 box: float = 1.0) -> QP:
+    """Equality-constrained dense QP (Sec. 2 with K = {0}; the QP class of the
+    paper's Sec. 6 CPU-time study): Q = A^T A / n + reg I with A (rank x n)
+    i.i.d. N(0,1), so Q is singular when rank < n and reg = 0 (Sec. 2, Case 2);
+    q ~ N(0,1); G (p x n) i.i.d. N(0,1); g = -(G x0) with x0 ~ U(-box/2, box/2),
+    so x0 is feasible and interior to the box.  Returned in the user form
+    rlo = rhi = 0.  Draw order: A, q, G, x0."""
+    rng = _rng(seed)
+    r = n if rank is None else rank
+    A = rng.standard_normal((r, n))
+    Q = A.T @ A / n + reg * np.eye(n)
+    Q = 0.5 * (Q + Q.T)
+    q = rng.standard_normal(n)
+    G = rng.standard_normal((p, n))
+    x0 = rng.uniform(-0.5 * box, 0.5 * box, n)
+    g = -(G @ x0)
+    z = np.zeros(p)
+    return QP(Q, q, G, g, -box * np.ones(n), box * np.ones(n), dict(kind="eq", seed=seed), z.copy(), z.copy())
+
+
+def random_rows_qp(n: int, p: int, seed=0, reg: float = 0.1) -> QP:
+    """Dense QP in the user form rlo <= G u + g <= rhi (Sec. 2) with every
+    kind of row: row i draws its kind uniformly from {equality, upper side
+    only, lower side only, both sides}.  Q = A^T A / n + reg I (A 2n x n),
+    q ~ N(0,1), G ~ N(0,1), x0 ~ U(-.5,.5), g = -(G x0); sides at distance
+    s ~ U(0.1, 1) from G x0 + g = 0 (an equality row at 0), so x0 satisfies
+    every inequality strictly.  Draw order: A, q, G, x0, kinds, s_lo, s_hi."""
+    rng = _rng(seed)
+    A = rng.standard_normal((2 * n, n))
+    Q = A.T @ A / n + reg * np.eye(n)
+    Q = 0.5 * (Q + Q.T)
+    q = rng.standard_normal(n)
+    G = rng.standard_normal((p, n))
+    x0 = rng.uniform(-0.5, 0.5, n)
+    g = -(G @ x0)
+    kind = rng.integers(0, 4, p)
+    s_lo = rng.uniform(0.1, 1.0, p)
+    s_hi = rng.uniform(0.1, 1.0, p)
+    rlo = np.where((kind == 2) | (kind == 3), -s_lo, -np.inf)
+    rhi = np.where((kind == 1) | (kind == 3), s_hi, np.inf)
+    rlo = np.where(kind == 0, 0.0, rlo)
+    rhi = np.where(kind == 0, 0.0, rhi)
+    return QP(Q, q, G, g, -np.ones(n), np.ones(n), dict(kind="rows", seed=seed), rlo, rhi)
 
 
 def config0() -> QP:

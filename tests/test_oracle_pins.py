@@ -716,3 +716,157 @@ def test_gradmap_certificate_valid_on_ill_conditioned_instances():
         xp = np.clip(y - (Q @ y + q) / L, lb, ub)
         cert = dfom.gradmap_certificate(y, xp, L, lb, ub, 0.0)
         assert objective(Q, q, xp) - phis <= cert + 1e-12
+
+
+# ----------------------------------------------------------------------------
+# Equality rows (K = {0}) and the user form lbar <= G u + g <= ubar (Sec. 2)
+# ----------------------------------------------------------------------------
+
+def _stacked(qp):
+    Gs, gs, eq, src, sign = dfom.stack_rows(qp.G, qp.g, qp.rlo, qp.rhi)
+    return gen.QP(qp.Q, qp.q, Gs, gs, qp.lb, qp.ub, eq=eq), src, sign
+
+
+def test_stack_rows_describes_the_same_feasible_set():
+    # row by row: u satisfies rlo_i <= G_i u + g_i <= rhi_i exactly when it
+    # satisfies every stacked row made from row i (random points near the sides)
+    qp = gen.random_rows_qp(5, 12, seed=201)
+    sq, src, sign = _stacked(qp)
+    rng = np.random.default_rng(202)
+    tol = 1e-12
+    seen = np.zeros((qp.p, 2), int)
+    for _ in range(4000):
+        u = rng.uniform(-1, 1, 5) * rng.choice([0.02, 0.2, 1.0])
+        r = qp.G @ u + qp.g
+        rs = sq.G @ u + sq.g
+        ok_s = np.where(sq.eq, np.abs(rs) <= tol, rs <= tol)
+        for i in range(qp.p):
+            if qp.rlo[i] == qp.rhi[i]:
+                user = abs(r[i] - qp.rhi[i]) <= tol
+            else:
+                user = (r[i] >= qp.rlo[i] - tol) and (r[i] <= qp.rhi[i] + tol)
+            assert user == bool(np.all(ok_s[src == i])), i
+            seen[i, int(user)] += 1
+    # both outcomes occur for every inequality row
+    ineq_rows = qp.rlo != qp.rhi
+    assert np.all(seen[ineq_rows] > 0)
+    assert np.all(sign[sq.eq] == 1.0) and set(src) == set(range(qp.p))
+    assert int(sq.eq.sum()) == int(np.sum(qp.rlo == qp.rhi))
+
+
+def test_inner_gradient_with_equality_rows_by_finite_differences():
+    # rho > 0: the derivative of L_rho(., mu) with rows in R_- and rows in {0}
+    qp = gen.random_rows_qp(6, 7, seed=203)
+    sq, _, _ = _stacked(qp)
+    rng = np.random.default_rng(204)
+    for rho in (0.0, 0.8):
+        for _ in range(5):
+            u = rng.uniform(-1, 1, 6)
+            mu = rng.standard_normal(sq.p)
+            gr = dfom.inner_gradient(sq.Q, sq.q, sq.G, sq.g, u, mu, rho, sq.eq)
+            h = 1e-6
+            fd = np.array([(dfom.lagrangian(sq.Q, sq.q, sq.G, sq.g, u + h * e, mu, rho, sq.eq)
+                            - dfom.lagrangian(sq.Q, sq.q, sq.G, sq.g, u - h * e, mu, rho, sq.eq)) / (2 * h)
+                           for e in np.eye(6)])
+            np.testing.assert_allclose(gr, fd, rtol=1e-6, atol=1e-6)
+
+
+def test_equality_rows_add_rho_GtG_to_the_inner_hessian():
+    # all rows equalities, rho > 0: L_rho(., mu) is the quadratic with Hessian
+    # Q + rho G^T G (Sec. 5.1), so sigma_in is its smallest eigenvalue, here
+    # positive although Q is singular (Sec. 2, Case 2)
+    qp = gen.random_eq_qp(6, 3, seed=205, rank=3)
+    sq, _, _ = _stacked(qp)
+    assert np.all(sq.eq)
+    rho = 1.7
+    c = problem_constants(sq.Q, sq.G, sq.lb, sq.ub, rho, 1e-6, eq=sq.eq)
+    rng = np.random.default_rng(206)
+    mu = rng.standard_normal(3)
+    u0 = rng.uniform(-1, 1, 6)
+    H = np.empty((6, 6))
+    h = 1e-4
+    for j, e in enumerate(np.eye(6)):
+        H[:, j] = (dfom.inner_gradient(sq.Q, sq.q, sq.G, sq.g, u0 + h * e, mu, rho, sq.eq)
+                   - dfom.inner_gradient(sq.Q, sq.q, sq.G, sq.g, u0 - h * e, mu, rho, sq.eq)) / (2 * h)
+    assert np.linalg.eigvalsh(sq.Q)[0] < 1e-12
+    assert math.isclose(c.sigma_in, np.linalg.eigvalsh(0.5 * (H + H.T))[0], rel_tol=1e-6)
+    assert c.sigma_in > 1e-3
+
+
+@pytest.mark.parametrize("method", [DGM, DFGM])
+@pytest.mark.parametrize("seed", [211, 212, 213])
+def test_rows_qp_reaches_bruteforce_optimum(method, seed):
+    # every kind of row; Q > 0, rho = 0: multipliers of equality rows are free
+    qp = gen.random_rows_qp(4, 3, seed=seed, reg=0.3)
+    sq, _, _ = _stacked(qp)
+    xs, fs, lam_s = brute_force_qp(sq.Q, sq.q, sq.G, sq.g, sq.lb, sq.ub, eq=sq.eq)
+    r = dfom_solve(sq, tight(method=method, eps_out=1e-8, eps_in=1e-14, max_outer=200000))
+    assert r.status == dfom.STATUS_OK
+    assert abs(r.F - fs) <= 1e-7 * max(1.0, abs(fs))
+    assert np.max(np.abs(r.x - xs)) <= 1e-5
+    assert np.all(r.lam[~sq.eq] >= 0.0)
+    # the interior-point solver with the equality rows as equations agrees
+    ineq = ~sq.eq
+    _, fi, _, _ = ipm_qp(sq.Q, sq.q, sq.G[ineq], sq.g[ineq], sq.lb, sq.ub, E=sq.G[sq.eq], e=sq.g[sq.eq])
+    assert abs(fi - fs) <= 1e-8 * max(1.0, abs(fs))
+
+
+def _kkt_eq_closed_form(Q, q, E, e):
+    # min 1/2 x^T Q x + q^T x s.t. E x + e = 0: [Q E^T; E 0][x; y] = [-q; -e]
+    n, m = Q.shape[0], E.shape[0]
+    K = np.block([[Q, E.T], [E, np.zeros((m, m))]])
+    sol = np.linalg.solve(K, np.concatenate([-q, -e]))
+    return sol[:n], sol[n:]
+
+
+@pytest.mark.parametrize("method", [DGM, DFGM])
+def test_equality_qp_singular_hessian_closed_form(method):
+    # Sec. 2 Case 2 (Q singular, rho > 0) with K = {0}: the box is wide enough
+    # to be inactive, so the optimum is the equality-constrained KKT solution
+    qp = gen.random_eq_qp(8, 3, seed=215, rank=6)
+    xs, ys = _kkt_eq_closed_form(qp.Q, qp.q, qp.G, qp.g)
+    box = 1.5 * float(np.max(np.abs(xs)))
+    sq = gen.QP(qp.Q, qp.q, qp.G, qp.g, -box * np.ones(8), box * np.ones(8), eq=np.ones(3, bool))
+    fs = objective(sq.Q, sq.q, xs)
+    r = dfom_solve(sq, tight(method=method, rho=2.0, eps_out=1e-9, eps_in=1e-12, max_outer=400000))
+    assert r.status == dfom.STATUS_OK
+    assert abs(r.F - fs) <= 1e-6 * max(1.0, abs(fs))
+    assert np.linalg.norm(sq.G @ r.x + sq.g) <= 1e-6
+    # the multipliers of the equations (free sign) are the KKT ones
+    np.testing.assert_allclose(r.lam, ys, rtol=1e-4, atol=1e-4)
+
+
+@pytest.mark.parametrize("rho", [0.0, 1.0])
+def test_rows_qp_weak_duality_along_the_run(rho):
+    # P4 with equality rows: every certified bound dbar_k - gap_k (taken where
+    # weak duality holds: mu >= 0 on inequality rows, or any mu with rho > 0)
+    # stays below F*, and the final point passes KKT to the tolerance
+    qp = gen.random_rows_qp(6, 5, seed=217, reg=0.2)
+    sq, _, _ = _stacked(qp)
+    xs, fs, _ = brute_force_qp(sq.Q, sq.q, sq.G, sq.g, sq.lb, sq.ub, eq=sq.eq)
+    r = dfom_solve(sq, Options(method=DFGM, rho=rho, eps_out=1e-7, eps_in=1e-11, max_outer=200000))
+    assert r.status == dfom.STATUS_OK
+    for e in r.log:
+        if math.isfinite(e["LB"]):
+            assert e["LB"] <= fs + 1e-9 * max(1.0, abs(fs))
+    x, lam = r.x, r.lam
+    grad = sq.Q @ x + sq.q + sq.G.T @ lam
+    kkt = np.max(np.abs(x - np.clip(x - grad, sq.lb, sq.ub)))
+    assert kkt <= 1e-3
+    assert dfom.dist_K(sq.G @ x + sq.g, sq.eq) <= 1e-6
+
+
+def test_infeasible_equality_row_is_certified():
+    # an equation no point of the box satisfies: the multiplier of an equality
+    # row (free sign) certifies it
+    qp = gen.random_dense_qp(5, 2, seed=219)
+    G = np.vstack([qp.G, np.ones((1, 5))])
+    g = np.concatenate([qp.g, [-9.0]])          # sum u = 9 is out of reach in [-1, 1]^5
+    eq = np.array([False, False, True])
+    sq = gen.QP(qp.Q, qp.q, G, g, qp.lb, qp.ub, eq=eq)
+    r = dfom_solve(sq, Options(method=DFGM, eps_out=1e-6, eps_in=1e-10, max_outer=100000))
+    assert r.status == dfom.STATUS_INFEASIBLE
+    mu = r.lam
+    assert np.all(mu[~eq] >= 0.0)
+    w = G.T @ mu
+    assert mu @ g + np.sum(np.minimum(sq.lb * w, sq.ub * w)) > 0.0
