@@ -20,8 +20,10 @@ design notes):
         mapping G_L = L (y - x):
         min(sum_i max(G_i (y_i - lb_i), G_i (y_i - ub_i)) - ||G_L||^2/(2L),
             ||G_L||^2 (1/sigma - 1/L) / 2)  [second term only when sigma > 0].
-    With rho = 0 the exact-gradient form is used at every inner iterate.
-    With rho > 0 the exact form is used for the warm start x^0 and the
+    With rho = 0, and with rho > 0 when every row is an equality (the inner
+    gradient is then affine in u: constant Hessian Q + rho G^T G, Sec. 5.1),
+    the exact-gradient form is used at every inner iterate.  Otherwise, with
+    rho > 0, the exact form is used for the warm start x^0 and the
     gradient-mapping form after each step (it needs no extra product).
     The loop also stops at the iteration count k_in of Sec. 5 (natural log,
     rounded up), which by Lemma lemma_sublin_dfg already implies the
@@ -322,7 +324,11 @@ def fom_inner(Q, q, G, g, lb, ub, mu, rho: float, c: Constants, x0,
     def done(gap, t):
         return (rule == CERT and gap <= eps_in) or t >= k_max
 
-    if rho == 0.0:
+    # The gradient is affine in u when rho = 0, and when rho > 0 with every row
+    # an equality (the constant inner Hessian Q + rho G^T G of Sec. 5.1): then
+    # the exact-gradient certificate is taken at every iterate.
+    affine = rho == 0.0 or (eq is not None and G.shape[0] > 0 and bool(np.all(eq)))
+    if affine:
         x_prev = x = x0.copy()
         t = 0
         while True:

@@ -870,3 +870,67 @@ def test_infeasible_equality_row_is_certified():
     assert np.all(mu[~eq] >= 0.0)
     w = G.T @ mu
     assert mu @ g + np.sum(np.minimum(sq.lb * w, sq.ub * w)) > 0.0
+
+
+# ----------------------------------------------------------------------------
+# Parameter planning: eq. choose_ein (Sec. 3.1) and rho* (Sec. 5)
+# ----------------------------------------------------------------------------
+
+from oracle import plan as oplan  # noqa: E402
+
+
+@pytest.mark.parametrize("method", [DGM, DFGM])
+@pytest.mark.parametrize("eps,Ld,Rd", [(1e-2, 540.0, 3.0), (1e-4, 2.0, 0.5), (1e-3, 1.3e5, 12.0)])
+def test_plan_makes_each_term_of_the_dual_bound_half_eps(method, eps, Ld, Rd):
+    # Theorem lemma_sublin_dfg_inexact: with eq. choose_ein both terms of the
+    # bound are about eps/2 at k_out (the second exactly eps/2 when k_out + 1 is
+    # read as the unrounded k_out, as the derivation does: within 2/k_out of it
+    # for DFGM), and k_out is the first k where the first term is <= eps/2
+    # (found by direct search over k, not by inverting the formula)
+    pl = oplan.plan(method, eps, Ld, Rd)
+    t1, t2 = oplan.dual_rate_terms(method, Ld, Rd, pl.k_out, pl.eps_in)
+    assert t1 <= eps / 2 * (1 + 1e-12)
+    assert eps / 2 * (1 - 1e-12) <= t2 <= eps / 2 * (1 + 2.0 / pl.k_out + 1e-12)
+    ok = lambda k: oplan.dual_rate_terms(method, Ld, Rd, k, 0.0)[0] <= eps / 2 * (1 + 1e-12)
+    hi = 1
+    while not ok(hi):                 # the first term decreases in k: bracket, then bisect
+        hi *= 2
+    lo = hi // 2
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        lo, hi = (lo, mid) if ok(mid) else (mid, hi)
+    k = hi if not ok(lo) else lo
+    assert pl.k_out in (k, k + 1), (pl.k_out, k)
+    assert math.isclose(pl.rho_star * eps / (8 * Rd * Rd), 1.0, rel_tol=1e-15)
+
+
+def _dual_exact(qp, lam):
+    # d(lam) = min over the box of F(u) + lam^T (G u + g), by face enumeration
+    _, v = box_qp_exact(qp.Q, qp.q + qp.G.T @ lam, qp.lb, qp.ub)
+    return v + float(lam @ qp.g)
+
+
+@pytest.mark.parametrize("seed", [401, 402, 403])
+def test_planned_dfgm_reaches_eps_dual_suboptimality(seed):
+    # the claim of Sec. 3.1: with R_d exact (lambda^0 = 0: R_d = ||lambda*||),
+    # eps_in and k_out from eq. choose_ein give F* - d(lambda^k_out) <= eps
+    qp = tiny_qp(4, 3, seed)
+    xs, fs, lam_s = brute_force_qp(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub)
+    Rd = max(float(np.linalg.norm(lam_s)), 1e-3)
+    c0 = problem_constants(qp.Q, qp.G, qp.lb, qp.ub, 0.0, 1e-6)
+    for eps in (1e-2, 1e-3):
+        pl = oplan.plan(DFGM, eps, c0.Ld, Rd)
+        c = problem_constants(qp.Q, qp.G, qp.lb, qp.ub, 0.0, pl.eps_in)
+        r = dfom_solve(qp, Options(method=DFGM, eps_out=1e-15, eps_in=pl.eps_in, max_outer=pl.k_out), consts=c)
+        assert r.outer_iters == pl.k_out
+        assert fs - _dual_exact(qp, r.lam) <= eps
+
+
+def test_planned_solve_doubles_R_until_the_test_passes():
+    # a guess far below R_d: the rounds double it; the answer is eps-accurate
+    qp = gen.config0()
+    _, fstar, lam_s = ipm_qp(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub)
+    r = oplan.planned_solve(qp, DGM, 1e-3, R0=1e-3 * float(np.linalg.norm(lam_s)), max_rounds=20)
+    assert r.status == dfom.STATUS_OK and r.rounds > 1
+    assert [p.k_out for p in r.plans] == sorted(p.k_out for p in r.plans)
+    assert abs(r.F - fstar) <= 1e-3 * max(1.0, abs(fstar))
