@@ -60,10 +60,18 @@ enum { DUQ_ACC_F64 = 0, DUQ_ACC_F32 = 1 };                    /* product accumul
 enum { DUQ_ENGINE_AUTO = 0, DUQ_ENGINE_BLOCK = 1, DUQ_ENGINE_GRID = 2,
        DUQ_ENGINE_TILE = 3 };   /* TILE: shared batches only, see duq_solve_batch */
 
-/* ---- problem data (Sec. 2, eq. original_primal) ------------------------- */
+/* ---- problem data (Sec. 2, eq. original_primal) ------------------------- *
+ * Constraints: G u + g <= 0 (K = R^p_-) when rlo and rhi are NULL.  With
+ * both given, the user form of Sec. 2, rlo <= G u + g <= rhi row by row:
+ * rlo_i = rhi_i makes row i an equality (K_i = {0}); otherwise -INFINITY /
+ * +INFINITY marks an absent side and each finite side is one inequality
+ * (two-sided rows read their row of G once per product).  Multipliers of
+ * equality rows are free; the multiplier returned per row is
+ * lambda+ - lambda- (positive: the upper side binds).  Row bounds are
+ * available on duq_setup / duq_solve (not in batches or the serving loop). */
 typedef struct duq_problem {
     int32_t n;            /* variables, n >= 1                                  */
-    int32_t p;            /* inequality rows, p >= 0                            */
+    int32_t p;            /* constraint rows, p >= 0                            */
     int32_t dtype;        /* DUQ_F64 or DUQ_F32: element type of Q and G        */
     int32_t memspace;     /* DUQ_HOST (copied) or DUQ_DEVICE (borrowed)         */
     const void *Q;        /* n x n row-major, symmetric                          */
@@ -72,15 +80,22 @@ typedef struct duq_problem {
     const double *g;      /* p                                                   */
     const double *lb;     /* n, lb <= ub                                         */
     const double *ub;     /* n                                                   */
+    const double *rlo;    /* p or NULL: lower row bounds (-INFINITY: none)      */
+    const double *rhi;    /* p or NULL: upper row bounds (+INFINITY: none)      */
 } duq_problem;
 
 /* ---- solver options ----------------------------------------------------- *
  * Initialise with duq_default_options().  Spectral constants lam_min(Q),
  * lam_max(Q) and ||G||^2 set to a value <= 0 are estimated on the device by
- * an FP64 Lanczos process (k steps), inflated by `safety`.  From them:
+ * an FP64 Lanczos process (k steps), inflated by `safety`.  With row bounds
+ * ||G||^2 is that of the rows in cone form (a two-sided row counts twice:
+ * lambda_max(G^T W G), W_ii = number of finite sides).  From them:
  *   L_d = ||G||^2/(lam_min + rho ||G||^2)   (Sec. 2 eq. Ld), outer step 1/(2 L_d)
  *   L_in = lam_max + rho ||G||^2, sigma_in = lam_min       (Sec. 3, Step 1)
- *   k_in cap of Sec. 5 (natural log, rounded up) unless max_inner > 0.      */
+ *   k_in cap of Sec. 5 (natural log, rounded up) unless max_inner > 0.
+ * sigma_in > 0 overrides the strong convexity of the inner problem; when it
+ * is <= 0 and every row is an equality with rho > 0 it is lambda_min(Q + rho
+ * G^T G) (Sec. 3, Step 1, K = {0}), estimated on the formed matrix.         */
 typedef struct duq_options {
     int32_t method;         /* DUQ_DGM | DUQ_DFGM                                */
     int32_t output;         /* DUQ_LAST | DUQ_AVG                                */
@@ -104,7 +119,9 @@ typedef struct duq_options {
     int32_t serve_slice;    /* serving loop: outer iterations per round (0 = 16)  */
     int32_t out_memspace;   /* duq_solve_batch: X_out / Lam_out are DUQ_HOST
                                (default) or DUQ_DEVICE buffers                  */
-    int32_t reserved[5];
+    int32_t reserved0;
+    double sigma_in;        /* strong convexity of L_rho(., mu), or <= 0 (above) */
+    int32_t reserved[2];
 } duq_options;
 
 /* ---- per-solve result --------------------------------------------------- *
@@ -160,7 +177,10 @@ int duq_max_n(int32_t p, int32_t engine, int32_t *n_max);
 
 /* Run Algorithm DFOM (Sec. 3) to the outer test.  x0 (n) warm-starts the
  * inner solver and lam0 (p) the multipliers (both host, may be NULL:
- * x0 = projection of 0 onto the box, lam0 = 0, Sec. 4).  x_out (n) and
+ * x0 = projection of 0 onto the box, lam0 = 0, Sec. 4; lam0 must be NULL
+ * with row bounds).  Every row an equality with rho > 0: duq_setup forms
+ * Q + rho G^T G once (the constant inner Hessian of Sec. 5.1), so an inner
+ * step reads one n x n matrix as with rho = 0.  x_out (n) and
  * lam_out (p) are host buffers (may be NULL).  Returns the result status
  * (DUQ_OK, DUQ_EMAXITER with the last iterate written, DUQ_ENUMERIC,
  * DUQ_EINFEASIBLE with the certificate in lam_out) or an error code.  With
@@ -175,12 +195,47 @@ int duq_solve(duq_handle *h, const double *x0, const double *lam0,
 /* Per-outer-iteration trace of the last duq_solve for the first
  * opts.trace_outer iterations: record k (k = 0..) is
  *   [DUQ_TRACE_SCALARS doubles][lambda^k (p)][mu^k (p)][ubar^k (n)]
+ * and with row bounds [..][lambda+ (p)][mu+ (p)][ubar (n)][lambda- (p)][mu- (p)]
+ * (sides a row does not have read 0).
  * Scalars: k, t_k, gap_k, dbar_k, LB_k, theta_k, S_k, F(cand), feas(cand),
  * ||lambda^k||, passed, extra_t, extra_gap, F2, feas2, passed2.
- * `out` holds max_records*(DUQ_TRACE_SCALARS+2p+n) doubles; *n_records gets
- * the number written.                                                       */
+ * `out` holds max_records*(DUQ_TRACE_SCALARS+2p+n) doubles (+2p with row
+ * bounds); *n_records gets the number written.                              */
 #define DUQ_TRACE_SCALARS 16
 int duq_get_trace(duq_handle *h, double *out, int32_t max_records, int32_t *n_records);
+
+/* ---- parameter planning (Sec. 3.1 eq. choose_ein, Sec. 5) --------------- *
+ * duq_plan_params: for a target accuracy eps of the dual function and
+ * R_d = min ||lambda* - lambda^0|| (Sec. 2), the inner accuracy and outer
+ * iteration count of eq. choose_ein that make both terms of the rate bound
+ * of Theorem lemma_sublin_dfg_inexact at most about eps/2:
+ *   DGM:  eps_in = eps/4,                        k_out = ceil(8 L_d R_d^2/eps)
+ *   DFGM: eps_in = eps^(3/2)/(8 R_d sqrt(2 L_d)), k_out = ceil(sqrt(8 L_d R_d^2/eps))
+ * the penalty rho* = 8 R_d^2/eps of Theorem in:th_last, and (when L_in > 0
+ * and D_U > 0 are given) the inner count k_in of Sec. 5 at that eps_in
+ * (sigma_in > 0: linear rate, else sublinear) with k_total = k_out k_in.
+ * Errors: DUQ_EINVAL (method, eps <= 0, L_d <= 0, R_d <= 0, null out).     */
+typedef struct duq_plan {
+    double eps_in;
+    int64_t k_out;
+    double rho_star;
+    int64_t k_in;        /* 0 when L_in or D_U was not given */
+    int64_t k_total;
+} duq_plan;
+int duq_plan_params(int32_t method, double eps, double Ld, double Rd, double L_in, double sigma_in,
+                    double D_U, duq_plan *out);
+
+/* duq_solve_planned: Algorithm DFOM with eps_in and max_outer planned from a
+ * guess R of R_d (the paper leaves a search on R_d open): the outer test runs
+ * at eps; when it has not passed after k_out(R) outer iterations the guess
+ * doubles and the next round starts from the last x (and lambda, without row
+ * bounds).  R0 > 0 is the first guess, max_rounds >= 1 the number of rounds.
+ * x_out (n) and lam_out (p) are host buffers (required); res sums the outer
+ * and inner iterations of all rounds; *R_out (may be NULL) gets the last
+ * guess and *rounds_out (may be NULL) the rounds run.  The handle's options
+ * are restored afterwards.  Returns as duq_solve.                          */
+int duq_solve_planned(duq_handle *h, double eps, double R0, int32_t max_rounds, double *x_out,
+                      double *lam_out, duq_result *res, double *R_out, int32_t *rounds_out);
 
 /* Constants in use: lambda_min(Q), lambda_max(Q), ||G||^2, L_d, L_in, sigma_in. */
 int duq_get_constants(duq_handle *h, double *lam_min, double *lam_max,

@@ -104,6 +104,9 @@ __device__ inline void batch_carve(char* base, int n, int p, int k, DevWork& W, 
     L.part = nullptr;
     L.gtp = nullptr;
     L.bar = nullptr;
+    W.lamm = nullptr;
+    W.mum = nullptr;
+    W.nu = nullptr;
     W.part = nullptr;
     W.gtp = nullptr;
     W.trace = nullptr;

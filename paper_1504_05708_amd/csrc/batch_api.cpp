@@ -20,7 +20,7 @@ int set_error(int code, const std::string& msg);
 int device_cus();
 void handle_params(duq_handle* h, DevParams* par);
 int derive_params(int p, double lam_min, double lam_max, double g2, double D_U, const duq_options& o,
-                  DevParams* par);
+                  DevParams* par, double sigma);
 }
 
 namespace {
@@ -101,7 +101,7 @@ int solve_shared_tiles(const duq_batch* b, const duq_options* o, hipStream_t s, 
                 return set_error(DUQ_EINVAL, "box must be finite with lb <= ub");
             du2 += (hi[i] - lo[i]) * (hi[i] - lo[i]);
         }
-        int rc = derive_params(p, oo.lam_min, oo.lam_max, p ? oo.G_norm2 : 0.0, std::sqrt(du2), oo, &t.par);
+        int rc = derive_params(p, oo.lam_min, oo.lam_max, p ? oo.G_norm2 : 0.0, std::sqrt(du2), oo, &t.par, 0.0);
         if (rc) return rc;
         t.lam_min = oo.lam_min;
         t.lam_max = oo.lam_max;

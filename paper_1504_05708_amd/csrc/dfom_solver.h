@@ -338,7 +338,26 @@ __device__ __forceinline__ void stage_shared(const double* src, int len, double*
 template <typename T>
 __host__ __device__ constexpr bool short_rows(int n) { return n <= 2 * kWave * (int)(16 / sizeof(T)); }
 
-template <typename T, typename Acc, bool SHORT>
+// A row of the user form rlo <= G_i u + g_i <= rhi (Sec. 2) in the cone form
+// G u + g in K: an equality G_i u + g_i - rhi = 0 (K_i = {0}, free
+// multiplier) when rlo = rhi; otherwise an upper side G_i u + g_i - rhi <= 0
+// when rhi is finite and a lower side rlo - G_i u - g_i <= 0 when rlo is
+// finite (K_i = R_-, one multiplier each: lambda+ and lambda-).
+struct RowSides {
+    double lo, hi;
+    bool up, dn, eq;
+};
+__device__ __forceinline__ RowSides row_sides(const double* rlo, const double* rhi, int i) {
+    RowSides s;
+    s.lo = rlo[i];
+    s.hi = rhi[i];
+    s.eq = s.lo == s.hi;
+    s.up = s.hi < INFINITY;
+    s.dn = !s.eq && s.lo > -INFINITY;
+    return s;
+}
+
+template <typename T, typename Acc, bool SHORT, bool ROWS = false>
 struct Dfom {
     DevProblem<T> P;
     DevParams par;
@@ -420,8 +439,13 @@ struct Dfom {
 
     // z = add + A^T v restricted to owned columns (full v on the team).
     __device__ __forceinline__ bool gemvT(const double* v, const double* add, double* z) {
+        return gemvT_w([&](int i) { return v[i]; }, add, z);
+    }
+    // z = add + A^T w with w_i = wt(i) for the owned rows.
+    template <typename F>
+    __device__ __forceinline__ bool gemvT_w(F wt, const double* add, double* z) {
         const int n = P.n;
-        for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) vl[i - plo] = v[i];
+        for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) vl[i - plo] = wt(i);
         __syncthreads();
         if (tm.size == 1) {
             gt_rows += gemvT_rows<T, Acc, false>(P.G, n, plo, phi, n, vl, z, add, false, tl);
@@ -511,7 +535,7 @@ struct Dfom {
     // Gradient Q y + q + G^T [mu + rho (G y + g)]_+ at the extrapolated point
     // only; G y and Q y follow by linearity from G x, Q x.  Certificate: exact
     // at x^0, gradient-mapping bound after each projected step.
-    __device__ __forceinline__ int inner_rhop(int& cur, const double* mu, double& gap) {
+    __device__ __forceinline__ int inner_rhop(int& cur, const double* mu, const double* mum, double& gap) {
         const int n = P.n;
         int prv = cur;
         int t = 0;
@@ -520,11 +544,25 @@ struct Dfom {
             const int nxt = third(cur, prv);
             const double* x = X(cur);
             const double* xp = X(prv);
-            // w = [mu + rho (G y + g)]_+ on owned rows, G y by linearity
+            // w = [mu + rho (G y + g)]_+ on owned rows, G y by linearity; with
+            // row bounds w = mu + rho (G y + g - s) per side (s the projection
+            // onto K_i), the lower side entering with a minus sign
             for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) {
                 const double gxi = GX(cur)[i];
                 const double gyi = gxi + beta * (gxi - GX(prv)[i]);
-                W.wv[i] = fmax(mu[i] + par.rho * (gyi + P.g[i]), 0.0);
+                if constexpr (ROWS) {
+                    const RowSides sd = row_sides(P.rlo, P.rhi, i);
+                    const double ry = gyi + P.g[i];
+                    double w = 0.0;
+                    if (sd.up) {
+                        const double v = mu[i] + par.rho * (ry - sd.hi);
+                        w += sd.eq ? v : fmax(v, 0.0);
+                    }
+                    if (sd.dn) w -= fmax(mum[i] + par.rho * (sd.lo - ry), 0.0);
+                    W.wv[i] = w;
+                } else {
+                    W.wv[i] = fmax(mu[i] + par.rho * (gyi + P.g[i]), 0.0);
+                }
             }
             __syncthreads();
             // h = q + G^T w into W.c (owned columns)
@@ -580,10 +618,21 @@ struct Dfom {
     // of its terms proves that no u in the box has G u + g <= 0.  The test
     // takes one team reduction; it runs at every kInfeasEvery-th outer
     // iteration, outside the inner loop.
-    __device__ __forceinline__ int inner(int& cur, const double* mu, double& gap, bool farkas) {
-        if (par.rho > 0.0) return inner_rhop(cur, mu, gap);
-        if (!gemvT(mu, P.q, W.c)) return -1;   // c = q + G^T mu (Sec. 5.1)
-        if (farkas && P.p > 0) {
+    __device__ __forceinline__ int inner(int& cur, const double* mu, const double* mum, double& gap, bool farkas) {
+        if (par.rho > 0.0 && !par.eqform) return inner_rhop(cur, mu, mum, gap);
+        if constexpr (ROWS) {
+            // c = q + G^T (lambda+ - lambda-); in the equality form (all rows
+            // equalities, Q + rho G^T G held in Q) c = q + G^T (mu + rho (g - rhi))
+            // (Sec. 5.1: the constant part rho G^T g folded into the weights)
+            if (par.eqform) {
+                if (!gemvT_w([&](int i) { return mu[i] + par.rho * (P.g[i] - P.rhi[i]); }, P.q, W.c)) return -1;
+            } else {
+                if (!gemvT_w([&](int i) { return mu[i] - mum[i]; }, P.q, W.c)) return -1;
+            }
+        } else {
+            if (!gemvT(mu, P.q, W.c)) return -1;   // c = q + G^T mu (Sec. 5.1)
+        }
+        if (farkas && P.p > 0 && par.rho == 0.0) {
             double e[3] = {0.0, 0.0, 0.0};   // v, scale, #(mu < 0)
             for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x) {
                 const double w = W.c[i] - P.q[i], lo = P.lb[i], hi = P.ub[i];
@@ -591,10 +640,28 @@ struct Dfom {
                 e[1] += fabs(w) * fmax(fabs(lo), fabs(hi));
             }
             for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) {
-                const double m = mu[i], mg = m * P.g[i];
-                e[0] += mg;
-                e[1] += fabs(mg);
-                e[2] += m < 0.0 ? 1.0 : 0.0;
+                if constexpr (ROWS) {
+                    // mu^T (G u + g - shifts) over the sides; equality multipliers
+                    // may take either sign
+                    const RowSides sd = row_sides(P.rlo, P.rhi, i);
+                    if (sd.up) {
+                        const double m = mu[i], mg = m * (P.g[i] - sd.hi);
+                        e[0] += mg;
+                        e[1] += fabs(mg);
+                        e[2] += (!sd.eq && m < 0.0) ? 1.0 : 0.0;
+                    }
+                    if (sd.dn) {
+                        const double m = mum[i], mg = m * (sd.lo - P.g[i]);
+                        e[0] += mg;
+                        e[1] += fabs(mg);
+                        e[2] += m < 0.0 ? 1.0 : 0.0;
+                    }
+                } else {
+                    const double m = mu[i], mg = m * P.g[i];
+                    e[0] += mg;
+                    e[1] += fabs(mg);
+                    e[2] += m < 0.0 ? 1.0 : 0.0;
+                }
             }
             if (!allreduce<3>(e)) return -1;
             if (e[2] == 0.0 && e[0] > kInfeasMargin * e[1]) return -3;
@@ -605,7 +672,7 @@ struct Dfom {
     // After an inner solve ending in xb[cur]: r = G u + g on owned rows (for
     // rho > 0 G u is already in gx[cur]).
     __device__ __forceinline__ void residual(int cur) {
-        if (par.rho > 0.0) {
+        if (par.rho > 0.0 && !par.eqform) {
             for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) W.r[i] = GX(cur)[i] + P.g[i];
             __syncthreads();
             return;
@@ -625,6 +692,93 @@ struct Dfom {
     __device__ __forceinline__ void write_outputs(const double* x, double scale, bool shared) {
         for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x)
             W.xout[i] = (shared ? get(x + i) : x[i]) * scale;
+    }
+
+    // ---- dual step with row bounds (Algorithm DFOM steps 2-3) ---------------
+    // The rows of the user form, each side an inequality of K = R_- or the row
+    // an equality of K = {0}, updated on owned rows: the partial sums of the
+    // outer test (same slots as the one-sided form) and lambda, mu of each side.
+    // Equality form: the rho ||G u||^2 parts of u^T (Q + rho G^T G) u are taken
+    // off a[0] (last iterate) and a[8] (theta-weighted sum, scaled by S^2).
+    __device__ __forceinline__ void dual_rows(double (&a)[11], double thk, double beta, double Sn, double* trec) {
+        const int n = P.n, p = P.p;
+        const double rho = par.rho;
+        for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) {
+            const RowSides sd = row_sides(P.rlo, P.rhi, i);
+            const double ri = W.r[i];
+            const double rs = W.rs[i] + thk * ri;
+            W.rs[i] = rs;
+            const double ravg = rs / Sn;
+            auto side = [&](double e, double ea, double* mu, double* lam, bool eq, double* tlam, double* tmu) {
+                const double mui = mu[i];
+                double dg;
+                if (rho > 0.0) {
+                    const double v = e + mui / rho;
+                    const double vk = eq ? v : fmax(v, 0.0);
+                    a[2] += vk * vk;
+                    a[3] += mui * mui;
+                    dg = eq ? e : e - fmin(v, 0.0);
+                } else {
+                    a[2] += mui * e;
+                    dg = e;
+                }
+                const double ep = eq ? e : fmax(e, 0.0);
+                a[4] += ep * ep;
+                double lk = mui + par.alpha * dg;
+                if (par.Kd_nonneg && !eq) lk = fmax(lk, 0.0);
+                a[5] += lk * lk;
+                const double hp = eq ? ea : fmax(ea, 0.0);
+                a[6] += hp * hp;
+                a[7] += (!eq && mui < 0.0) ? 1.0 : 0.0;
+                a[10] += (!eq && lk < 0.0) ? 1.0 : 0.0;
+                if (trec) {
+                    tlam[i] = lk;
+                    tmu[i] = mui;
+                }
+                mu[i] = lk + beta * (lk - lam[i]);
+                lam[i] = lk;
+            };
+            double* t0 = trec ? trec + kTraceScalars : nullptr;
+            double* t1 = trec ? trec + kTraceScalars + p : nullptr;
+            double* t2 = trec ? trec + kTraceScalars + 2 * p + n : nullptr;
+            double* t3 = trec ? trec + kTraceScalars + 3 * p + n : nullptr;
+            if (sd.up) side(ri - sd.hi, ravg - sd.hi, W.mu, W.lamp, sd.eq, t0, t1);
+            else if (trec) { t0[i] = 0.0; t1[i] = 0.0; }
+            if (sd.dn) side(sd.lo - ri, sd.lo - ravg, W.mum, W.lamm, false, t2, t3);
+            else if (trec) { t2[i] = 0.0; t3[i] = 0.0; }
+            if (par.eqform) {
+                const double gu = ri - P.g[i], ga = ravg - P.g[i];
+                a[0] -= rho * gu * gu;
+                a[8] -= rho * ga * ga * Sn * Sn;
+            }
+        }
+    }
+
+    // Partial sums of the last-iterate test at lambda^k with row bounds.
+    __device__ __forceinline__ void extra_rows(double (&b)[6]) {
+        const double rho = par.rho;
+        for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) {
+            const RowSides sd = row_sides(P.rlo, P.rhi, i);
+            const double ri = W.r[i];
+            auto side = [&](double e, double li, bool eq) {
+                if (rho > 0.0) {
+                    const double v = e + li / rho;
+                    const double vk = eq ? v : fmax(v, 0.0);
+                    b[2] += vk * vk;
+                    b[3] += li * li;
+                } else {
+                    b[2] += li * e;
+                }
+                const double ep = eq ? e : fmax(e, 0.0);
+                b[4] += ep * ep;
+            };
+            if (sd.up) side(ri - sd.hi, W.lamp[i], sd.eq);
+            if (sd.dn) side(sd.lo - ri, W.lamm[i], false);
+            if (par.eqform) {
+                const double gu = ri - P.g[i];
+                b[0] -= rho * gu * gu;
+            }
+        }
     }
 
     // ---- Algorithm DFOM ---------------------------------------------------
@@ -654,14 +808,24 @@ struct Dfom {
                 W.lamp[i] = l;   // lambda^{-1} = lambda^0
                 W.mu[i] = l;     // mu^1 = lambda^0
                 W.rs[i] = 0.0;
-                gg[0] += P.g[i] * P.g[i];
+                if constexpr (ROWS) {
+                    // lambda^0 = 0 for both sides; ||g|| is the norm of the
+                    // constant terms of the sides
+                    W.lamm[i] = 0.0;
+                    W.mum[i] = 0.0;
+                    const RowSides sd = row_sides(P.rlo, P.rhi, i);
+                    const double gu = sd.up ? P.g[i] - sd.hi : 0.0, gd = sd.dn ? sd.lo - P.g[i] : 0.0;
+                    gg[0] += gu * gu + gd * gd;
+                } else {
+                    gg[0] += P.g[i] * P.g[i];
+                }
             }
             if (!allreduce<1>(gg)) return;
             gnorm = sqrt(gg[0]);
             if (tm.size > 1 && tm.sync()) return;
             stage_x(xb0);
             prodQ(qb0);
-            if (par.rho > 0.0) prodG(gx0, nullptr);
+            if (par.rho > 0.0 && !par.eqform) prodG(gx0, nullptr);
             __syncthreads();
             theta = 1.0;
             S = 0.0;
@@ -681,7 +845,7 @@ struct Dfom {
                 // products of the warm start in this launch's accumulation precision
                 stage_x(X(cur));
                 prodQ(QX(cur));
-                if (par.rho > 0.0) prodG(GX(cur), nullptr);
+                if (par.rho > 0.0 && !par.eqform) prodG(GX(cur), nullptr);
                 __syncthreads();
             }   // resume == 2: the stored products are this precision's; keep them
         }
@@ -696,13 +860,16 @@ struct Dfom {
             ++k;
             // Step 1: inner solve at mu^k, warm-started from ubar^{k-1}
             double gap = 0.0;
-            const int t = inner(cur, W.mu, gap, k % kInfeasEvery == 1);
+            const int t = inner(cur, W.mu, W.mum, gap, k % kInfeasEvery == 1);
             if (t == -1) return;
             if (t == -2) { status = 2; break; }
             if (t == -3) {
                 // mu^k certifies infeasibility: it is returned as the multiplier,
                 // the warm start ubar^{k-1} as the iterate
-                for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) W.lamp[i] = W.mu[i];
+                for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) {
+                    W.lamp[i] = W.mu[i];
+                    if constexpr (ROWS) W.lamm[i] = W.mum[i];
+                }
                 __syncthreads();
                 status = kStInfeasible;
                 ans_cur = cur;
@@ -720,7 +887,8 @@ struct Dfom {
 #pragma unroll
             for (int z = 0; z < 11; ++z) a[z] = 0.0;
             const bool tr = k <= par.trace_iters;
-            double* trec = tr ? W.trace + (long)(k - 1) * (kTraceScalars + 2 * p + n) : nullptr;
+            const long rec = ROWS ? kTraceScalars + 4L * p + n : kTraceScalars + 2L * p + n;
+            double* trec = tr ? W.trace + (long)(k - 1) * rec : nullptr;
             for (int i = nlo + (int)threadIdx.x; i < nhi; i += blockDim.x) {
                 const double ui = get(X(cur) + i), qui = QX(cur)[i];
                 a[0] += ui * qui;
@@ -732,6 +900,8 @@ struct Dfom {
                 a[9] += P.q[i] * us;
                 if (tr) trec[kTraceScalars + 2 * p + i] = ui;
             }
+            if constexpr (ROWS) dual_rows(a, thk, beta, Sn, trec);
+            else
             for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) {
                 const double ri = W.r[i], mui = W.mu[i];
                 double dg;
@@ -763,6 +933,8 @@ struct Dfom {
                 W.lamp[i] = lk;
             }
             if (!allreduce<11>(a)) return;
+            // equality form: a[0] and a[8] hold u^T (Q + rho G^T G) u terms with
+            // the rho ||G u||^2 parts already taken off (dual_rows)
             const double Fu = 0.5 * a[0] + a[1];
             const double dbar = par.rho > 0.0 ? Fu + 0.5 * par.rho * a[2] - a[3] / (2.0 * par.rho)
                                               : Fu + a[2];
@@ -795,7 +967,7 @@ struct Dfom {
                 __syncthreads();
                 int c2 = cur;
                 double gap2 = 0.0;
-                const int t2 = inner(c2, W.lamp, gap2, false);
+                const int t2 = inner(c2, W.lamp, W.lamm, gap2, false);
                 if (t2 == -1) return;
                 if (t2 == -2) { status = 2; break; }
                 inner_total += t2;
@@ -806,6 +978,8 @@ struct Dfom {
                     b[0] += ui * QX(c2)[i];
                     b[1] += P.q[i] * ui;
                 }
+                if constexpr (ROWS) extra_rows(b);
+                else
                 for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) {
                     const double ri = W.r[i], li = W.lamp[i];
                     if (par.rho > 0.0) {
@@ -862,6 +1036,10 @@ struct Dfom {
         // outputs
         if (ans_avg) write_outputs(W.us, 1.0 / S, false);
         else write_outputs(X(ans_cur), 1.0, true);
+        if constexpr (ROWS) {
+            // one multiplier per row: lambda+ - lambda- (an equality's own sign)
+            for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) W.nu[i] = W.lamp[i] - W.lamm[i];
+        }
         if (tm.rank == 0 && threadIdx.x == 0) {
             st->status = status;
             st->done = status == 0;

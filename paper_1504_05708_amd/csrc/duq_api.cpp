@@ -117,6 +117,11 @@ struct duq_handle {
     void* dG = nullptr;
     double *dq = nullptr, *dg = nullptr, *dlb = nullptr, *dub = nullptr;
     void* owned_data = nullptr;   // allocation holding copied data (HOST memspace)
+    // row bounds (user form of Sec. 2) and the equality form
+    bool rows = false;
+    bool eqform = false;
+    double *drlo = nullptr, *drhi = nullptr;
+    void* dH = nullptr;            // Q + rho G^T G (equality form), owned
     // constants
     double lam_min = 0, lam_max = 0, G2 = 0;
     double Ld = 0, alpha = 0, L_in = 0, sigma = 0, beta_in = 0, D_U = 0;
@@ -181,6 +186,7 @@ const char* duq_strerror(int code) {
 void duq_destroy(duq_handle* h) {
     if (!h) return;
     if (h->ws) (void)hipFree(h->ws);
+    if (h->dH) (void)hipFree(h->dH);
     if (h->owned_data) (void)hipFree(h->owned_data);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
@@ -199,6 +205,9 @@ int validate_problem(const duq_problem* pr, const duq_options* o) {
     if (pr->memspace != DUQ_HOST && pr->memspace != DUQ_DEVICE) return fail(DUQ_EINVAL, "bad memspace");
     if (!pr->Q || !pr->q || !pr->lb || !pr->ub) return fail(DUQ_EINVAL, "null Q, q, lb or ub");
     if (pr->p > 0 && (!pr->G || !pr->g)) return fail(DUQ_EINVAL, "null G or g with p > 0");
+    if ((pr->rlo == nullptr) != (pr->rhi == nullptr)) return fail(DUQ_EINVAL, "give both rlo and rhi, or neither");
+    if (pr->rlo && o->accumulate != DUQ_ACC_F64)
+        return fail(DUQ_EINVAL, "row bounds need FP64 accumulation (no precision switch)");
     if (o->method != DUQ_DGM && o->method != DUQ_DFGM) return fail(DUQ_EINVAL, "bad method");
     if (o->output != DUQ_LAST && o->output != DUQ_AVG) return fail(DUQ_EINVAL, "bad output");
     if (o->inner_rule != DUQ_CERT && o->inner_rule != DUQ_FIXED) return fail(DUQ_EINVAL, "bad inner_rule");
@@ -225,7 +234,7 @@ int estimate_constants(duq_handle* h, const DeviceInfo& di);
 // 1/(2 L_d); L_in = lam_max + rho ||G||^2, sigma_in = lam_min (Sec. 3 Step 1);
 // the inner cap k_in of Sec. 5 (natural log, rounded up) unless max_inner > 0.
 int derive_params(int p, double lam_min, double lam_max, double g2, double D_U, const duq_options& o,
-                  DevParams* par) {
+                  DevParams* par, double sigma) {
     const double rho = o.rho;
     const double denom = lam_min + rho * g2;
     if (p > 0 && !(denom > 0.0)) return fail(DUQ_EINVAL, "lambda_min(Q) = 0 needs rho > 0 (Sec. 2, Case 2)");
@@ -233,7 +242,9 @@ int derive_params(int p, double lam_min, double lam_max, double g2, double D_U, 
     const double Ld = p > 0 ? g2 / denom : 0.0;
     par->alpha = Ld > 0.0 ? 1.0 / (2.0 * Ld) : 0.0;
     par->L = lam_max + rho * g2;
-    par->sigma = std::max(lam_min, 0.0);
+    // sigma > 0: the strong convexity of the inner problem (with equality
+    // rows and rho > 0, lambda_min(Q + rho G_eq^T G_eq), Sec. 3 Step 1)
+    par->sigma = std::max(sigma > 0.0 ? sigma : lam_min, 0.0);
     const double sqL = std::sqrt(par->L), sqs = std::sqrt(par->sigma);
     par->beta_in = (sqL - sqs) / (sqL + sqs);
     int k_in;
@@ -319,6 +330,40 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
     }
     h->D_U = std::sqrt(du2);
 
+    // row bounds: rlo <= G u + g <= rhi (Sec. 2), each row an equality or up to
+    // two inequalities
+    std::vector<double> rlo, rhi;
+    if (pr->rlo) {
+        rlo.resize(std::max(p, 1));
+        rhi.resize(std::max(p, 1));
+        if (p > 0) {
+            if (pr->memspace == DUQ_HOST) {
+                std::memcpy(rlo.data(), pr->rlo, p * sizeof(double));
+                std::memcpy(rhi.data(), pr->rhi, p * sizeof(double));
+            } else if (hipMemcpyAsync(rlo.data(), pr->rlo, p * sizeof(double), hipMemcpyDeviceToHost, h->stream) !=
+                           hipSuccess ||
+                       hipMemcpyAsync(rhi.data(), pr->rhi, p * sizeof(double), hipMemcpyDeviceToHost, h->stream) !=
+                           hipSuccess ||
+                       hipStreamSynchronize(h->stream) != hipSuccess) {
+                duq_destroy(h);
+                return fail(DUQ_EINVAL, "rlo/rhi are not readable device pointers");
+            }
+        }
+        bool all_eq = p > 0;
+        for (int i = 0; i < p; ++i) {
+            const double lo = rlo[i], hi = rhi[i];
+            if (std::isnan(lo) || std::isnan(hi) || lo > hi || lo == INFINITY || hi == -INFINITY ||
+                (lo == hi && std::isinf(lo))) {
+                duq_destroy(h);
+                return fail(DUQ_EINVAL, "row bounds need rlo <= rhi, rlo < +inf, rhi > -inf (row " +
+                                            std::to_string(i) + ")");
+            }
+            all_eq = all_eq && lo == hi;
+        }
+        h->rows = true;
+        h->eqform = all_eq && opts->rho > 0.0;
+    }
+
     if (pr->memspace == DUQ_HOST) {
         bool ok = finite_all(pr->q, n) && (p == 0 || finite_all(pr->g, p));
         ok = ok && (dtype == DUQ_F64 ? finite_all_t((const double*)pr->Q, nn) : finite_all_t((const float*)pr->Q, nn));
@@ -335,6 +380,8 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
         c.take<double>(std::max(p, 1));
         c.take<double>(n);
         c.take<double>(n);
+        c.take<double>(std::max(p, 1));
+        c.take<double>(std::max(p, 1));
         if (hipMalloc(&h->owned_data, c.off) != hipSuccess) {
             duq_destroy(h);
             return fail(DUQ_ENOMEM, "device allocation of problem data");
@@ -347,6 +394,12 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
         h->dg = c.take<double>(std::max(p, 1));
         h->dlb = c.take<double>(n);
         h->dub = c.take<double>(n);
+        double* rl = c.take<double>(std::max(p, 1));
+        double* rh = c.take<double>(std::max(p, 1));
+        if (h->rows) {
+            h->drlo = rl;
+            h->drhi = rh;
+        }
         hipError_t e = hipSuccess;
         e = e ? e : hipMemcpy(h->dQ, pr->Q, nn * esize(dtype), hipMemcpyHostToDevice);
         if (p > 0) e = e ? e : hipMemcpy(h->dG, pr->G, pn * esize(dtype), hipMemcpyHostToDevice);
@@ -354,6 +407,10 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
         if (p > 0) e = e ? e : hipMemcpy(h->dg, pr->g, p * sizeof(double), hipMemcpyHostToDevice);
         e = e ? e : hipMemcpy(h->dlb, lb.data(), n * sizeof(double), hipMemcpyHostToDevice);
         e = e ? e : hipMemcpy(h->dub, ub.data(), n * sizeof(double), hipMemcpyHostToDevice);
+        if (h->rows && p > 0) {
+            e = e ? e : hipMemcpy(h->drlo, rlo.data(), p * sizeof(double), hipMemcpyHostToDevice);
+            e = e ? e : hipMemcpy(h->drhi, rhi.data(), p * sizeof(double), hipMemcpyHostToDevice);
+        }
         if (e != hipSuccess) {
             duq_destroy(h);
             return fail(DUQ_EDEVICE, std::string("copy of problem data: ") + hipGetErrorString(e));
@@ -365,6 +422,10 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
         h->dg = const_cast<double*>(pr->g);
         h->dlb = const_cast<double*>(pr->lb);
         h->dub = const_cast<double*>(pr->ub);
+        if (h->rows) {
+            h->drlo = const_cast<double*>(pr->rlo);
+            h->drhi = const_cast<double*>(pr->rhi);
+        }
         // borrowed data: count non-finite entries on the device
         unsigned* cnt = nullptr;
         if (hipMalloc(&cnt, sizeof(unsigned)) != hipSuccess) {
@@ -413,7 +474,8 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
     if (h->cfg.cooperative) {
         for (int acc = 0; acc <= (dtype == DUQ_F32 ? 1 : 0); ++acc) {
             int bpc = 0;
-            if (dfom_occupancy(dtype, acc, n, h->cfg.nthreads, h->cfg.shmem, &bpc) != hipSuccess || bpc < 1) {
+            if (dfom_occupancy(dtype, acc, n, h->cfg.nthreads, h->cfg.shmem, &bpc, h->rows) != hipSuccess ||
+                bpc < 1) {
                 duq_destroy(h);
                 return fail(DUQ_EDEVICE, "cooperative launch does not fit one block per CU");
             }
@@ -444,11 +506,26 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
         return fail(DUQ_EDEVICE, "event creation");
     }
 
+    // equality form: every row an equality and rho > 0, the inner Hessian
+    // Q + rho G^T G is constant (Sec. 5.1) and formed once here
+    if (h->eqform) {
+        if (hipMalloc(&h->dH, nn * esize(dtype)) != hipSuccess) {
+            duq_destroy(h);
+            return fail(DUQ_ENOMEM, "device allocation of Q + rho G^T G");
+        }
+        hipError_t e = launch_form_hessian(dtype, n, p, h->dQ, h->dG, opts->rho, h->dH, h->stream);
+        if (e != hipSuccess) {
+            duq_destroy(h);
+            return fail(DUQ_EDEVICE, std::string("forming Q + rho G^T G: ") + hipGetErrorString(e));
+        }
+    }
+
     // constants (a1): caller-supplied or estimated
     h->lam_min = opts->lam_min;
     h->lam_max = opts->lam_max;
     h->G2 = p > 0 ? opts->G_norm2 : 0.0;
-    if (h->lam_min <= 0.0 || h->lam_max <= 0.0 || (p > 0 && h->G2 <= 0.0)) {
+    h->sigma = opts->sigma_in > 0.0 ? opts->sigma_in : 0.0;
+    if (h->lam_min <= 0.0 || h->lam_max <= 0.0 || (p > 0 && h->G2 <= 0.0) || (h->eqform && h->sigma <= 0.0)) {
         rc = estimate_constants(h, di);
         if (rc) {
             duq_destroy(h);
@@ -456,7 +533,7 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
         }
     }
     DevParams dp;
-    rc = derive_params(p, h->lam_min, h->lam_max, h->G2, h->D_U, *opts, &dp);
+    rc = derive_params(p, h->lam_min, h->lam_max, h->G2, h->D_U, *opts, &dp, h->sigma);
     if (rc) {
         duq_destroy(h);
         return rc;
@@ -504,12 +581,14 @@ int estimate_constants(duq_handle* h, const DeviceInfo& di) {
         (void)hipFree(buf);
         return fail(DUQ_EINVAL, "problem too large for the Lanczos estimate; pass the constants");
     }
-    GenericProblem gp{n, p, h->dQ, h->dG, h->dq, h->dg, h->dlb, h->dub};
-    double outQ[4] = {0, 0, 0, 0}, outG[4] = {0, 0, 0, 0};
+    GenericProblem gp{n, p, h->dQ, h->dG, h->dq, h->dg, h->dlb, h->dub, h->drlo, h->drhi};
+    double outQ[4] = {0, 0, 0, 0}, outG[4] = {0, 0, 0, 0}, outH[4] = {0, 0, 0, 0};
     unsigned flag = 0;
-    auto run = [&](int use_gtg, double* out) -> int {
+    auto run = [&](int use_gtg, double* out, const void* Qop) -> int {
+        GenericProblem g2 = gp;
+        g2.Q = Qop;
         hipError_t e = hipMemsetAsync(buf, 0, c0.off, h->stream);
-        e = e ? e : launch_lanczos(h->dtype, cfg, gp, L, k, use_gtg);
+        e = e ? e : launch_lanczos(h->dtype, cfg, g2, L, k, use_gtg);
         e = e ? e : hipMemcpyAsync(out, L.out, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
         e = e ? e : hipMemcpyAsync(&flag, L.bar + kBarErr, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream);
         e = e ? e : hipStreamSynchronize(h->stream);
@@ -518,14 +597,16 @@ int estimate_constants(duq_handle* h, const DeviceInfo& di) {
         return DUQ_OK;
     };
     int rc = DUQ_OK;
-    if (h->lam_min <= 0.0 || h->lam_max <= 0.0) rc = run(0, outQ);
-    if (!rc && h->p > 0 && h->G2 <= 0.0) rc = run(1, outG);
+    if (h->lam_min <= 0.0 || h->lam_max <= 0.0) rc = run(0, outQ, h->dQ);
+    if (!rc && h->p > 0 && h->G2 <= 0.0) rc = run(1, outG, h->dQ);
+    if (!rc && h->eqform && h->sigma <= 0.0) rc = run(0, outH, h->dH);   // lambda_min(Q + rho G^T G)
     (void)hipFree(buf);
     if (rc) return rc;
     const double sf = h->opts.safety;
     if (h->lam_min <= 0.0) h->lam_min = outQ[0] / sf;
     if (h->lam_max <= 0.0) h->lam_max = outQ[1] * sf;
     if (h->p > 0 && h->G2 <= 0.0) h->G2 = outG[1] * sf;
+    if (h->eqform && h->sigma <= 0.0) h->sigma = outH[0] / sf;
     if (!(h->lam_max > 0.0)) return fail(DUQ_EINVAL, "Q appears to be zero");
     return DUQ_OK;
 }
@@ -554,6 +635,7 @@ extern "C" int duq_solve(duq_handle* h, const double* x0, const double* lam0, do
             if (!std::isfinite(x0[i])) return fail(DUQ_EINVAL, "non-finite x0");
         HIP_TRY(hipMemcpyAsync(h->xstage, x0, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
     }
+    if (lam0 && p > 0 && h->rows) return fail(DUQ_EINVAL, "lam0 is not available with row bounds");
     if (lam0 && p > 0) {
         for (int i = 0; i < p; ++i)
             if (!std::isfinite(lam0[i])) return fail(DUQ_EINVAL, "non-finite lam0");
@@ -583,7 +665,8 @@ extern "C" int duq_solve(duq_handle* h, const double* x0, const double* lam0, do
     par.L = h->L_in;
     par.sigma = h->sigma;
     par.beta_in = h->beta_in;
-    GenericProblem gp{n, p, h->dQ, h->dG, h->dq, h->dg, h->dlb, h->dub};
+    par.eqform = h->eqform ? 1 : 0;
+    GenericProblem gp{n, p, h->eqform ? h->dH : h->dQ, h->dG, h->dq, h->dg, h->dlb, h->dub, h->drlo, h->drhi};
     DevState st;
     unsigned bar_err = 0;
     int k_phase1 = 0;
@@ -617,7 +700,8 @@ extern "C" int duq_solve(duq_handle* h, const double* x0, const double* lam0, do
     HIP_TRY(hipMemcpyAsync(&bar_err, h->W.bar + kBarErr, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
     if (x_out) HIP_TRY(hipMemcpyAsync(x_out, h->W.xout, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     if (lam_out && p > 0)
-        HIP_TRY(hipMemcpyAsync(lam_out, h->W.lamp, p * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(lam_out, h->rows ? h->W.nu : h->W.lamp, p * sizeof(double), hipMemcpyDeviceToHost,
+                               h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
@@ -728,9 +812,97 @@ void handle_info(duq_handle* h, double* lam_min, double* lam_max, double* g2, in
 extern "C" int duq_get_trace(duq_handle* h, double* out, int32_t max_records, int32_t* n_records) {
     if (!h || !out || max_records < 0) return fail(DUQ_EINVAL, "bad trace arguments");
     const int rec = std::min(std::min(h->last_records, h->trace_cap), (int)max_records);
-    const size_t per = (size_t)(kTraceScalars + 2 * h->p + h->n);
+    const size_t per = (size_t)(kTraceScalars + (h->rows ? 4 : 2) * h->p + h->n);
     if (rec > 0)
         HIP_TRY(hipMemcpy(out, h->W.trace, rec * per * sizeof(double), hipMemcpyDeviceToHost));
     if (n_records) *n_records = rec;
     return DUQ_OK;
+}
+
+// ---- parameter planning (Sec. 3.1 eq. choose_ein, Sec. 5) -----------------
+
+extern "C" int duq_plan_params(int32_t method, double eps, double Ld, double Rd, double L_in, double sigma_in,
+                               double D_U, duq_plan* out) {
+    if (!out) return fail(DUQ_EINVAL, "null plan");
+    if (method != DUQ_DGM && method != DUQ_DFGM) return fail(DUQ_EINVAL, "bad method");
+    if (!(eps > 0.0) || !(Ld > 0.0) || !(Rd > 0.0) || !std::isfinite(eps) || !std::isfinite(Ld) ||
+        !std::isfinite(Rd))
+        return fail(DUQ_EINVAL, "eps, L_d and R_d must be finite and > 0");
+    std::memset(out, 0, sizeof(*out));
+    const double a = 8.0 * Ld * Rd * Rd / eps;
+    double kout;
+    if (method == DUQ_DGM) {
+        out->eps_in = eps / 4.0;
+        kout = std::ceil(a);
+    } else {
+        out->eps_in = eps * std::sqrt(eps) / (8.0 * Rd * std::sqrt(2.0 * Ld));
+        kout = std::ceil(std::sqrt(a));
+    }
+    out->k_out = (int64_t)std::min(std::max(kout, 1.0), 9.0e18);
+    out->rho_star = 8.0 * Rd * Rd / eps;
+    if (L_in > 0.0 && D_U > 0.0) {
+        double kin;
+        if (sigma_in > 0.0) {
+            const double arg = L_in * D_U * D_U / out->eps_in;
+            kin = arg > 1.0 ? std::ceil(std::sqrt(L_in / sigma_in) * std::log(arg)) + 1.0 : 1.0;
+        } else {
+            kin = std::ceil(std::sqrt(2.0 * L_in * D_U * D_U / out->eps_in));
+        }
+        out->k_in = (int64_t)std::min(std::max(kin, 1.0), 9.0e18);
+        out->k_total = out->k_in * out->k_out;
+    }
+    return DUQ_OK;
+}
+
+extern "C" int duq_solve_planned(duq_handle* h, double eps, double R0, int32_t max_rounds, double* x_out,
+                                 double* lam_out, duq_result* res, double* R_out, int32_t* rounds_out) {
+    if (!h || !x_out || (h->p > 0 && !lam_out)) return fail(DUQ_EINVAL, "null handle or output");
+    if (!(eps > 0.0) || !(R0 > 0.0) || max_rounds < 1) return fail(DUQ_EINVAL, "eps, R0 > 0 and max_rounds >= 1");
+    if (!(h->Ld > 0.0)) return fail(DUQ_EINVAL, "planning needs constraint rows (L_d > 0)");
+    const duq_options saved = h->opts;
+    const int saved_kin = h->k_in;
+    double R = R0;
+    int rounds = 0, code = DUQ_EMAXITER;
+    long long outer = 0, inner = 0, gt_rows = 0;
+    double ms = 0.0;
+    duq_result r{};
+    for (int rnd = 0; rnd < max_rounds; ++rnd) {
+        duq_plan pl;
+        int rc = duq_plan_params(saved.method, eps, h->Ld, R, 0.0, 0.0, 0.0, &pl);
+        if (rc) break;
+        h->opts.eps_out = eps;
+        h->opts.eps_in = pl.eps_in;
+        h->opts.max_outer = (int32_t)std::min<int64_t>(pl.k_out, INT32_MAX);
+        DevParams dp;
+        rc = derive_params(h->p, h->lam_min, h->lam_max, h->G2, h->D_U, h->opts, &dp, h->sigma);
+        if (rc) {
+            code = rc;
+            break;
+        }
+        h->k_in = dp.k_in_max;
+        const bool warm = rnd > 0;
+        code = duq_solve(h, warm ? x_out : nullptr, (warm && !h->rows) ? lam_out : nullptr, x_out, lam_out, &r);
+        ++rounds;
+        if (code != DUQ_OK && code != DUQ_EMAXITER) break;
+        outer += r.outer_iters;
+        inner += r.inner_iters;
+        gt_rows += r.gt_rows;
+        ms += r.time_ms;
+        if (code == DUQ_OK) break;
+        R *= 2.0;
+    }
+    h->opts = saved;
+    h->k_in = saved_kin;
+    if (res) {
+        *res = r;
+        res->outer_iters = (int32_t)std::min<long long>(outer, INT32_MAX);
+        res->inner_iters = inner;
+        res->gt_rows = gt_rows;
+        res->time_ms = ms;
+        res->f64_outer_iters = res->outer_iters;
+        res->status = code;
+    }
+    if (R_out) *R_out = R;
+    if (rounds_out) *rounds_out = rounds;
+    return code;
 }

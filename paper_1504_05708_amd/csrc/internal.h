@@ -33,6 +33,10 @@ struct DevProblem {
     const double* g;
     const double* lb;
     const double* ub;
+    // Row bounds of the user form rlo <= G u + g <= rhi (Sec. 2), or null for
+    // G u + g <= 0.  rlo = rhi: an equality; +-inf: an absent side.
+    const double* rlo = nullptr;
+    const double* rhi = nullptr;
 };
 
 // Per-solve parameters derived on the host from the options and constants.
@@ -52,7 +56,8 @@ struct DevParams {
                        // switch), 2 keeping the stored ones (time slicing)
     int phase1;        // first precision phase: no last-iterate solve, stall exit
     int stall_iters;   // phase 1 ends after this many iterations without progress
-    int pad2;
+    int eqform;        // every row an equality and rho > 0: Q holds Q + rho G^T G
+                       // (Sec. 5.1), the inner loop is the rho = 0 one
     double eps_out;    // outer tolerance used by this launch
     double eps_in;
     double rho;
@@ -97,6 +102,9 @@ struct DevWork {
     double* rs;        // sum_j theta_j (G ubar^j + g)
     double* lamp;      // lambda^{k} (after the step) = lambda^{k-1} before it
     double* mu;        // mu^k
+    double* lamm;      // row bounds: multipliers of the lower sides (lambda-)
+    double* mum;       //   and their extrapolation (mu-)
+    double* nu;        // row bounds: returned multiplier per row, lambda+ - lambda-
     double* wv;        // rho > 0: [mu + rho (G y + g)]_+
     double* gsave;     // rho > 0: G ubar^k kept across the extra DFGM-last solve
     double* gx[3];     // rho > 0: G x for the rotating iterates

@@ -20,10 +20,10 @@ static size_t lanczos_lds_doubles(int n, int p, int nblocks, int k) {
     return (size_t)n + (size_t)pmax + (size_t)(k + 2) + (size_t)kMaxWaves * 2 + 2 + kTlDoubles;
 }
 
-template <typename T, typename Acc, bool SHORT>
+template <typename T, typename Acc, bool SHORT, bool ROWS>
 __global__ void __launch_bounds__(512) dfom_kernel(DevProblem<T> P, DevParams par, DevWork W) {
     extern __shared__ __align__(16) double lds[];
-    Dfom<T, Acc, SHORT> s;
+    Dfom<T, Acc, SHORT, ROWS> s;
     s.P = P;
     s.par = par;
     s.W = W;
@@ -75,27 +75,97 @@ __global__ void count_nonfinite_kernel(const T* a, long len, unsigned* out) {
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
 }
 
+// H = Q + rho G^T G, 64 x 64 output tiles per workgroup of 256 threads (4 x 4
+// outputs per thread), G staged in LDS 16 rows at a time; each entry sums
+// over the rows of G in ascending order in FP64, so the result does not depend
+// on the launch.
+template <typename T>
+__global__ void __launch_bounds__(256) form_hessian_kernel(int n, int p, const T* __restrict__ Q,
+                                                           const T* __restrict__ G, double rho, T* __restrict__ H) {
+    constexpr int TB = 64, KB = 16;
+    __shared__ double gi[KB][TB + 1];
+    __shared__ double gj[KB][TB + 1];
+    const int i0 = blockIdx.y * TB, j0 = blockIdx.x * TB;
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int k0 = 0; k0 < p; k0 += KB) {
+        for (int e = threadIdx.x; e < KB * TB; e += blockDim.x) {
+            const int kr = e / TB, c = e % TB;
+            const int k = k0 + kr;
+            gi[kr][c] = (k < p && i0 + c < n) ? (double)G[(long)k * n + i0 + c] : 0.0;
+            gj[kr][c] = (k < p && j0 + c < n) ? (double)G[(long)k * n + j0 + c] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kr = 0; kr < KB; ++kr) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = gi[kr][ty * 4 + u];
+                b[u] = gj[kr][tx * 4 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = i0 + ty * 4 + u;
+        if (i >= n) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int j = j0 + tx * 4 + v;
+            if (j < n) H[(long)i * n + j] = (T)((double)Q[(long)i * n + j] + rho * acc[u][v]);
+        }
+    }
+}
+
+hipError_t launch_form_hessian(int dtype, int n, int p, const void* Q, const void* G, double rho, void* H,
+                               hipStream_t s) {
+    const dim3 grid((n + 63) / 64, (n + 63) / 64);
+    if (dtype == 0)
+        hipLaunchKernelGGL(form_hessian_kernel<double>, grid, dim3(256), 0, s, n, p, (const double*)Q,
+                           (const double*)G, rho, (double*)H);
+    else
+        hipLaunchKernelGGL(form_hessian_kernel<float>, grid, dim3(256), 0, s, n, p, (const float*)Q,
+                           (const float*)G, rho, (float*)H);
+    return hipGetLastError();
+}
+
 size_t dfom_lds_bytes(int n, int p, int nblocks) { return solver_lds_doubles(n, p, nblocks) * sizeof(double); }
 size_t lanczos_lds_bytes(int n, int p, int nblocks, int k) {
     return lanczos_lds_doubles(n, p, nblocks, k) * sizeof(double);
 }
 
 template <bool SHORT>
-static const void* dfom_fn_t(int dtype, int acc) {
-    if (dtype == 0) return reinterpret_cast<const void*>(&dfom_kernel<double, double, SHORT>);
-    if (acc == 0) return reinterpret_cast<const void*>(&dfom_kernel<float, double, SHORT>);
-    return reinterpret_cast<const void*>(&dfom_kernel<float, float, SHORT>);
+static const void* dfom_fn_t(int dtype, int acc, bool rows = false) {
+    // row bounds: FP64 accumulation only (the precision switch is not offered)
+    if (rows)
+        return dtype == 0 ? reinterpret_cast<const void*>(&dfom_kernel<double, double, SHORT, true>)
+                          : reinterpret_cast<const void*>(&dfom_kernel<float, double, SHORT, true>);
+    if (dtype == 0) return reinterpret_cast<const void*>(&dfom_kernel<double, double, SHORT, false>);
+    if (acc == 0) return reinterpret_cast<const void*>(&dfom_kernel<float, double, SHORT, false>);
+    return reinterpret_cast<const void*>(&dfom_kernel<float, float, SHORT, false>);
 }
 
-static const void* dfom_fn(int dtype, int acc, int n) {
+static const void* dfom_fn(int dtype, int acc, int n, bool rows = false) {
     const bool sh = dtype == 0 ? short_rows<double>(n) : short_rows<float>(n);
-    return sh ? dfom_fn_t<true>(dtype, acc) : dfom_fn_t<false>(dtype, acc);
+    return sh ? dfom_fn_t<true>(dtype, acc, rows) : dfom_fn_t<false>(dtype, acc, rows);
 }
 
 size_t dfom_static_lds_bytes() {
     static size_t bytes = [] {
         const void* fns[] = {dfom_fn_t<true>(0, 0), dfom_fn_t<true>(1, 0), dfom_fn_t<true>(1, 1),
                              dfom_fn_t<false>(0, 0), dfom_fn_t<false>(1, 0), dfom_fn_t<false>(1, 1),
+                             dfom_fn_t<true>(0, 0, true), dfom_fn_t<true>(1, 0, true),
+                             dfom_fn_t<false>(0, 0, true), dfom_fn_t<false>(1, 0, true),
                              reinterpret_cast<const void*>(&lanczos_kernel<double, true>),
                              reinterpret_cast<const void*>(&lanczos_kernel<double, false>),
                              reinterpret_cast<const void*>(&lanczos_kernel<float, true>),
@@ -111,8 +181,8 @@ size_t dfom_static_lds_bytes() {
     return bytes;
 }
 
-hipError_t dfom_occupancy(int dtype, int acc, int n, int nthreads, size_t shmem, int* blocks_per_cu) {
-    const void* f = dfom_fn(dtype, acc, n);
+hipError_t dfom_occupancy(int dtype, int acc, int n, int nthreads, size_t shmem, int* blocks_per_cu, bool rows) {
+    const void* f = dfom_fn(dtype, acc, n, rows);
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, nthreads, shmem);
@@ -122,13 +192,16 @@ hipError_t launch_dfom(int dtype, int acc, const LaunchCfg& cfg, const GenericPr
                        const DevParams& par, const DevWork& W) {
     DevParams pr = par;
     DevWork w = W;
-    const void* f = dfom_fn(dtype, acc, gp.n);
+    const bool rows = gp.rlo != nullptr;
+    const void* f = dfom_fn(dtype, acc, gp.n, rows);
     if (dtype == 0) {
-        DevProblem<double> P{gp.n, gp.p, (const double*)gp.Q, (const double*)gp.G, gp.q, gp.g, gp.lb, gp.ub};
+        DevProblem<double> P{gp.n, gp.p, (const double*)gp.Q, (const double*)gp.G, gp.q, gp.g, gp.lb, gp.ub,
+                             gp.rlo, gp.rhi};
         void* args[] = {&P, &pr, &w};
         return launch_fn(f, cfg, args);
     }
-    DevProblem<float> P{gp.n, gp.p, (const float*)gp.Q, (const float*)gp.G, gp.q, gp.g, gp.lb, gp.ub};
+    DevProblem<float> P{gp.n, gp.p, (const float*)gp.Q, (const float*)gp.G, gp.q, gp.g, gp.lb, gp.ub,
+                        gp.rlo, gp.rhi};
     void* args[] = {&P, &pr, &w};
     return launch_fn(f, cfg, args);
 }
@@ -138,13 +211,15 @@ hipError_t launch_lanczos(int dtype, const LaunchCfg& cfg, const GenericProblem&
     LanczosWork l = L;
     int kk = k, ug = use_gtg;
     if (dtype == 0) {
-        DevProblem<double> P{gp.n, gp.p, (const double*)gp.Q, (const double*)gp.G, gp.q, gp.g, gp.lb, gp.ub};
+        DevProblem<double> P{gp.n, gp.p, (const double*)gp.Q, (const double*)gp.G, gp.q, gp.g, gp.lb, gp.ub,
+                             gp.rlo, gp.rhi};
         void* args[] = {&P, &l, &kk, &ug};
         const void* f = short_rows<double>(gp.n) ? reinterpret_cast<const void*>(&lanczos_kernel<double, true>)
                                                  : reinterpret_cast<const void*>(&lanczos_kernel<double, false>);
         return launch_fn(f, cfg, args);
     }
-    DevProblem<float> P{gp.n, gp.p, (const float*)gp.Q, (const float*)gp.G, gp.q, gp.g, gp.lb, gp.ub};
+    DevProblem<float> P{gp.n, gp.p, (const float*)gp.Q, (const float*)gp.G, gp.q, gp.g, gp.lb, gp.ub,
+                        gp.rlo, gp.rhi};
     void* args[] = {&P, &l, &kk, &ug};
     const void* f = short_rows<float>(gp.n) ? reinterpret_cast<const void*>(&lanczos_kernel<float, true>)
                                             : reinterpret_cast<const void*>(&lanczos_kernel<float, false>);

@@ -139,7 +139,16 @@ struct Lanczos {
         if (tm.size > 1) gemv_rows<T, double, 8, true, SHORT>(P.G, n, plo, phi, n, xl, L.r, nullptr);
         else gemv_rows<T, double, 8, false, SHORT>(P.G, n, plo, phi, n, xl, L.r, nullptr);
         __syncthreads();
-        for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) vl[i - plo] = L.r[i];
+        // G^T W G with W_ii = the number of sides of row i in cone form (row
+        // bounds: an equality or one-sided row counts once, a two-sided row twice)
+        for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) {
+            double r = L.r[i];
+            if (P.rlo) {
+                const RowSides sd = row_sides(P.rlo, P.rhi, i);
+                r *= (sd.up ? 1.0 : 0.0) + (sd.dn ? 1.0 : 0.0);
+            }
+            vl[i - plo] = r;
+        }
         __syncthreads();
         if (tm.size == 1) {
             gemvT_rows<T, double, false>(P.G, n, plo, phi, n, vl, w, nullptr, false, tl);

@@ -26,6 +26,8 @@ struct GenericProblem {
     const double* g;
     const double* lb;
     const double* ub;
+    const double* rlo = nullptr;   // row bounds (both or neither)
+    const double* rhi = nullptr;
 };
 
 struct LanczosWork;
@@ -117,11 +119,16 @@ size_t dfom_lds_bytes(int n, int p, int nblocks);
 // dynamic LDS of a launch may use what is left of the workgroup's LDS.
 size_t dfom_static_lds_bytes();
 size_t lanczos_lds_bytes(int n, int p, int nblocks, int k);
-hipError_t dfom_occupancy(int dtype, int acc, int n, int nthreads, size_t shmem, int* blocks_per_cu);
+hipError_t dfom_occupancy(int dtype, int acc, int n, int nthreads, size_t shmem, int* blocks_per_cu,
+                          bool rows = false);
 hipError_t launch_dfom(int dtype, int acc, const LaunchCfg& cfg, const GenericProblem& gp,
                        const DevParams& par, const DevWork& W);
 hipError_t launch_lanczos(int dtype, const LaunchCfg& cfg, const GenericProblem& gp, const LanczosWork& L,
                           int k, int use_gtg);
 hipError_t launch_count_nonfinite(int dtype, const void* a, long len, unsigned* out, hipStream_t s);
+// H = Q + rho G^T G (n x n, dtype of Q and G, FP64 accumulation): the constant
+// inner Hessian of a problem whose rows are all equalities (Sec. 5.1).
+hipError_t launch_form_hessian(int dtype, int n, int p, const void* Q, const void* G, double rho, void* H,
+                               hipStream_t s);
 
 }  // namespace duq

@@ -616,6 +616,7 @@ int duq_server_create(size_t hbm_budget_bytes, const duq_options* opts, duq_serv
 
 int duq_register_shared(duq_server* s, const duq_problem* pr, int32_t* id) {
     if (!s || !pr || !id) return set_error(DUQ_EINVAL, "null argument");
+    if (pr->rlo || pr->rhi) return set_error(DUQ_EINVAL, "row bounds are available on duq_setup / duq_solve only");
     const int n = pr->n, p = pr->p;
     if (n < 1 || n > DUQ_SERVE_BATCH_NMAX || p < 0)
         return set_error(DUQ_EINVAL, "shared systems need 1 <= n <= DUQ_SERVE_BATCH_NMAX and p >= 0");
@@ -677,6 +678,7 @@ int duq_register_shared(duq_server* s, const duq_problem* pr, int32_t* id) {
 int duq_submit(duq_server* s, const duq_request* rq, uint64_t* ticket) {
     if (!s || !rq || !ticket) return set_error(DUQ_EINVAL, "null argument");
     const duq_problem& pr = rq->prob;
+    if (pr.rlo || pr.rhi) return set_error(DUQ_EINVAL, "row bounds are available on duq_setup / duq_solve only");
     std::unique_ptr<Req> r(new (std::nothrow) Req());
     if (!r) return set_error(DUQ_ENOMEM, "host allocation");
     r->shared_id = rq->shared_id;

@@ -44,9 +44,13 @@ inline void carve_solver(Carve& c, int n, int p, int nb, int trace, DevWork* W, 
     W->wv = c.take<double>(pp);
     W->gsave = c.take<double>(pp);
     for (int i = 0; i < 3; ++i) W->gx[i] = c.take<double>(pp);
+    W->lamm = c.take<double>(pp);
+    W->mum = c.take<double>(pp);
+    W->nu = c.take<double>(pp);
     W->part = c.take<double>((size_t)2 * nb * kNP);
     W->gtp = c.take<double>(nb > 1 ? (size_t)nb * n : 1);
-    W->trace = c.take<double>(trace > 0 ? (size_t)trace * (kTraceScalars + 2 * p + n) : 1);
+    // a record holds lambda+, mu+, ubar and, with row bounds, lambda-, mu-
+    W->trace = c.take<double>(trace > 0 ? (size_t)trace * (kTraceScalars + 4 * p + n) : 1);
     W->st = c.take<DevState>(1);
     W->bar = c.take<unsigned>(bar_words(nb));
     *xstage = c.take<double>(n);

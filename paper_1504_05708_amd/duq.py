@@ -38,13 +38,14 @@ SERVE_BATCH_NMAX = 1536
 
 EXPORTS = ["duq_default_options", "duq_setup", "duq_max_n", "duq_solve", "duq_get_trace", "duq_get_constants",
            "duq_destroy", "duq_last_error", "duq_strerror", "duq_solve_batch", "duq_server_create",
-           "duq_register_shared", "duq_submit", "duq_poll", "duq_server_destroy"]
+           "duq_register_shared", "duq_submit", "duq_poll", "duq_server_destroy", "duq_plan_params",
+           "duq_solve_planned"]
 
 
 class DuqProblem(Structure):
     _fields_ = [("n", c_int32), ("p", c_int32), ("dtype", c_int32), ("memspace", c_int32),
                 ("Q", c_void_p), ("G", c_void_p), ("q", c_void_p), ("g", c_void_p),
-                ("lb", c_void_p), ("ub", c_void_p)]
+                ("lb", c_void_p), ("ub", c_void_p), ("rlo", c_void_p), ("rhi", c_void_p)]
 
 
 class DuqOptions(Structure):
@@ -55,7 +56,7 @@ class DuqOptions(Structure):
                 ("rho", c_double), ("lam_min", c_double), ("lam_max", c_double),
                 ("G_norm2", c_double), ("safety", c_double), ("switch_factor", c_double),
                 ("switch_stall", c_int32), ("serve_slice", c_int32), ("out_memspace", c_int32),
-                ("reserved", c_int32 * 5)]
+                ("reserved0", c_int32), ("sigma_in", c_double), ("reserved", c_int32 * 2)]
 
 
 class DuqResult(Structure):
@@ -92,6 +93,11 @@ class DuqBatch(Structure):
                 ("voff", c_void_p), ("coff", c_void_p), ("Q", c_void_p), ("G", c_void_p),
                 ("q", c_void_p), ("g", c_void_p), ("lb", c_void_p), ("ub", c_void_p),
                 ("lam_min", c_void_p), ("lam_max", c_void_p), ("G_norm2", c_void_p)]
+
+
+class DuqPlan(Structure):
+    _fields_ = [("eps_in", c_double), ("k_out", c_int64), ("rho_star", c_double), ("k_in", c_int64),
+                ("k_total", c_int64)]
 
 
 class DuqRequest(Structure):
@@ -146,6 +152,12 @@ def lib() -> ctypes.CDLL:
     L.duq_poll.restype = c_int32
     L.duq_server_destroy.argtypes = [c_void_p]
     L.duq_server_destroy.restype = None
+    L.duq_plan_params.argtypes = [c_int32, c_double, c_double, c_double, c_double, c_double, c_double,
+                                  POINTER(DuqPlan)]
+    L.duq_plan_params.restype = c_int32
+    L.duq_solve_planned.argtypes = [c_void_p, c_double, c_double, c_int32, c_void_p, c_void_p, POINTER(DuqResult),
+                                    POINTER(c_double), POINTER(c_int32)]
+    L.duq_solve_planned.restype = c_int32
     _lib = L
     return L
 
@@ -194,9 +206,10 @@ class Solver:
 
     Q, G: NumPy float64/float32 arrays (copied) or torch tensors on the GPU
     (borrowed: they must outlive the solver).  q, g, lb, ub: float64 of the
-    same kind."""
+    same kind.  rlo, rhi (optional, both or neither): row bounds
+    rlo <= G u + g <= rhi (equality where rlo = rhi, +-inf for no side)."""
 
-    def __init__(self, Q, q, G, g, lb, ub, **opts):
+    def __init__(self, Q, q, G, g, lb, ub, rlo=None, rhi=None, **opts):
         self._keep = []
         dev = hasattr(Q, "data_ptr")
         if dev:
@@ -211,11 +224,14 @@ class Solver:
             dt = {np.dtype(np.float64): F64, np.dtype(np.float32): F32}[Q.dtype]
             G = np.ascontiguousarray(G, dtype=Q.dtype)
             q, g, lb, ub = (np.ascontiguousarray(v, dtype=np.float64) for v in (q, g, lb, ub))
-        self._keep = [Q, G, q, g, lb, ub]
+            if rlo is not None:
+                rlo, rhi = (np.ascontiguousarray(v, dtype=np.float64) for v in (rlo, rhi))
+        self._keep = [Q, G, q, g, lb, ub, rlo, rhi]
         n, p = int(Q.shape[0]), int(G.shape[0])
         self.n, self.p = n, p
+        self.rows = rlo is not None
         prob = DuqProblem(n, p, dt, DEVICE if dev else HOST, _ptr(Q), _ptr(G) if p else None,
-                          _ptr(q), _ptr(g) if p else None, _ptr(lb), _ptr(ub))
+                          _ptr(q), _ptr(g) if p else None, _ptr(lb), _ptr(ub), _ptr(rlo), _ptr(rhi))
         self.opts = default_options(**opts)
         h = c_void_p()
         rc = lib().duq_setup(ctypes.byref(prob), ctypes.byref(self.opts), _stream_of(Q if dev else None),
@@ -239,7 +255,7 @@ class Solver:
         return x, lam, res.as_dict()
 
     def trace(self, max_records: int):
-        per = TRACE_SCALARS + 2 * self.p + self.n
+        per = TRACE_SCALARS + (4 if self.rows else 2) * self.p + self.n
         out = np.zeros((max_records, per))
         nrec = c_int32()
         rc = lib().duq_get_trace(self._h, _ptr(out), max_records, ctypes.byref(nrec))
@@ -248,8 +264,27 @@ class Solver:
         out = out[:nrec.value]
         p, n = self.p, self.n
         S = TRACE_SCALARS
-        return dict(scalars=out[:, :S], lam=out[:, S:S + p], mu=out[:, S + p:S + 2 * p],
-                    u=out[:, S + 2 * p:S + 2 * p + n])
+        tr = dict(scalars=out[:, :S], lam=out[:, S:S + p], mu=out[:, S + p:S + 2 * p],
+                  u=out[:, S + 2 * p:S + 2 * p + n])
+        if self.rows:   # lower sides of the row bounds
+            tr.update(lam_lo=out[:, S + 2 * p + n:S + 3 * p + n], mu_lo=out[:, S + 3 * p + n:S + 4 * p + n])
+        return tr
+
+    def solve_planned(self, eps: float, R0: float, max_rounds: int = 12, check=True):
+        """duq_solve_planned: eps_in and max_outer from eq. choose_ein for a
+        guess R of R_d, doubled per round until the test at eps passes.
+        Returns (x, lam, result dict with 'R' and 'rounds')."""
+        x = np.empty(self.n)
+        lam = np.empty(max(self.p, 1))
+        res = DuqResult()
+        R, rounds = c_double(), c_int32()
+        rc = lib().duq_solve_planned(self._h, eps, R0, max_rounds, _ptr(x), _ptr(lam), ctypes.byref(res),
+                                     ctypes.byref(R), ctypes.byref(rounds))
+        if check and rc not in SOLVE_OUTCOMES:
+            raise DuqError(rc, last_error())
+        d = res.as_dict()
+        d.update(R=R.value, rounds=rounds.value)
+        return x, lam[:self.p], d
 
     def constants(self) -> dict:
         vals = [c_double() for _ in range(6)]
@@ -274,6 +309,16 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def plan_params(method: int, eps: float, Ld: float, Rd: float, L_in: float = 0.0, sigma_in: float = 0.0,
+                D_U: float = 0.0) -> dict:
+    """duq_plan_params: eq. choose_ein (eps_in, k_out), rho* and k_in."""
+    out = DuqPlan()
+    rc = lib().duq_plan_params(method, eps, Ld, Rd, L_in, sigma_in, D_U, ctypes.byref(out))
+    if rc != DUQ_OK:
+        raise DuqError(rc, last_error())
+    return {k: getattr(out, k) for k, _ in out._fields_}
 
 
 def solve_batch_uneven(batch, constants=None, check=True, **opts):

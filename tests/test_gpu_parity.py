@@ -445,3 +445,25 @@ def test_mixed_precision_switch_accuracy(n, p, engine, key):
     # the returned point is feasible to the tolerance on the FP64 data as well
     feas64 = np.linalg.norm(np.maximum(qp32.G @ x + qp32.g, 0))
     assert feas64 / max(1.0, np.linalg.norm(qp.g)) <= 1e-4 * (1 + 1e-6)
+
+
+# ----------------------------------------------------------------------------
+# planned solve: eq. choose_ein with a doubling guess of R_d (Sec. 3.1, Sec. 5)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("method", [duq.DFGM, duq.DGM])
+def test_planned_solve_matches_oracle(method):
+    from oracle import plan as oplan
+    print(f"[case] planned solve m={method}", flush=True)
+    qp = gen.config0()
+    c = consts_of(qp)
+    eps = 1e-3 if method == duq.DFGM else 1e-2
+    ref = oplan.planned_solve(qp, method, eps, R0=0.05, max_rounds=16, consts=c)
+    assert ref.status == dfom.STATUS_OK
+    with gpu_solver(qp, c, method=method) as s:
+        x, lam, r = s.solve_planned(eps, 0.05, max_rounds=16)
+    assert r["status"] == duq.DUQ_OK and r["rounds"] == ref.rounds
+    assert r["R"] == pytest.approx(ref.R, rel=1e-15)
+    assert r["outer_iters"] == ref.outer_iters and r["inner_iters"] == ref.inner_iters
+    close(x, ref.x, rel=1e-7, what="x")
+    close(lam, ref.lam, rel=1e-7, what="lambda")
