@@ -57,10 +57,12 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="single workload: leave out the batched sub-results (MPC B=4096, uneven B=10000)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--workload", choices=["single", "uneven", "mpc", "serve"], default="single",
+    ap.add_argument("--workload", choices=["single", "uneven", "mpc", "serve", "studies"], default="single",
                     help="single large QP (default), uneven batch, or shared-Hessian MPC batch")
     ap.add_argument("--batch", type=int, default=None, help="instances of a batch workload")
     ap.add_argument("--plain-sample", type=int, default=48)
+    ap.add_argument("--batch-max-outer", type=int, default=20000,
+                    help="outer iteration cap per instance in the batched forms")
     ap.add_argument("--gen-workers", type=int, default=16,
                     help="processes generating uneven instances (1: in-process, e.g. under a profiler)")
     ap.add_argument("--batch-engine", choices=["auto", "block", "tile"], default="auto",
@@ -147,6 +149,9 @@ def main():
         return
     if a.workload == "serve":
         bench_serve(a)
+        return
+    if a.workload == "studies":
+        bench_studies(a)
         return
     if a.workload != "single":
         bench_batch(a)
@@ -352,8 +357,12 @@ def batch_result(a, workload, B, steps, warmup, precision, with_cpu, oracle_samp
     method = duq.DFGM if a.method == "dfgm" else duq.DGM
     output = duq.LAST if a.output == "last" else duq.AVG
     eps_in = a.eps_in if a.eps_in is not None else (1e-8 if method == duq.DFGM else 1e-6)
+    # max_outer: about 40 times the mean outer count of the uneven batch; the
+    # few DFGM instances that plateau above the test (inner accuracy too coarse
+    # for DFGM, Sec. 3.1) end there as failures instead of holding one
+    # workgroup for 200 000 iterations after every other instance is done
     opts = dict(method=method, output=output, eps_out=a.eps_out,
-                eps_in=eps_in, rho=a.rho, max_outer=200000,
+                eps_in=eps_in, rho=a.rho, max_outer=a.batch_max_outer,
                 engine={"auto": duq.ENGINE_AUTO, "block": duq.ENGINE_BLOCK, "tile": duq.ENGINE_TILE}[a.batch_engine])
     npdt = np.float32 if precision == "f32" else np.float64
     s_bytes = 4 if npdt == np.float32 else 8
@@ -533,7 +542,7 @@ def batch_result(a, workload, B, steps, warmup, precision, with_cpu, oracle_samp
             sub.append(abs(F - fstar) / max(1.0, abs(fstar)))
             feas_o.append(float(np.linalg.norm(np.maximum(qp.G @ x + qp.g, 0.0))) / max(1.0, np.linalg.norm(qp.g)))
             ref = dfom.dfom_solve(qp, dfom.Options(method=method, output=output, eps_out=a.eps_out, eps_in=eps_in,
-                                                   rho=a.rho, max_outer=200000, lam_min=res[i]["lam_min"],
+                                                   rho=a.rho, max_outer=a.batch_max_outer, lam_min=res[i]["lam_min"],
                                                    lam_max=res[i]["lam_max"], G_norm2=res[i]["G_norm2"]))
             dx.append(float(np.max(np.abs(x - ref.x))))
             fo_rel.append(abs(F - ref.F) / max(1.0, abs(ref.F)))
@@ -546,7 +555,7 @@ def batch_result(a, workload, B, steps, warmup, precision, with_cpu, oracle_samp
         for i, c in zip(idx, consts):
             qp = instance(int(i))
             dfom.dfom_solve(qp, dfom.Options(method=method, output=output, eps_out=a.eps_out, eps_in=eps_in,
-                                             rho=a.rho, max_outer=200000, lam_min=c["lam_min"],
+                                             rho=a.rho, max_outer=a.batch_max_outer, lam_min=c["lam_min"],
                                              lam_max=c["lam_max"], G_norm2=c["G_norm2"]))
             done += 1
             if time.perf_counter() - t > a.cpu_seconds:
@@ -723,5 +732,104 @@ def bench_serve(a):
     print(json.dumps(line), flush=True)
 
 
+# ----------------------------------------------------------------------------
+# The paper's studies, reproduced qualitatively on synthetic QPs (the paper's
+# own data and figures are not available): Sec. 3.1 / Fig. 1 (sensitivity to
+# the inner accuracy) and Sec. 6.3 / Fig. 5 (outer iterations against n, last
+# against averaged primal iterate).  Every solve runs on the GPU; the optimal
+# value used for suboptimality comes from a tight GPU solve of the same QP.
+# ----------------------------------------------------------------------------
+
+def study_inner_accuracy(seeds=range(501, 509), n=60, p=30, eps_ins=(1e-1, 1e-2, 1e-3, 1e-4, 1e-6),
+                         K=600, checkpoints=(50, 200, 600)):
+    """Fig. 1: primal suboptimality |F(ubar^k) - F*|/|F*| and feasibility
+    ||[G ubar^k + g]_+|| after k outer iterations of DGM and DFGM (last
+    iterate) for several eps_in, on strongly convex random dense QPs; mean over
+    the seeds."""
+    from paper_1504_05708_amd import duq, gen
+    qps = [gen.random_dense_qp(n, p, seed=s) for s in seeds]
+    fstar = []
+    for qp in qps:
+        with duq.Solver(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub, method=duq.DFGM, eps_out=1e-9, eps_in=1e-13,
+                        max_outer=200000, engine=duq.ENGINE_BLOCK) as s:
+            fstar.append(s.solve()[2]["f"])
+    table = []
+    for method, name in ((duq.DGM, "DGM"), (duq.DFGM, "DFGM")):
+        for ein in eps_ins:
+            sub = np.zeros(len(checkpoints))
+            feas = np.zeros(len(checkpoints))
+            inner = 0
+            for qp, fs in zip(qps, fstar):
+                with duq.Solver(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub, method=method, eps_out=1e-13, eps_in=ein,
+                                max_outer=K, trace_outer=K, engine=duq.ENGINE_BLOCK) as s:
+                    _, _, r = s.solve(check=False)
+                    S = s.trace(K)["scalars"]
+                inner += r["inner_iters"]
+                for j, k in enumerate(checkpoints):
+                    sub[j] += abs(S[k - 1, 7] - fs) / max(1.0, abs(fs)) / len(qps)
+                    feas[j] += S[k - 1, 8] / len(qps)
+            table.append({"method": name, "eps_in": ein,
+                          "subopt_rel": {str(k): float(v) for k, v in zip(checkpoints, sub)},
+                          "feas": {str(k): float(v) for k, v in zip(checkpoints, feas)},
+                          "inner_steps_per_qp": inner / len(qps)})
+    return {"study": "inner_accuracy (Sec. 3.1, Fig. 1)",
+            "workload": f"{len(qps)} random dense QPs n={n} p={p} (Q=A^T A/n+0.1I), seeds {min(seeds)}..{max(seeds)}; "
+                        f"last primal iterate after k outer iterations; F* from a tight GPU solve",
+            "rows": table}
+
+
+def study_outer_vs_n(ns=(10, 50, 100, 200, 300, 400, 500), per_n=25, eps=1e-2, eps_in=1e-6, seed0=700):
+    """Fig. 5: outer iterations to the outer test at eps, against n, for the
+    last and the averaged primal iterate (DGM and DFGM), 25 random QPs per n
+    solved as one batch on the GPU (p = n/2)."""
+    from paper_1504_05708_amd import duq, gen
+    rows = []
+    for n in ns:
+        qps = [gen.random_dense_qp(n, n // 2, seed=seed0 + 1000 * n + j) for j in range(per_n)]
+        ub = gen.pack_uneven(qps)
+        row = {"n": n}
+        for method, mname in ((duq.DGM, "DGM"), (duq.DFGM, "DFGM")):
+            for output, oname in ((duq.LAST, "LAST"), (duq.AVG, "AVG")):
+                _, _, res = duq.solve_batch_uneven(ub, method=method, output=output, eps_out=eps, eps_in=eps_in,
+                                                   max_outer=200000, check=False)
+                outer = [r["outer_iters"] for r in res if r["status"] == duq.DUQ_OK]
+                row[f"{mname}-{oname}"] = {"mean_outer": float(np.mean(outer)) if outer else None,
+                                           "median_outer": float(np.median(outer)) if outer else None,
+                                           "ok": len(outer)}
+        rows.append(row)
+    return {"study": "outer_vs_n (Sec. 6.3, Fig. 5)",
+            "workload": f"{per_n} random dense QPs per n (Q=A^T A/n+0.1I, p=n/2, inequality rows), eps_out={eps:g}, "
+                        f"eps_in={eps_in:g}; one uneven batch per n and method",
+            "rows": rows}
+
+
+def bench_studies(a):
+    import torch
+    from paper_1504_05708_amd import duq
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    duq.lib()
+    for fn in (study_inner_accuracy, study_outer_vs_n):
+        t = time.perf_counter()
+        out = fn()
+        out["seconds"] = round(time.perf_counter() - t, 1)
+        print(json.dumps(out), flush=True)
+
+
+def _release_device():
+    # Free everything the run holds on the device before the interpreter's
+    # own teardown, so that no library handle or cached block is released
+    # after the HIP runtime (or a profiler attached to it) has shut down.
+    import gc
+    gc.collect()
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+    except Exception:
+        pass
+
+
 if __name__ == "__main__":
     main()
+    _release_device()
