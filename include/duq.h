@@ -352,6 +352,31 @@ int duq_poll(duq_server *s, uint64_t ticket, double *x_out, double *lam_out, duq
  * requests not yet collected are dropped (NULL is allowed).                */
 void duq_server_destroy(duq_server *s);
 
+/* ---- allocation-free solve ---------------------------------------------- *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * duq_solve_static runs one solve of Algorithm DFOM (as duq_setup + duq_solve
+ * would, same kernels and engine choice) on a problem whose data are DEVICE
+ * pointers (prob->memspace = DUQ_DEVICE, borrowed for the call), with the
+ * spectral constants given in opts (lam_min > 0, or = 0 with rho > 0;
+ * lam_max > 0; G_norm2 > 0 when p > 0: no Lanczos estimate runs).  x_out (n)
+ * and lam_out (p) are DEVICE buffers.  x0 = projection of 0, lam0 = 0.
+ * The workspace lives in a static device array of DUQ_STATIC_SCRATCH_BYTES
+ * that each GPU the library runs on holds until the process ends; a problem
+ * whose workspace does not fit (about 8 (14 n + 12 p) bytes on one
+ * workgroup, plus 8 n bytes per workgroup of the grid engine) is DUQ_EINVAL.
+ * The call makes no hipMalloc, hipFree or other allocating call; it clears
+ * what must start at zero with a fill kernel, validates the data on the
+ * device and synchronises `stream` twice (validation result, final state).
+ * Every call on one GPU uses that GPU's one array: calls that overlap in time
+ * on the same GPU (other threads, other streams) race and must be
+ * serialised by the caller.  Not available: tracing (trace_outer must be 0),
+ * the precision switch (accumulate must be DUQ_ACC_F64), warm starts.
+ * res->time_ms is 0.  Returns as duq_solve.                                 */
+#define DUQ_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int duq_solve_static(const duq_problem *prob, const duq_options *opts, void *stream,
+                     double *x_out, double *lam_out, duq_result *res);
+
 /* Release every resource of the handle (NULL is allowed).                  */
 void duq_destroy(duq_handle *h);
 

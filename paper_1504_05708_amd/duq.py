@@ -38,8 +38,9 @@ SERVE_BATCH_NMAX = 1536
 
 EXPORTS = ["duq_default_options", "duq_setup", "duq_max_n", "duq_solve", "duq_get_trace", "duq_get_constants",
            "duq_destroy", "duq_last_error", "duq_strerror", "duq_solve_batch", "duq_server_create",
-           "duq_register_shared", "duq_submit", "duq_poll", "duq_server_destroy", "duq_plan_params",
-           "duq_solve_planned"]
+           "duq_register_shared", "duq_submit", "duq_poll", "duq_server_destroy", "duq_solve_static",
+           "duq_plan_params", "duq_solve_planned"]
+STATIC_SCRATCH_BYTES = 64 << 20
 
 
 class DuqProblem(Structure):
@@ -152,6 +153,9 @@ def lib() -> ctypes.CDLL:
     L.duq_poll.restype = c_int32
     L.duq_server_destroy.argtypes = [c_void_p]
     L.duq_server_destroy.restype = None
+    L.duq_solve_static.argtypes = [POINTER(DuqProblem), POINTER(DuqOptions), c_void_p, c_void_p, c_void_p,
+                                   POINTER(DuqResult)]
+    L.duq_solve_static.restype = c_int32
     L.duq_plan_params.argtypes = [c_int32, c_double, c_double, c_double, c_double, c_double, c_double,
                                   POINTER(DuqPlan)]
     L.duq_plan_params.restype = c_int32
@@ -319,6 +323,29 @@ def plan_params(method: int, eps: float, Ld: float, Rd: float, L_in: float = 0.0
     if rc != DUQ_OK:
         raise DuqError(rc, last_error())
     return {k: getattr(out, k) for k, _ in out._fields_}
+
+
+def solve_static(Q, q, G, g, lb, ub, x_out, lam_out, check=True, **opts):
+    """duq_solve_static: one solve with the workspace in the library's static
+    device scratch (no allocation in the call).  Every array is a torch tensor
+    on the GPU (Q, G float64 or float32; the rest float64); x_out (n) and
+    lam_out (p) receive the answer.  lam_min, lam_max, G_norm2 must be given.
+    Returns (status, result dict)."""
+    import torch
+    dt = {torch.float64: F64, torch.float32: F32}[Q.dtype]
+    for t in (q, g, lb, ub, x_out, lam_out):
+        assert t.dtype == torch.float64 and t.is_contiguous()
+    assert Q.is_contiguous() and G.is_contiguous()
+    n, p = int(Q.shape[0]), int(G.shape[0])
+    prob = DuqProblem(n, p, dt, DEVICE, _ptr(Q), _ptr(G) if p else None, _ptr(q), _ptr(g) if p else None,
+                      _ptr(lb), _ptr(ub))
+    o = default_options(**opts)
+    res = DuqResult()
+    rc = lib().duq_solve_static(ctypes.byref(prob), ctypes.byref(o), _stream_of(Q), _ptr(x_out),
+                                _ptr(lam_out) if p else None, ctypes.byref(res))
+    if check and rc not in SOLVE_OUTCOMES:
+        raise DuqError(rc, last_error())
+    return rc, res.as_dict()
 
 
 def solve_batch_uneven(batch, constants=None, check=True, **opts):
