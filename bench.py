@@ -470,7 +470,7 @@ def batch_result(a, workload, B, steps, warmup, precision, with_cpu, oracle_samp
         roof = {"bound": "mfma", "achieved": round(tf, 2), "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
                 "frac": round(tf / FP64_MFMA_PEAK_TFS, 4), "traffic": tr, "kernel": "dfom_tile_kernel",
                 "alg_flops_per_launch": flops, "launch_ms": round(kern_ms, 3),
-                "note": "FP64 MFMA 16x16x4; Q held in LDS, G through L2; flops of masked (finished) "
+                "note": "FP64 MFMA 16x16x4; Q held in registers, X through LDS, G through L2; flops of masked (finished) "
                         "columns and of padding are not counted"}
     else:
         tr = (measured_traffic(f"dfom_batch_kernel_uneven{B}_{precision}.txt", "dfom_batch_kernel")

@@ -119,7 +119,9 @@ typedef struct duq_options {
     int32_t serve_slice;    /* serving loop: outer iterations per round (0 = 16)  */
     int32_t out_memspace;   /* duq_solve_batch: X_out / Lam_out are DUQ_HOST
                                (default) or DUQ_DEVICE buffers                  */
-    int32_t reserved0;
+    int32_t batch_wpc;      /* per-instance batches: workgroups per CU (1..3), or
+                               0 = the tuned value (duq_tune_batch) if one is
+                               known for the batch's sizes, else the most that fit */
     double sigma_in;        /* strong convexity of L_rho(., mu), or <= 0 (above) */
     int32_t reserved[2];
 } duq_options;
@@ -276,7 +278,7 @@ typedef struct duq_batch {
  *                     as GEMVs (DUQ_ENGINE_GRID is taken as BLOCK here);
  *   DUQ_ENGINE_TILE   SHARED only: one workgroup per 16 instances in
  *                     lockstep, Q X, G U and G^T M as FP64 MFMA GEMMs with Q
- *                     held in LDS (rho = 0, n <= 128).
+ *                     held in registers (rho = 0, n <= 128).
  * Both accumulate in FP64 and give each instance the iterates it has alone.
  * With opts.out_memspace = DUQ_DEVICE the kernels write X_out / Lam_out
  * (device buffers) directly and nothing crosses PCIe but `res`.  X_out (sum n_i, or B x n) and
@@ -286,6 +288,23 @@ typedef struct duq_batch {
  * DUQ_EINFEASIBLE when one did not (see res[i].status), or an error code.   */
 int duq_solve_batch(const duq_batch *batch, const duq_options *opts, void *stream,
                     double *X_out, double *Lam_out, duq_result *res);
+
+/* ---- launch-shape tuning for per-instance batches ----------------------- *
+ * duq_tune_batch solves an UNEVEN batch (a representative sample of the
+ * batches to come) once per candidate launch shape -- 1, 2 and 3 workgroups
+ * per CU, as far as they fit -- timing each launch with events on `stream`.
+ * The shape only decides how many instances run at once: every candidate
+ * must give bitwise the same X, multipliers and counts (checked; DUQ_EDEVICE
+ * if not).  The fastest is recorded in a table of this process keyed by
+ * (dtype, row class, largest n rounded up to 64) and used by later
+ * duq_solve_batch calls whose opts.batch_wpc is 0.  *best_wpc gets it;
+ * ms_out (3 doubles, may be NULL) the device time per candidate (0 when a
+ * shape does not fit).  duq_tune_save / duq_tune_load write and read the
+ * table as text ("dtype short_rows n_bucket wpc" per line).                */
+int duq_tune_batch(const duq_batch *batch, const duq_options *opts, void *stream, int32_t *best_wpc,
+                   double *ms_out);
+int duq_tune_save(const char *path);
+int duq_tune_load(const char *path);
 
 /* ---- serving loop (the paper has none; requests are independent QPs) ---- *
  * A server owns a device arena of hbm_budget_bytes (0 = 4 GiB), one HIP

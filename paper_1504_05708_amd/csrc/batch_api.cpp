@@ -4,9 +4,13 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/duq.h"
@@ -24,6 +28,17 @@ int derive_params(int p, double lam_min, double lam_max, double g2, double D_U, 
 }
 
 namespace {
+
+// Launch shapes chosen by duq_tune_batch: (dtype, short-row class, largest n
+// rounded up to 64) -> workgroups per CU.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, int> g_tune;
+
+int tuned_wpc(int dtype, bool sh, int n_max) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(dtype, sh ? 1 : 0, (n_max + 63) / 64));
+    return it == g_tune.end() ? 0 : it->second;
+}
 
 struct DevBuf {
     void* p = nullptr;
@@ -299,7 +314,7 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
                           tile_occupancy(b->dtype, tile_lds_bytes(n_max), &bpc) == hipSuccess && bpc >= 1;
         if (fits) return solve_shared_tiles(b, o, s, dQ, dG, dq, dg, dlb, dub, bpc, X_out, Lam_out, res);
         if (o->engine == DUQ_ENGINE_TILE)
-            return set_error(DUQ_EINVAL, "the MFMA tile engine needs rho = 0 and n <= 128 (Q in LDS)");
+            return set_error(DUQ_EINVAL, "the MFMA tile engine needs rho = 0 and n <= 128");
         (void)hipGetLastError();
     }
     if (o->engine == DUQ_ENGINE_TILE) return set_error(DUQ_EINVAL, "the MFMA tile engine serves shared batches");
@@ -363,7 +378,10 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
         int bpc = 0;
         BTRY(batch_occupancy(b->dtype, c.sh, false, c.shmem, &bpc));
         if (bpc < 1) return set_error(DUQ_EINVAL, "batch instance too large for one workgroup's LDS");
-        c.nblocks = std::max(1, std::min(c.count, device_cus() * bpc));
+        // workgroups per CU: the caller's, else the tuned one, else all that fit
+        int wpc = o->batch_wpc > 0 ? o->batch_wpc : tuned_wpc(b->dtype, c.sh, c.n_max);
+        wpc = wpc > 0 ? std::min(wpc, bpc) : bpc;
+        c.nblocks = std::max(1, std::min(c.count, device_cus() * wpc));
         c.slot = batch_slot_bytes_host(c.n_max, c.p_max, c.k);
     }
 
@@ -516,4 +534,97 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
     }
     if (code != DUQ_OK) set_error(code, "at least one instance did not pass its outer test");
     return code;
+}
+
+// ---- launch-shape tuning ------------------------------------------------------
+
+extern "C" int duq_tune_batch(const duq_batch* b, const duq_options* o, void* stream, int32_t* best_wpc,
+                              double* ms_out) {
+    if (!b || !o || !best_wpc) return set_error(DUQ_EINVAL, "null argument");
+    if (b->kind != DUQ_BATCH_UNEVEN) return set_error(DUQ_EINVAL, "tuning takes an uneven batch");
+    if (b->B < 1 || !b->n || !b->p) return set_error(DUQ_EINVAL, "empty batch");
+    if (ms_out)
+        for (int i = 0; i < 3; ++i) ms_out[i] = 0.0;
+    long long vtot = 0, ctot = 0;
+    for (int i = 0; i < b->B; ++i) {
+        vtot = std::max<long long>(vtot, b->voff[i] + b->n[i]);
+        ctot = std::max<long long>(ctot, b->coff[i] + b->p[i]);
+    }
+    std::vector<double> X0, L0, X1, L1;
+    std::vector<duq_result> r0(b->B), r1(b->B);
+    double best_ms = 0.0;
+    int best = 0;
+    for (int wpc = 1; wpc <= 3; ++wpc) {
+        duq_options oo = *o;
+        oo.batch_wpc = wpc;
+        oo.out_memspace = DUQ_HOST;
+        oo.engine = DUQ_ENGINE_BLOCK;
+        std::vector<double>& X = best ? X1 : X0;
+        std::vector<double>& L = best ? L1 : L0;
+        std::vector<duq_result>& r = best ? r1 : r0;
+        X.assign(std::max<long long>(vtot, 1), 0.0);
+        L.assign(std::max<long long>(ctot, 1), 0.0);
+        const int rc = duq_solve_batch(b, &oo, stream, X.data(), L.data(), r.data());
+        if (rc != DUQ_OK && rc != DUQ_EMAXITER && rc != DUQ_ENUMERIC && rc != DUQ_EINFEASIBLE) return rc;
+        const double ms = r[0].time_ms;
+        if (ms_out) ms_out[wpc - 1] = ms;
+        if (best) {
+            // the shape must not change any result
+            const bool same = std::memcmp(X0.data(), X1.data(), 8 * X0.size()) == 0 &&
+                              std::memcmp(L0.data(), L1.data(), 8 * L0.size()) == 0;
+            bool cnt = true;
+            for (int i = 0; i < b->B; ++i)
+                cnt = cnt && r0[i].outer_iters == r1[i].outer_iters && r0[i].inner_iters == r1[i].inner_iters;
+            if (!same || !cnt)
+                return set_error(DUQ_EDEVICE, "tuning: results differ between launch shapes");
+        }
+        if (!best || ms < best_ms) {
+            best_ms = ms;
+            best = wpc;
+        }
+    }
+    // record the choice for both row classes present in the batch
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    int nmax[2] = {0, 0};
+    for (int i = 0; i < b->B; ++i) {
+        const int sh = batch_short_class(b->dtype, b->n[i]) ? 1 : 0;
+        nmax[sh] = std::max(nmax[sh], b->n[i]);
+    }
+    for (int sh = 0; sh < 2; ++sh)
+        if (nmax[sh] > 0) g_tune[std::make_tuple(b->dtype, sh, (nmax[sh] + 63) / 64)] = best;
+    *best_wpc = best;
+    return DUQ_OK;
+}
+
+extern "C" int duq_tune_save(const char* path) {
+    if (!path) return set_error(DUQ_EINVAL, "null path");
+    FILE* f = std::fopen(path, "w");
+    if (!f) return set_error(DUQ_EINVAL, std::string("cannot write ") + path);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : g_tune)
+        std::fprintf(f, "%d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), kv.second);
+    std::fclose(f);
+    return DUQ_OK;
+}
+
+extern "C" int duq_tune_load(const char* path) {
+    if (!path) return set_error(DUQ_EINVAL, "null path");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return set_error(DUQ_EINVAL, std::string("cannot read ") + path);
+    int dt, sh, nb, w;
+    std::map<std::tuple<int, int, int>, int> t;
+    int got;
+    while ((got = std::fscanf(f, "%d %d %d %d", &dt, &sh, &nb, &w)) == 4) {
+        if ((dt != DUQ_F64 && dt != DUQ_F32) || (sh != 0 && sh != 1) || nb < 1 || w < 1 || w > 3) {
+            std::fclose(f);
+            return set_error(DUQ_EINVAL, "bad tuning record");
+        }
+        t[std::make_tuple(dt, sh, nb)] = w;
+    }
+    const bool eof = got == EOF;
+    std::fclose(f);
+    if (!eof) return set_error(DUQ_EINVAL, "bad tuning file");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : t) g_tune[kv.first] = kv.second;
+    return DUQ_OK;
 }

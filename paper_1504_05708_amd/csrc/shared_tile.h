@@ -1,16 +1,19 @@
 // Shared-Hessian batches on the matrix cores.
 //
-// A workgroup of eight waves advances a tile of 16 instances that share Q
-// (n x n), G (p x n) and the box, in lockstep.  The products of the tile are
-// dense GEMMs on FP64 MFMA (16x16x4):
+// A workgroup of four waves (one per SIMD) advances a tile of 16 instances
+// that share Q (n x n), G (p x n) and the box, in lockstep.  The products of
+// the tile are dense GEMMs on FP64 MFMA (16x16x4):
 //   Q X      (n x 16)  once per inner step       (Sec. 5.1, inner gradient)
 //   G U      (p x 16)  once per outer iteration  (residual of Sec. 3 Step 2)
 //   G^T M    (n x 16)  once per outer iteration  (linear term q + G^T mu)
-// Q stays in LDS (FP64) for the whole launch; G is read through the caches.
-// Wave w owns row tile w of the n rows: lane l holds rows 16 w + l/16 + 4 i
-// (i < 4) of column l % 16 -- the FP64 MFMA result layout -- and keeps its rows of its
-// instance's primal vectors in registers.  The multipliers (p per instance)
-// live in device memory and are updated in the epilogue of the G U product.
+// Wave w owns row tiles w and w + 4 of the n rows (two independent MFMA
+// chains): lane l holds rows 16 t + l/16 + 4 i (i < 4) of column l % 16 --
+// the FP64 MFMA result layout -- and keeps its rows of its instance's primal
+// vectors in registers.  Q never moves during the launch, so each lane keeps
+// its own A-operand entries of Q (its row, every fourth column) in registers
+// for the whole launch; only the B operand X goes through LDS.  G is read
+// through the caches.  The multipliers (p per instance) live in device
+// memory and are updated in the epilogue of the G U product.
 //
 // Per column the arithmetic is Algorithm DFOM with inner FOM (rho = 0) as in
 // the single-instance solver: an instance whose inner or outer loop has ended
@@ -24,8 +27,9 @@
 namespace duq {
 
 constexpr int kTile = 16;       // instances per workgroup
-constexpr int kTileWaves = 8;   // waves per workgroup (two per SIMD hide each other's stalls)
-constexpr int kTileRT = 1;      // row tiles of 16 per wave: n <= 16 * kTileWaves * kTileRT
+constexpr int kTileWaves = 4;   // waves per workgroup, one per SIMD (512 registers each)
+constexpr int kTileRT = 2;      // row tiles of 16 per wave: n <= 16 * kTileWaves * kTileRT
+constexpr int kTileQS = 32;     // k-steps of 4 columns of Q held per lane: n <= 4 * kTileQS
 constexpr int kTileK = 6;       // slots of the outer reduction buffer (longer records go in chunks)
 
 typedef double tile_v4d __attribute__((ext_vector_type(4)));
@@ -50,20 +54,16 @@ struct TileArgs {
     unsigned* queue;
 };
 
-// LDS layout, in doubles: Q (n rows, odd stride), two buffers of the B
-// operand X (kp x 16), the inner reduction (two buffers), the outer one, the
-// box (lb then ub).
-__host__ __device__ inline int tile_ldh(int n) { return n | 1; }
+// LDS layout, in doubles: two buffers of the B operand X (kp x 16), the
+// inner reduction (two buffers), the outer one, the box (lb then ub).
 __host__ __device__ inline int tile_kp(int n) { return (n + 3) & ~3; }
 __host__ __device__ inline long tile_lds_doubles(int n) {
-    return (long)n * tile_ldh(n) + 2L * tile_kp(n) * kTile + 2L * kTileWaves * kTile * 2 +
-           (long)kTileWaves * kTile * kTileK + 2L * n;
+    return 2L * tile_kp(n) * kTile + 2L * kTileWaves * kTile * 2 + (long)kTileWaves * kTile * kTileK + 2L * n;
 }
 
 template <typename T>
 struct Tile {
     TileArgs<T> a;
-    double* Hs;
     double* Xs0;
     double* Xs1;
     double* red2;
@@ -73,6 +73,23 @@ struct Tile {
     bool valid;
     // this lane's rows of its column
     double x[kTileRT][4], xp[kTileRT][4], qx[kTileRT][4], qxp[kTileRT][4], c[kTileRT][4];
+    // this lane's A-operand entries of Q: row 16 (w + kTileWaves j) + lane % 16,
+    // columns 4 s + lane / 16 (zero outside the matrix)
+    double qa[kTileRT][kTileQS];
+    double invL;   // 1 / L_in of the inner step
+
+    __device__ __forceinline__ void load_q() {
+        const int n = a.n;
+#pragma unroll
+        for (int j = 0; j < kTileRT; ++j) {
+            const int r = 16 * (w + kTileWaves * j) + (lane & 15);
+#pragma unroll
+            for (int s = 0; s < kTileQS; ++s) {
+                const int k = 4 * s + grp;
+                qa[j][s] = (r < n && k < n) ? (double)a.Q[(long)r * n + k] : 0.0;
+            }
+        }
+    }
 
     __device__ __forceinline__ int row(int j, int i) const { return 16 * (w + kTileWaves * j) + grp + 4 * i; }
 
@@ -91,6 +108,33 @@ struct Tile {
             for (int k = 0; k < K; ++k) buf[(w * kTile + col) * K + k] = v[k];
         }
         __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double t = buf[col * K + k];
+#pragma unroll
+            for (int ww = 1; ww < kTileWaves; ++ww) t += buf[(ww * kTile + col) * K + k];
+            v[k] = t;
+        }
+    }
+
+    // colsum in two halves: publish (wave partials to LDS, then the barrier)
+    // and finish (every lane sums its column), so that independent work can
+    // be issued between the barrier and the reads.
+    template <int K>
+    __device__ __forceinline__ void colsum_publish(double (&v)[K], double* buf) const {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            v[k] += __shfl_xor(v[k], 16, 64);
+            v[k] += __shfl_xor(v[k], 32, 64);
+        }
+        if (grp == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) buf[(w * kTile + col) * K + k] = v[k];
+        }
+        __syncthreads();
+    }
+    template <int K>
+    __device__ __forceinline__ void colsum_finish(double (&v)[K], const double* buf) const {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             double t = buf[col * K + k];
@@ -123,35 +167,28 @@ struct Tile {
     // each MFMA waiting for its own.
     static constexpr int kB = 8;
 
-    // acc[j] = Q Xs for this wave's row tiles (Q from LDS).
+    // acc[j] = Q Xs for this wave's row tiles: A from the registers of Q, B
+    // from LDS in batches of kB k-steps (loads issued before their MFMAs).
     __device__ __forceinline__ void prodQ(const double* Xs, tile_v4d (&acc)[kTileRT]) const {
-        const int n = a.n, ldh = tile_ldh(n), ks = tile_kp(n) / 4;
-        const double* h[kTileRT];
-        bool v[kTileRT];
+        const int ks = tile_kp(a.n) / 4;
 #pragma unroll
-        for (int j = 0; j < kTileRT; ++j) {
-            const int r = 16 * (w + kTileWaves * j) + (lane & 15);
-            v[j] = r < n;
-            h[j] = Hs + (v[j] ? r : 0) * ldh;
-            acc[j] = tile_v4d{0.0, 0.0, 0.0, 0.0};
-        }
-        for (int s0 = 0; s0 < ks; s0 += kB) {
-            double av[kTileRT][kB], bv[kB];
+        for (int j = 0; j < kTileRT; ++j) acc[j] = tile_v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int u = 0; u < kB; ++u) {
-                const int k = 4 * (s0 + u) + grp;
-                const bool kv = s0 + u < ks && k < n;
-                const int kk = kv ? k : 0;
-                bv[u] = kv ? Xs[kk * kTile + col] : 0.0;
+        for (int s0 = 0; s0 < kTileQS; s0 += kB) {
+            if (s0 < ks) {   // uniform
+                double bv[kB];
 #pragma unroll
-                for (int j = 0; j < kTileRT; ++j) av[j][u] = (v[j] && kv) ? h[j][kk] : 0.0;
+                for (int u = 0; u < kB; ++u) {
+                    // rows of Xs from n up to kp are zero; steps past ks add zeros
+                    const int k = 4 * (s0 + u) + grp;
+                    bv[u] = s0 + u < ks ? Xs[k * kTile + col] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < kB; ++u)
+#pragma unroll
+                    for (int j = 0; j < kTileRT; ++j)
+                        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[j][s0 + u], bv[u], acc[j], 0, 0, 0);
             }
-            // steps past ks carry zero operands: they add exact zeros
-#pragma unroll
-            for (int u = 0; u < kB; ++u)
-#pragma unroll
-                for (int j = 0; j < kTileRT; ++j)
-                    acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j][u], bv[u], acc[j], 0, 0, 0);
         }
     }
 
@@ -291,12 +328,19 @@ struct Tile {
                         acc[1] += pi * pi;
                         const double yi = xi + beta * (xi - xp[j][i]);
                         const double qyi = qx[j][i] + beta * (qx[j][i] - qxp[j][i]);
-                        xn[j][i] = fmin(fmax(yi - (qyi + c[j][i]) / par.L, l), h);
+                        xn[j][i] = fmin(fmax(yi - (qyi + c[j][i]) * invL, l), h);
                     }
                 }
             double* Xs = sel ? Xs1 : Xs0;
+            double* rbuf = red2 + sel * (kTileWaves * kTile * 2);
             put_x(Xs, xn);
-            colsum<2>(acc, red2 + sel * (kTileWaves * kTile * 2));   // barrier: Xs and sums
+            colsum_publish<2>(acc, rbuf);   // barrier: Xs and the partial sums
+            // Q x^{t+1} is issued before the stop decision is read back: the
+            // product overlaps the column sums, and is dropped when every
+            // column has stopped
+            tile_v4d qn[kTileRT];
+            prodQ(Xs, qn);
+            colsum_finish<2>(acc, rbuf);
             const double gap = gap_from(acc[0], acc[1]);
             if (run) {
                 if (!(gap == gap)) {
@@ -312,8 +356,6 @@ struct Tile {
             }
             if (!__any(run)) break;   // every wave holds all 16 columns: same decision
             if (t > 0 && par.inner_variant == 2) th = 0.5 * (1.0 + sqrt(1.0 + 4.0 * th * th));
-            tile_v4d qn[kTileRT];
-            prodQ(Xs, qn);
             if (run) {
 #pragma unroll
                 for (int j = 0; j < kTileRT; ++j)
@@ -664,8 +706,7 @@ __device__ __forceinline__ void tile_solve(const TileArgs<T>& args, double* lds)
     Tile<T> s;
     s.a = args;
     const int n = args.n;
-    s.Hs = lds;
-    s.Xs0 = lds + (long)n * tile_ldh(n);
+    s.Xs0 = lds;
     s.Xs1 = s.Xs0 + tile_kp(n) * kTile;
     s.red2 = s.Xs1 + tile_kp(n) * kTile;
     s.redK = s.red2 + 2 * kTileWaves * kTile * 2;
@@ -674,9 +715,10 @@ __device__ __forceinline__ void tile_solve(const TileArgs<T>& args, double* lds)
     s.w = threadIdx.x >> 6;
     s.col = s.lane & 15;
     s.grp = s.lane >> 4;
-    // Q into LDS once (FP64); both X buffers cleared: their rows >= n stay zero
-    const int ldh = tile_ldh(n);
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) s.Hs[(e / n) * ldh + e % n] = (double)args.Q[e];
+    s.invL = 1.0 / args.par.L;
+    // this lane's entries of Q into registers once; both X buffers cleared:
+    // their rows >= n stay zero
+    s.load_q();
     for (int e = threadIdx.x; e < 2 * tile_kp(n) * kTile; e += blockDim.x) s.Xs0[e] = 0.0;
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
         s.box[e] = args.lb[e];

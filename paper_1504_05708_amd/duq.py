@@ -39,7 +39,7 @@ SERVE_BATCH_NMAX = 1536
 EXPORTS = ["duq_default_options", "duq_setup", "duq_max_n", "duq_solve", "duq_get_trace", "duq_get_constants",
            "duq_destroy", "duq_last_error", "duq_strerror", "duq_solve_batch", "duq_server_create",
            "duq_register_shared", "duq_submit", "duq_poll", "duq_server_destroy", "duq_solve_static",
-           "duq_plan_params", "duq_solve_planned"]
+           "duq_plan_params", "duq_solve_planned", "duq_tune_batch", "duq_tune_save", "duq_tune_load"]
 STATIC_SCRATCH_BYTES = 64 << 20
 
 
@@ -57,7 +57,7 @@ class DuqOptions(Structure):
                 ("rho", c_double), ("lam_min", c_double), ("lam_max", c_double),
                 ("G_norm2", c_double), ("safety", c_double), ("switch_factor", c_double),
                 ("switch_stall", c_int32), ("serve_slice", c_int32), ("out_memspace", c_int32),
-                ("reserved0", c_int32), ("sigma_in", c_double), ("reserved", c_int32 * 2)]
+                ("batch_wpc", c_int32), ("sigma_in", c_double), ("reserved", c_int32 * 2)]
 
 
 class DuqResult(Structure):
@@ -156,6 +156,13 @@ def lib() -> ctypes.CDLL:
     L.duq_solve_static.argtypes = [POINTER(DuqProblem), POINTER(DuqOptions), c_void_p, c_void_p, c_void_p,
                                    POINTER(DuqResult)]
     L.duq_solve_static.restype = c_int32
+    L.duq_tune_batch.argtypes = [POINTER(DuqBatch), POINTER(DuqOptions), c_void_p, POINTER(c_int32),
+                                 POINTER(c_double)]
+    L.duq_tune_batch.restype = c_int32
+    L.duq_tune_save.argtypes = [c_char_p]
+    L.duq_tune_save.restype = c_int32
+    L.duq_tune_load.argtypes = [c_char_p]
+    L.duq_tune_load.restype = c_int32
     L.duq_plan_params.argtypes = [c_int32, c_double, c_double, c_double, c_double, c_double, c_double,
                                   POINTER(DuqPlan)]
     L.duq_plan_params.restype = c_int32
@@ -375,6 +382,39 @@ def solve_batch_uneven(batch, constants=None, check=True, **opts):
     b = DuqBatch(BATCH_UNEVEN, B, dt, DEVICE if dev else HOST, 0, 0, _ptr(n), _ptr(p), *[_ptr(o) for o in offs],
                  _ptr(Q), _ptr(G), *[_ptr(v) for v in vecs], *[_ptr(c) for c in cs])
     return _run_batch(b, B, int(batch.q.shape[0]), int(batch.g.shape[0]), check, opts)
+
+
+def tune_batch(batch, **opts):
+    """duq_tune_batch on a packed gen.UnevenBatch (host arrays): returns
+    (best workgroups per CU, device ms per candidate 1..3)."""
+    n = np.ascontiguousarray(batch.n, dtype=np.int32)
+    p = np.ascontiguousarray(batch.p, dtype=np.int32)
+    offs = [np.ascontiguousarray(v, dtype=np.int64) for v in (batch.qoff, batch.goff, batch.voff, batch.coff)]
+    Q = np.ascontiguousarray(batch.Q)
+    dt = {np.dtype(np.float64): F64, np.dtype(np.float32): F32}[Q.dtype]
+    G = np.ascontiguousarray(batch.G, dtype=Q.dtype)
+    vecs = [np.ascontiguousarray(v, dtype=np.float64) for v in (batch.q, batch.g, batch.lb, batch.ub)]
+    b = DuqBatch(BATCH_UNEVEN, batch.B, dt, HOST, 0, 0, _ptr(n), _ptr(p), *[_ptr(o) for o in offs],
+                 _ptr(Q), _ptr(G), *[_ptr(v) for v in vecs], None, None, None)
+    o = default_options(**opts)
+    best = c_int32()
+    ms = (c_double * 3)()
+    rc = lib().duq_tune_batch(ctypes.byref(b), ctypes.byref(o), c_void_p(None), ctypes.byref(best), ms)
+    if rc != DUQ_OK:
+        raise DuqError(rc, last_error())
+    return best.value, list(ms)
+
+
+def tune_save(path: str):
+    rc = lib().duq_tune_save(path.encode())
+    if rc != DUQ_OK:
+        raise DuqError(rc, last_error())
+
+
+def tune_load(path: str):
+    rc = lib().duq_tune_load(path.encode())
+    if rc != DUQ_OK:
+        raise DuqError(rc, last_error())
 
 
 def solve_batch_shared(Q, G, lb, ub, q, g, constants=None, check=True, **opts):

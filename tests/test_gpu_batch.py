@@ -186,3 +186,21 @@ def test_uneven_batch_other_options_match_oracle(method, output, rho):
             assert abs(r["outer_iters"] - ref.outer_iters) <= 2, (i, r["outer_iters"], ref.outer_iters)
             assert abs(r["inner_iters"] - ref.inner_iters) <= 0.01 * ref.inner_iters, (i, r, ref.inner_iters)
             np.testing.assert_allclose(X[ub.voff[i]:ub.voff[i] + qp.n], ref.x, rtol=0, atol=1e-5)
+
+
+def test_tuned_launch_shape_leaves_results_unchanged(tmp_path):
+    # duq_tune_batch times 1, 2 and 3 workgroups per CU (checking inside that
+    # all three give the same bits), records the fastest, and later batches
+    # with batch_wpc = 0 use it: results equal a run at every explicit shape
+    print("[case] batch launch-shape tuning", flush=True)
+    ub = gen.uneven_batch(B=60, seed=71, n_lo=20, n_hi=300, dtype=np.float32)
+    kw = dict(method=duq.DFGM, eps_out=1e-4, eps_in=1e-8, max_outer=20000)
+    best, ms = duq.tune_batch(ub, **kw)
+    assert best in (1, 2, 3) and ms[best - 1] > 0.0
+    X, Lam, res = duq.solve_batch_uneven(ub, **kw)
+    for wpc in (1, 2, 3):
+        Xw, Lw, rw = duq.solve_batch_uneven(ub, batch_wpc=wpc, **kw)
+        assert np.array_equal(X, Xw) and np.array_equal(Lam, Lw), wpc
+        assert [r["inner_iters"] for r in res] == [r["inner_iters"] for r in rw]
+    duq.tune_save(str(tmp_path / "tune.txt"))
+    assert (tmp_path / "tune.txt").read_text().strip()

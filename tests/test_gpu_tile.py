@@ -95,11 +95,12 @@ def test_tile_engine_rejects_what_it_cannot_run():
     assert e.value.code == duq.DUQ_EINVAL
 
 
-@pytest.mark.parametrize("n,p", [(37, 21), (1, 3), (13, 0), (121, 50)])
+@pytest.mark.parametrize("n,p", [(37, 21), (1, 3), (13, 0), (121, 50), (128, 40)])
 def test_tile_ragged_generic_shapes_match_oracle(n, p):
     """Shapes the MPC systems never produce: n not a multiple of 4 (a partial
-    last k-step), p not a multiple of 16, no constraints, n = 1, the largest n
-    whose Q fits the LDS."""
+    last k-step), p not a multiple of 16, no constraints, n = 1, and n = 128,
+    the largest n the tile holds (eight row tiles of 16, 32 k-steps of Q per
+    lane in registers)."""
     print(f"[case] tile generic shape n={n} p={p}", flush=True)
     base = gen.random_dense_qp(n, max(p, 1), seed=60 + n, reg=0.1)
     G = base.G[:p]

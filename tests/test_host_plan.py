@@ -27,3 +27,20 @@ def test_library_plan_rejects_bad_input():
         with pytest.raises(duq.DuqError) as e:
             duq.plan_params(*args)
         assert e.value.code == duq.DUQ_EINVAL
+
+
+def test_tuning_table_round_trip(tmp_path):
+    # the tuning table is host data: records load, save back unchanged, and a
+    # malformed file is refused
+    src = tmp_path / "tune.txt"
+    src.write_text("0 0 4 2\n1 1 2 3\n")
+    duq.tune_load(str(src))
+    out = tmp_path / "out.txt"
+    duq.tune_save(str(out))
+    lines = set(out.read_text().split("\n")) - {""}
+    assert {"0 0 4 2", "1 1 2 3"} <= lines
+    bad = tmp_path / "bad.txt"
+    bad.write_text("0 0 4 9\n")
+    with pytest.raises(duq.DuqError) as e:
+        duq.tune_load(str(bad))
+    assert e.value.code == duq.DUQ_EINVAL
