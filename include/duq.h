@@ -59,6 +59,7 @@ enum { DUQ_INNER_AUTO = 0, DUQ_INNER_GM = 1, DUQ_INNER_FGM = 2,
 enum { DUQ_ACC_F64 = 0, DUQ_ACC_F32 = 1 };                    /* product accumulation */
 enum { DUQ_ENGINE_AUTO = 0, DUQ_ENGINE_BLOCK = 1, DUQ_ENGINE_GRID = 2,
        DUQ_ENGINE_TILE = 3 };   /* TILE: shared batches only, see duq_solve_batch */
+enum { DUQ_SPX_AUTO = 0, DUQ_SPX_LDS = 1, DUQ_SPX_IN_PLACE = 2 };  /* options.sparse_x */
 
 /* ---- problem data (Sec. 2, eq. original_primal) ------------------------- *
  * Constraints: G u + g <= 0 (K = R^p_-) when rlo and rhi are NULL.  With
@@ -123,7 +124,10 @@ typedef struct duq_options {
                                0 = the tuned value (duq_tune_batch) if one is
                                known for the batch's sizes, else the most that fit */
     double sigma_in;        /* strong convexity of L_rho(., mu), or <= 0 (above) */
-    int32_t reserved[2];
+    int32_t sparse_x;       /* duq_setup_csr: where products read x: DUQ_SPX_AUTO
+                               (staged in LDS when it fits, else in place),
+                               DUQ_SPX_LDS, DUQ_SPX_IN_PLACE (device memory)  */
+    int32_t reserved[1];
 } duq_options;
 
 /* ---- per-solve result --------------------------------------------------- *
@@ -167,6 +171,40 @@ void duq_default_options(duq_options *o);
  * duq_last_error() states the exact bound; duq_max_n gives it in advance. */
 int duq_setup(const duq_problem *prob, const duq_options *opts, void *stream,
               duq_handle **out);
+
+/* ---- sparse Q and G (Sec. 5.1) ------------------------------------------ *
+ * The inner gradient Q u + q + G^T w and the dual gradient G u + g are the
+ * bottleneck of both stages (Sec. 5.1); with sparse Q and G they cost their
+ * nonzeros instead of n^2 and n p.  A matrix in compressed-row form:       */
+typedef struct duq_csr {
+    int32_t rows, cols;
+    const int64_t *rowptr;  /* rows + 1 offsets: rowptr[0] = 0, nondecreasing    */
+    const int32_t *col;     /* rowptr[rows] column indices, each in [0, cols);    */
+                            /* any order inside a row; a repeated index adds     */
+    const void *val;        /* rowptr[rows] values of the problem's dtype        */
+} duq_csr;
+
+/* duq_setup for sparse data: Q (n x n, symmetric, both triangles stored) and
+ * G (p x n) in compressed-row form.  prob->Q and prob->G are not read (may be
+ * NULL); every array (the CSR arrays included) is host memory and is copied
+ * (prob->memspace must be DUQ_HOST); G^T is formed on the host once so that
+ * the transposed product gathers along rows.  Everything else is as
+ * duq_setup: row bounds, options, constants estimated by Lanczos on the
+ * sparse operators, block or grid engine, duq_solve / duq_get_trace /
+ * duq_solve_planned on the handle.  Every row an equality with rho > 0: the inner
+ * products stay Q u and G^T (G u) (no formed Q + rho G^T G) and the inner
+ * strong convexity is lambda_min(Q) unless opts->sigma_in is given.  Each
+ * product row is summed by sixteen lanes in a fixed order, so a solve is
+ * reproducible run to run.  The products read x from a copy staged in LDS
+ * (the LDS bound on n of duq_setup) or, with opts->sparse_x IN_PLACE (AUTO
+ * when the copy does not fit), from device memory, which leaves n bounded
+ * by device memory only; the LDS then holds the engine's share of the p
+ * rows (block engine: all p).
+ * Errors: DUQ_EINVAL (null arrays, shapes other than n x n and p x n,
+ * offsets, an index out of range, a non-finite value, memspace),
+ * DUQ_ENOMEM, DUQ_EDEVICE.                                                  */
+int duq_setup_csr(const duq_problem *prob, const duq_csr *Q, const duq_csr *G,
+                  const duq_options *opts, void *stream, duq_handle **out);
 
 /* Largest n that duq_setup accepts for a problem with p rows of G on
  * `engine` (DUQ_ENGINE_BLOCK or DUQ_ENGINE_GRID; AUTO is answered for GRID,

@@ -107,6 +107,7 @@ __device__ inline void batch_carve(char* base, int n, int p, int k, DevWork& W, 
     W.lamm = nullptr;
     W.mum = nullptr;
     W.nu = nullptr;
+    W.wsh = nullptr;
     W.part = nullptr;
     W.gtp = nullptr;
     W.trace = nullptr;

@@ -300,6 +300,55 @@ __device__ __forceinline__ void gemvT_reduce(const double* part, int nb, int n, 
     }
 }
 
+// Sparse rows (Sec. 5.1: with sparse Q and G the products cost their
+// nonzeros): out[r] = sum_k val[k] x[col[k]] + add[r] for rows [rlo, rhi) of
+// a compressed-row matrix, x read through `xa` (LDS, or device memory when x
+// does not fit).  Sixteen lanes per row, four rows per wavefront per trip; a
+// row's lanes take its nonzeros in a fixed stride and reduce by a butterfly,
+// so the sum order depends on the row only.
+template <typename T, typename Acc, typename X>
+__device__ __forceinline__ void spmv_rows(const long long* rp, const int* ci, const T* val, int rlo, int rhi,
+                                          X xa, double* out, const double* add) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    const int sub = lane >> 4, sl = lane & 15;
+    for (int r0 = rlo + wid * 4; r0 < rhi; r0 += nw * 4) {
+        const int r = r0 + sub;
+        Acc s = 0;
+        if (r < rhi) {
+            const long long e = rp[r + 1];
+            for (long long k = rp[r] + sl; k < e; k += 16) s += (Acc)val[k] * (Acc)xa(ci[k]);
+        }
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
+        if (sl == 0 && r < rhi) out[r] = (double)s + (add ? add[r] : 0.0);
+    }
+}
+
+// Sparse transposed product for the owned columns [clo, chi): z[j] = add[j] +
+// sum over the nonzeros of row j of G^T (= column j of G) of val[k] w[col[k]],
+// with the weights w read through `wt` (LDS or the team-visible buffer).
+template <typename T, typename W>
+__device__ __forceinline__ void spmvT_cols(const long long* rp, const int* ci, const T* val, int clo, int chi,
+                                           W wt, const double* add, double* z) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    const int sub = lane >> 4, sl = lane & 15;
+    for (int j0 = clo + wid * 4; j0 < chi; j0 += nw * 4) {
+        const int j = j0 + sub;
+        double s = 0.0;
+        if (j < chi) {
+            const long long e = rp[j + 1];
+            for (long long k = rp[j] + sl; k < e; k += 16) s += (double)val[k] * wt(ci[k]);
+        }
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
+        if (sl == 0 && j < chi) z[j] = s + (add ? add[j] : 0.0);
+    }
+}
+
 __device__ __forceinline__ void stage(const double* src, int len, double* dst) {
     for (int i = threadIdx.x; i < len; i += blockDim.x) dst[i] = src[i];
     __syncthreads();
@@ -357,7 +406,7 @@ __device__ __forceinline__ RowSides row_sides(const double* rlo, const double* r
     return s;
 }
 
-template <typename T, typename Acc, bool SHORT, bool ROWS = false>
+template <typename T, typename Acc, bool SHORT, bool ROWS = false, bool SPARSE = false>
 struct Dfom {
     DevProblem<T> P;
     DevParams par;
@@ -365,6 +414,7 @@ struct Dfom {
     Team tm;
     int nlo, nhi, plo, phi;  // owned variable / row ranges
     double* xl;              // LDS: staged n-vector
+    const double* xsrc;      // sparse data with x read in place (par.x_global)
     double* vl;              // LDS: staged owned rows of a p-vector
     double* red;             // LDS: reduction scratch
     double* tl;              // LDS: blockDim*4 doubles for short-row G^T v
@@ -382,17 +432,35 @@ struct Dfom {
     }
     __device__ __forceinline__ double get(const double* p) const { return tm.size > 1 ? xload(p) : *p; }
     __device__ __forceinline__ void stage_x(const double* src) {
+        if constexpr (SPARSE) {
+            if (par.x_global) {
+                xsrc = src;
+                __syncthreads();
+                return;
+            }
+        }
         if (tm.size > 1) stage_shared(src, P.n, xl); else stage(src, P.n, xl);
+    }
+    // Compressed-row product over rows [lo, hi) with x from LDS or, when it
+    // does not fit there, from the rotating buffer itself (device-scope loads
+    // on a grid team: other workgroups wrote it).
+    __device__ __forceinline__ void sp_rows(const long long* rp, const int* ci, const T* v, int lo, int hi,
+                                            double* out, const double* add) const {
+        if (!par.x_global) spmv_rows<T, Acc>(rp, ci, v, lo, hi, [&](int j) { return xl[j]; }, out, add);
+        else if (tm.size > 1) spmv_rows<T, Acc>(rp, ci, v, lo, hi, [&](int j) { return xload(xsrc + j); }, out, add);
+        else spmv_rows<T, Acc>(rp, ci, v, lo, hi, [&](int j) { return xsrc[j]; }, out, add);
     }
 
     // Products over owned rows: streamed (non-temporal) on a grid team,
     // cached inside a single workgroup.
     __device__ __forceinline__ void prodQ(double* out) const {
-        if (tm.size > 1) gemv_rows<T, Acc, 16, true, SHORT>(P.Q, P.n, nlo, nhi, P.n, xl, out, nullptr);
+        if constexpr (SPARSE) sp_rows(P.Qrp, P.Qci, P.Qv, nlo, nhi, out, nullptr);
+        else if (tm.size > 1) gemv_rows<T, Acc, 16, true, SHORT>(P.Q, P.n, nlo, nhi, P.n, xl, out, nullptr);
         else gemv_rows<T, Acc, 16, false, SHORT>(P.Q, P.n, nlo, nhi, P.n, xl, out, nullptr);
     }
     __device__ __forceinline__ void prodG(double* out, const double* add) const {
-        if (tm.size > 1) gemv_rows<T, Acc, 8, true, SHORT>(P.G, P.n, plo, phi, P.n, xl, out, add);
+        if constexpr (SPARSE) sp_rows(P.Grp, P.Gci, P.Gv, plo, phi, out, add);
+        else if (tm.size > 1) gemv_rows<T, Acc, 8, true, SHORT>(P.G, P.n, plo, phi, P.n, xl, out, add);
         else gemv_rows<T, Acc, 8, false, SHORT>(P.G, P.n, plo, phi, P.n, xl, out, add);
     }
     __device__ __forceinline__ void bind_rings() {
@@ -445,18 +513,36 @@ struct Dfom {
     template <typename F>
     __device__ __forceinline__ bool gemvT_w(F wt, const double* add, double* z) {
         const int n = P.n;
-        for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) vl[i - plo] = wt(i);
-        __syncthreads();
-        if (tm.size == 1) {
-            gt_rows += gemvT_rows<T, Acc, false>(P.G, n, plo, phi, n, vl, z, add, false, tl);
+        if constexpr (SPARSE) {
+            // sparse: gather along the rows of G^T; the weights of every row are
+            // needed, so they are published (LDS inside one workgroup, the
+            // team-visible buffer on a grid team)
+            if (tm.size == 1) {
+                for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) vl[i - plo] = wt(i);
+                __syncthreads();
+                spmvT_cols<T>(P.Trp, P.Tci, P.Tv, nlo, nhi, [&](int k) { return vl[k - plo]; }, add, z);
+            } else {
+                for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) xstore(W.wsh + i, wt(i));
+                if (tm.sync()) return false;
+                spmvT_cols<T>(P.Trp, P.Tci, P.Tv, nlo, nhi, [&](int k) { return xload(W.wsh + k); }, add, z);
+            }
+            __syncthreads();
+            return true;
+        } else {
+            for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) vl[i - plo] = wt(i);
+            __syncthreads();
+            if (tm.size == 1) {
+                gt_rows += gemvT_rows<T, Acc, false>(P.G, n, plo, phi, n, vl, z, add, false, tl);
+                __syncthreads();
+                return true;
+            }
+            gt_rows +=
+                gemvT_rows<T, Acc, true>(P.G, n, plo, phi, n, vl, W.gtp + (long)tm.rank * n, nullptr, true, tl);
+            if (tm.sync()) return false;
+            gemvT_reduce(W.gtp, tm.size, n, nlo, nhi, add, z);
             __syncthreads();
             return true;
         }
-        gt_rows += gemvT_rows<T, Acc, true>(P.G, n, plo, phi, n, vl, W.gtp + (long)tm.rank * n, nullptr, true, tl);
-        if (tm.sync()) return false;
-        gemvT_reduce(W.gtp, tm.size, n, nlo, nhi, add, z);
-        __syncthreads();
-        return true;
     }
 
     __device__ __forceinline__ double clip(double v, int i) const {

@@ -122,6 +122,11 @@ struct duq_handle {
     bool eqform = false;
     double *drlo = nullptr, *drhi = nullptr;
     void* dH = nullptr;            // Q + rho G^T G (equality form), owned
+    // compressed-row Q, G and G^T (inside owned_data) when set up from CSR
+    bool sparse = false;
+    bool x_global = false;         // sparse: x read in place (it does not fit in LDS)
+    SparseRefs sp{};
+    long long nnzQ = 0, nnzG = 0;
     // constants
     double lam_min = 0, lam_max = 0, G2 = 0;
     double Ld = 0, alpha = 0, L_in = 0, sigma = 0, beta_in = 0, D_U = 0;
@@ -197,14 +202,14 @@ void duq_destroy(duq_handle* h) {
 
 namespace duq {
 
-int validate_problem(const duq_problem* pr, const duq_options* o) {
+int validate_common(const duq_problem* pr, const duq_options* o, bool sparse) {
     if (!pr || !o) return fail(DUQ_EINVAL, "null problem or options");
     if (pr->n <= 0) return fail(DUQ_EINVAL, "n must be positive");
     if (pr->p < 0) return fail(DUQ_EINVAL, "p must be non-negative");
     if (pr->dtype != DUQ_F64 && pr->dtype != DUQ_F32) return fail(DUQ_EINVAL, "dtype must be F64 or F32");
     if (pr->memspace != DUQ_HOST && pr->memspace != DUQ_DEVICE) return fail(DUQ_EINVAL, "bad memspace");
-    if (!pr->Q || !pr->q || !pr->lb || !pr->ub) return fail(DUQ_EINVAL, "null Q, q, lb or ub");
-    if (pr->p > 0 && (!pr->G || !pr->g)) return fail(DUQ_EINVAL, "null G or g with p > 0");
+    if ((!sparse && !pr->Q) || !pr->q || !pr->lb || !pr->ub) return fail(DUQ_EINVAL, "null Q, q, lb or ub");
+    if (pr->p > 0 && ((!sparse && !pr->G) || !pr->g)) return fail(DUQ_EINVAL, "null G or g with p > 0");
     if ((pr->rlo == nullptr) != (pr->rhi == nullptr)) return fail(DUQ_EINVAL, "give both rlo and rhi, or neither");
     if (pr->rlo && o->accumulate != DUQ_ACC_F64)
         return fail(DUQ_EINVAL, "row bounds need FP64 accumulation (no precision switch)");
@@ -221,8 +226,39 @@ int validate_problem(const duq_problem* pr, const duq_options* o) {
     if (o->max_inner < 0 || o->trace_outer < 0 || o->lanczos_steps < 0)
         return fail(DUQ_EINVAL, "negative count");
     if (!(o->safety >= 1.0)) return fail(DUQ_EINVAL, "safety must be >= 1");
+    if (o->sparse_x < DUQ_SPX_AUTO || o->sparse_x > DUQ_SPX_IN_PLACE) return fail(DUQ_EINVAL, "bad sparse_x");
     return DUQ_OK;
 }
+
+int validate_problem(const duq_problem* pr, const duq_options* o) { return validate_common(pr, o, false); }
+
+// A compressed-row matrix of shape rows x cols (Sec. 5.1 sparse data): offsets
+// from 0 and nondecreasing, indices in range, finite values.
+int check_csr(const duq_csr* M, int rows, int cols, int dtype, const char* name) {
+    const std::string nm(name);
+    if (!M) return fail(DUQ_EINVAL, "null " + nm);
+    if (M->rows != rows || M->cols != cols)
+        return fail(DUQ_EINVAL, nm + " has shape " + std::to_string(M->rows) + " x " + std::to_string(M->cols) +
+                                    ", expected " + std::to_string(rows) + " x " + std::to_string(cols));
+    if (!M->rowptr) return fail(DUQ_EINVAL, "null " + nm + " row offsets");
+    if (M->rowptr[0] != 0) return fail(DUQ_EINVAL, nm + " row offsets must start at 0");
+    for (int i = 0; i < rows; ++i)
+        if (M->rowptr[i + 1] < M->rowptr[i])
+            return fail(DUQ_EINVAL, nm + " row offsets decrease at row " + std::to_string(i));
+    const long long nnz = M->rowptr[rows];
+    if (nnz > 0 && (!M->col || !M->val)) return fail(DUQ_EINVAL, "null " + nm + " indices or values");
+    for (long long k = 0; k < nnz; ++k)
+        if (M->col[k] < 0 || M->col[k] >= cols)
+            return fail(DUQ_EINVAL, nm + " column index out of range at entry " + std::to_string(k));
+    const bool ok =
+        dtype == DUQ_F64 ? finite_all_t((const double*)M->val, nnz) : finite_all_t((const float*)M->val, nnz);
+    if (!ok) return fail(DUQ_EINVAL, "non-finite value in " + nm);
+    return DUQ_OK;
+}
+
+int upload_sparse(duq_handle* h, const duq_problem* pr, const duq_csr* Qs, const duq_csr* Gs,
+                  const std::vector<double>& lb, const std::vector<double>& ub, const std::vector<double>& rlo,
+                  const std::vector<double>& rhi);
 
 }  // namespace duq
 
@@ -285,10 +321,14 @@ extern "C" int duq_max_n(int32_t p, int32_t engine, int32_t* n_max) {
     return DUQ_OK;
 }
 
-extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* stream, duq_handle** out) {
+// duq_setup (Qs null: dense Q and G in `pr`) and duq_setup_csr (compressed-row
+// Q and G, already checked).
+static int setup_impl(const duq_problem* pr, const duq_csr* Qs, const duq_csr* Gs, const duq_options* opts,
+                      void* stream, duq_handle** out) {
     if (!out) return fail(DUQ_EINVAL, "null output handle");
     *out = nullptr;
-    int rc = validate_problem(pr, opts);
+    const bool sparse = Qs != nullptr;
+    int rc = validate_common(pr, opts, sparse);
     if (rc) return rc;
     const int n = pr->n, p = pr->p, dtype = pr->dtype;
     const long nn = (long)n * n, pn = (long)p * n;
@@ -296,7 +336,12 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
     if ((rc = device_info(&di))) return rc;
     int engine = opts->engine;
     if (engine == DUQ_ENGINE_AUTO) engine = (n <= 1536) ? DUQ_ENGINE_BLOCK : DUQ_ENGINE_GRID;
-    if (dfom_lds_bytes(n, p, solver_blocks(di, n, engine)) > di.lds_max) return too_large(di, n, p, engine);
+    // compressed-row data reads x in place when asked, or when it does not fit in LDS
+    const bool x_global =
+        sparse && (opts->sparse_x == DUQ_SPX_IN_PLACE ||
+                   (opts->sparse_x == DUQ_SPX_AUTO && dfom_lds_bytes(n, p, solver_blocks(di, n, engine)) > di.lds_max));
+    if (dfom_lds_bytes(n, p, solver_blocks(di, n, engine), x_global) > di.lds_max)
+        return too_large(di, n, p, engine);
 
     duq_handle* h = new (std::nothrow) duq_handle();
     if (!h) return fail(DUQ_ENOMEM, "host allocation");
@@ -361,10 +406,15 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
             all_eq = all_eq && lo == hi;
         }
         h->rows = true;
-        h->eqform = all_eq && opts->rho > 0.0;
+        h->eqform = all_eq && opts->rho > 0.0 && !sparse;
     }
 
-    if (pr->memspace == DUQ_HOST) {
+    if (sparse) {
+        if ((rc = upload_sparse(h, pr, Qs, Gs, lb, ub, rlo, rhi))) {
+            duq_destroy(h);
+            return rc;
+        }
+    } else if (pr->memspace == DUQ_HOST) {
         bool ok = finite_all(pr->q, n) && (p == 0 || finite_all(pr->g, p));
         ok = ok && (dtype == DUQ_F64 ? finite_all_t((const double*)pr->Q, nn) : finite_all_t((const float*)pr->Q, nn));
         if (p > 0)
@@ -466,7 +516,8 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
         h->cfg.cooperative = true;
     }
     h->cfg.stream = h->stream;
-    h->cfg.shmem = dfom_lds_bytes(n, p, h->cfg.nblocks);
+    h->x_global = x_global;
+    h->cfg.shmem = dfom_lds_bytes(n, p, h->cfg.nblocks, x_global);
     if (h->cfg.shmem > di.lds_max) {   // checked before any data moved; kept as a guard
         duq_destroy(h);
         return too_large(di, n, p, engine);
@@ -474,7 +525,7 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
     if (h->cfg.cooperative) {
         for (int acc = 0; acc <= (dtype == DUQ_F32 ? 1 : 0); ++acc) {
             int bpc = 0;
-            if (dfom_occupancy(dtype, acc, n, h->cfg.nthreads, h->cfg.shmem, &bpc, h->rows) != hipSuccess ||
+            if (dfom_occupancy(dtype, acc, n, h->cfg.nthreads, h->cfg.shmem, &bpc, h->rows, sparse) != hipSuccess ||
                 bpc < 1) {
                 duq_destroy(h);
                 return fail(DUQ_EDEVICE, "cooperative launch does not fit one block per CU");
@@ -486,7 +537,7 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
     // workspace
     const int nb = h->cfg.nblocks;
     const int trace = opts->trace_outer;
-    auto carve = [&](Carve& c) { carve_solver(c, n, p, nb, trace, &h->W, &h->xstage, &h->lstage); };
+    auto carve = [&](Carve& c) { carve_solver(c, n, p, nb, trace, &h->W, &h->xstage, &h->lstage, sparse); };
     Carve c0;
     carve(c0);
     if (hipMalloc(&h->ws, c0.off) != hipSuccess) {
@@ -550,7 +601,118 @@ extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* s
     return DUQ_OK;
 }
 
+extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* stream, duq_handle** out) {
+    return setup_impl(pr, nullptr, nullptr, opts, stream, out);
+}
+
+extern "C" int duq_setup_csr(const duq_problem* pr, const duq_csr* Q, const duq_csr* G, const duq_options* opts,
+                             void* stream, duq_handle** out) {
+    if (!out) return fail(DUQ_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!pr || !opts) return fail(DUQ_EINVAL, "null problem or options");
+    if (pr->memspace != DUQ_HOST) return fail(DUQ_EINVAL, "compressed-row data is read from host memory (DUQ_HOST)");
+    if (pr->n <= 0 || pr->p < 0) return fail(DUQ_EINVAL, "n must be positive and p non-negative");
+    if (pr->dtype != DUQ_F64 && pr->dtype != DUQ_F32) return fail(DUQ_EINVAL, "dtype must be F64 or F32");
+    int rc = check_csr(Q, pr->n, pr->n, pr->dtype, "Q");
+    if (!rc && pr->p > 0) rc = check_csr(G, pr->p, pr->n, pr->dtype, "G");
+    if (rc) return rc;
+    return setup_impl(pr, Q, G, opts, stream, out);
+}
+
 namespace duq {
+
+// Copy compressed-row Q, G, the vectors and the row bounds to one device
+// allocation, and form G^T (a counting sort of the entries of G by column,
+// stable in the row index) so the transposed product gathers along rows.
+int upload_sparse(duq_handle* h, const duq_problem* pr, const duq_csr* Qs, const duq_csr* Gs,
+                  const std::vector<double>& lb, const std::vector<double>& ub, const std::vector<double>& rlo,
+                  const std::vector<double>& rhi) {
+    const int n = h->n, p = h->p;
+    const size_t es = esize(h->dtype);
+    const long long nq = Qs->rowptr[n];
+    const long long ng = p > 0 ? Gs->rowptr[p] : 0;
+    if (!finite_all(pr->q, n) || (p > 0 && !finite_all(pr->g, p))) return fail(DUQ_EINVAL, "non-finite problem data");
+    std::vector<long long> trp((size_t)n + 1, 0);
+    std::vector<int> tci((size_t)std::max<long long>(ng, 1));
+    std::vector<char> tv((size_t)std::max<long long>(ng, 1) * es);
+    for (long long k = 0; k < ng; ++k) ++trp[(size_t)Gs->col[k] + 1];
+    for (int j = 0; j < n; ++j) trp[j + 1] += trp[j];
+    {
+        std::vector<long long> pos(trp.begin(), trp.end() - 1);
+        const char* gv = (const char*)Gs->val;
+        for (int r = 0; r < p; ++r)
+            for (long long k = Gs->rowptr[r]; k < Gs->rowptr[r + 1]; ++k) {
+                const long long d = pos[Gs->col[k]]++;
+                tci[d] = r;
+                std::memcpy(tv.data() + d * es, gv + k * es, es);
+            }
+    }
+    auto layout = [&](Carve& c, SparseRefs* s, double** vec) {
+        s->Qrp = c.take<long long>((size_t)n + 1);
+        s->Qci = c.take<int>(std::max<long long>(nq, 1));
+        s->Qv = c.take<char>(std::max<long long>(nq, 1) * es);
+        s->Grp = c.take<long long>((size_t)p + 1);
+        s->Gci = c.take<int>(std::max<long long>(ng, 1));
+        s->Gv = c.take<char>(std::max<long long>(ng, 1) * es);
+        s->Trp = c.take<long long>((size_t)n + 1);
+        s->Tci = c.take<int>(std::max<long long>(ng, 1));
+        s->Tv = c.take<char>(std::max<long long>(ng, 1) * es);
+        vec[0] = c.take<double>(n);
+        vec[1] = c.take<double>(std::max(p, 1));
+        vec[2] = c.take<double>(n);
+        vec[3] = c.take<double>(n);
+        vec[4] = c.take<double>(std::max(p, 1));
+        vec[5] = c.take<double>(std::max(p, 1));
+    };
+    SparseRefs sp{};
+    double* vec[6];
+    Carve c0;
+    layout(c0, &sp, vec);
+    if (hipMalloc(&h->owned_data, c0.off) != hipSuccess)
+        return fail(DUQ_ENOMEM, "device allocation of sparse problem data (" + std::to_string(c0.off) + " bytes)");
+    Carve c1;
+    c1.base = (char*)h->owned_data;
+    layout(c1, &sp, vec);
+    hipError_t e = hipSuccess;
+    auto put = [&](const void* dst, const void* src, size_t bytes) {
+        if (bytes && e == hipSuccess) e = hipMemcpy(const_cast<void*>(dst), src, bytes, hipMemcpyHostToDevice);
+    };
+    std::vector<long long> zeros((size_t)p + 1, 0);
+    put(sp.Qrp, Qs->rowptr, ((size_t)n + 1) * sizeof(long long));
+    put(sp.Qci, Qs->col, (size_t)nq * sizeof(int));
+    put(sp.Qv, Qs->val, (size_t)nq * es);
+    put(sp.Grp, p > 0 ? (const void*)Gs->rowptr : (const void*)zeros.data(), ((size_t)p + 1) * sizeof(long long));
+    if (p > 0) {
+        put(sp.Gci, Gs->col, (size_t)ng * sizeof(int));
+        put(sp.Gv, Gs->val, (size_t)ng * es);
+    }
+    put(sp.Trp, trp.data(), trp.size() * sizeof(long long));
+    put(sp.Tci, tci.data(), (size_t)ng * sizeof(int));
+    put(sp.Tv, tv.data(), (size_t)ng * es);
+    put(vec[0], pr->q, (size_t)n * sizeof(double));
+    if (p > 0) put(vec[1], pr->g, (size_t)p * sizeof(double));
+    put(vec[2], lb.data(), (size_t)n * sizeof(double));
+    put(vec[3], ub.data(), (size_t)n * sizeof(double));
+    if (h->rows && p > 0) {
+        put(vec[4], rlo.data(), (size_t)p * sizeof(double));
+        put(vec[5], rhi.data(), (size_t)p * sizeof(double));
+    }
+    if (e != hipSuccess)
+        return fail(DUQ_EDEVICE, std::string("copy of sparse problem data: ") + hipGetErrorString(e));
+    h->sparse = true;
+    h->sp = sp;
+    h->nnzQ = nq;
+    h->nnzG = ng;
+    h->dq = vec[0];
+    h->dg = vec[1];
+    h->dlb = vec[2];
+    h->dub = vec[3];
+    if (h->rows) {
+        h->drlo = vec[4];
+        h->drhi = vec[5];
+    }
+    return DUQ_OK;
+}
 
 int estimate_constants(duq_handle* h, const DeviceInfo& di) {
     const int n = h->n, p = h->p;
@@ -564,10 +726,11 @@ int estimate_constants(duq_handle* h, const DeviceInfo& di) {
         L.w = c.take<double>(n);
         L.r = c.take<double>(std::max(p, 1));
         L.part = c.take<double>((size_t)nb * (k + 2));
-        L.gtp = c.take<double>(nb > 1 ? (size_t)nb * n : 1);
+        L.gtp = c.take<double>(nb > 1 && !h->sparse ? (size_t)nb * n : 1);
         L.ab = c.take<double>(2 * (size_t)k + 2);
         L.out = c.take<double>(4);
         L.bar = c.take<unsigned>(bar_words(nb));
+        L.rsh = c.take<double>(std::max(p, 1));
     };
     carve(c0);
     void* buf = nullptr;
@@ -575,13 +738,15 @@ int estimate_constants(duq_handle* h, const DeviceInfo& di) {
     Carve c1;
     c1.base = (char*)buf;
     carve(c1);
+    L.x_global = h->x_global ? 1 : 0;
     LaunchCfg cfg = h->cfg;
-    cfg.shmem = lanczos_lds_bytes(n, p, nb, k);
+    cfg.shmem = lanczos_lds_bytes(n, p, nb, k, h->x_global);
     if (cfg.shmem > di.lds_max) {
         (void)hipFree(buf);
         return fail(DUQ_EINVAL, "problem too large for the Lanczos estimate; pass the constants");
     }
     GenericProblem gp{n, p, h->dQ, h->dG, h->dq, h->dg, h->dlb, h->dub, h->drlo, h->drhi};
+    gp.sp = h->sp;
     double outQ[4] = {0, 0, 0, 0}, outG[4] = {0, 0, 0, 0}, outH[4] = {0, 0, 0, 0};
     unsigned flag = 0;
     auto run = [&](int use_gtg, double* out, const void* Qop) -> int {
@@ -666,7 +831,9 @@ extern "C" int duq_solve(duq_handle* h, const double* x0, const double* lam0, do
     par.sigma = h->sigma;
     par.beta_in = h->beta_in;
     par.eqform = h->eqform ? 1 : 0;
+    par.x_global = h->x_global ? 1 : 0;
     GenericProblem gp{n, p, h->eqform ? h->dH : h->dQ, h->dG, h->dq, h->dg, h->dlb, h->dub, h->drlo, h->drhi};
+    gp.sp = h->sp;
     DevState st;
     unsigned bar_err = 0;
     int k_phase1 = 0;
@@ -761,6 +928,7 @@ int handle_slice(duq_handle* h, bool first, int slice, int k_done, DevState* st_
     par.sigma = h->sigma;
     par.beta_in = h->beta_in;
     GenericProblem gp{h->n, h->p, h->dQ, h->dG, h->dq, h->dg, h->dlb, h->dub};
+    gp.sp = h->sp;
     HIP_TRY(launch_dfom(h->dtype, DUQ_ACC_F64, h->cfg, gp, par, h->W));
     HIP_TRY(hipMemcpyAsync(st_host, h->W.st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
     return DUQ_OK;

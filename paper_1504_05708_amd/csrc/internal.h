@@ -37,6 +37,30 @@ struct DevProblem {
     // G u + g <= 0.  rlo = rhi: an equality; +-inf: an absent side.
     const double* rlo = nullptr;
     const double* rhi = nullptr;
+    // Sparse Q and G (compressed rows; Qrp null for dense data): Q (n rows),
+    // G (p rows) and G^T (n rows, for the transposed product).
+    const long long* Qrp = nullptr;
+    const int* Qci = nullptr;
+    const T* Qv = nullptr;
+    const long long* Grp = nullptr;
+    const int* Gci = nullptr;
+    const T* Gv = nullptr;
+    const long long* Trp = nullptr;
+    const int* Tci = nullptr;
+    const T* Tv = nullptr;
+};
+
+// Type-erased compressed-row arrays of a sparse problem (host runtime).
+struct SparseRefs {
+    const long long* Qrp = nullptr;
+    const int* Qci = nullptr;
+    const void* Qv = nullptr;
+    const long long* Grp = nullptr;
+    const int* Gci = nullptr;
+    const void* Gv = nullptr;
+    const long long* Trp = nullptr;
+    const int* Tci = nullptr;
+    const void* Tv = nullptr;
 };
 
 // Per-solve parameters derived on the host from the options and constants.
@@ -58,6 +82,7 @@ struct DevParams {
     int stall_iters;   // phase 1 ends after this many iterations without progress
     int eqform;        // every row an equality and rho > 0: Q holds Q + rho G^T G
                        // (Sec. 5.1), the inner loop is the rho = 0 one
+    int x_global;      // sparse data: x read in place from its buffer, not staged in LDS
     double eps_out;    // outer tolerance used by this launch
     double eps_in;
     double rho;
@@ -105,6 +130,8 @@ struct DevWork {
     double* lamm;      // row bounds: multipliers of the lower sides (lambda-)
     double* mum;       //   and their extrapolation (mu-)
     double* nu;        // row bounds: returned multiplier per row, lambda+ - lambda-
+    double* wsh;       // sparse G on a grid team: the weights of G^T w, written
+                       // by their owners and read by every workgroup
     double* wv;        // rho > 0: [mu + rho (G y + g)]_+
     double* gsave;     // rho > 0: G ubar^k kept across the extra DFGM-last solve
     double* gx[3];     // rho > 0: G x for the rotating iterates
@@ -156,6 +183,8 @@ struct LanczosWork {
     double* ab;      // alpha[0..k), beta[0..k]
     double* out;     // [theta_min, theta_max, steps]
     unsigned* bar;
+    double* rsh = nullptr;   // sparse G on a grid team: G v shared by every workgroup
+    int x_global = 0;        // sparse data: Krylov vectors read in place, not staged in LDS
 };
 
 }  // namespace duq

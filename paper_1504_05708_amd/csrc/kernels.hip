@@ -20,10 +20,10 @@ static size_t lanczos_lds_doubles(int n, int p, int nblocks, int k) {
     return (size_t)n + (size_t)pmax + (size_t)(k + 2) + (size_t)kMaxWaves * 2 + 2 + kTlDoubles;
 }
 
-template <typename T, typename Acc, bool SHORT, bool ROWS>
+template <typename T, typename Acc, bool SHORT, bool ROWS, bool SPARSE = false>
 __global__ void __launch_bounds__(512) dfom_kernel(DevProblem<T> P, DevParams par, DevWork W) {
     extern __shared__ __align__(16) double lds[];
-    Dfom<T, Acc, SHORT, ROWS> s;
+    Dfom<T, Acc, SHORT, ROWS, SPARSE> s;
     s.P = P;
     s.par = par;
     s.W = W;
@@ -34,17 +34,19 @@ __global__ void __launch_bounds__(512) dfom_kernel(DevProblem<T> P, DevParams pa
     share(P.n, blockIdx.x, gridDim.x, s.nlo, s.nhi);
     share(P.p, blockIdx.x, gridDim.x, s.plo, s.phi);
     const int pmax = (P.p + gridDim.x - 1) / gridDim.x + 1;
+    const int xn = (SPARSE && par.x_global) ? 0 : P.n;   // x read in place: no LDS copy
     s.xl = lds;
-    s.vl = lds + P.n;
-    s.red = lds + P.n + pmax;
+    s.xsrc = nullptr;
+    s.vl = lds + xn;
+    s.red = lds + xn + pmax;
     s.tl = s.red + kMaxWaves * kNP + 2;
     s.run();
 }
 
-template <typename T, bool SHORT>
+template <typename T, bool SHORT, bool SPARSE = false>
 __global__ void __launch_bounds__(512) lanczos_kernel(DevProblem<T> P, LanczosWork L, int k, int use_gtg) {
     extern __shared__ __align__(16) double lds[];
-    Lanczos<T, SHORT> s;
+    Lanczos<T, SHORT, SPARSE> s;
     s.P = P;
     s.L = L;
     s.k = k;
@@ -56,9 +58,10 @@ __global__ void __launch_bounds__(512) lanczos_kernel(DevProblem<T> P, LanczosWo
     share(P.n, blockIdx.x, gridDim.x, s.nlo, s.nhi);
     share(P.p, blockIdx.x, gridDim.x, s.plo, s.phi);
     const int pmax = (P.p + gridDim.x - 1) / gridDim.x + 1;
+    const int xn = (SPARSE && L.x_global) ? 0 : P.n;
     s.xl = lds;
-    s.vl = lds + P.n;
-    s.hl = lds + P.n + pmax;
+    s.vl = lds + xn;
+    s.hl = lds + xn + pmax;
     s.red = s.hl + (k + 2);
     s.tl = s.red + kMaxWaves * 2 + 2;
     s.run();
@@ -139,9 +142,12 @@ hipError_t launch_form_hessian(int dtype, int n, int p, const void* Q, const voi
     return hipGetLastError();
 }
 
-size_t dfom_lds_bytes(int n, int p, int nblocks) { return solver_lds_doubles(n, p, nblocks) * sizeof(double); }
-size_t lanczos_lds_bytes(int n, int p, int nblocks, int k) {
-    return lanczos_lds_doubles(n, p, nblocks, k) * sizeof(double);
+// x_global: sparse data whose x is read in place (no n-vector in LDS).
+size_t dfom_lds_bytes(int n, int p, int nblocks, bool x_global) {
+    return solver_lds_doubles(x_global ? 0 : n, p, nblocks) * sizeof(double);
+}
+size_t lanczos_lds_bytes(int n, int p, int nblocks, int k, bool x_global) {
+    return lanczos_lds_doubles(x_global ? 0 : n, p, nblocks, k) * sizeof(double);
 }
 
 template <bool SHORT>
@@ -155,7 +161,19 @@ static const void* dfom_fn_t(int dtype, int acc, bool rows = false) {
     return reinterpret_cast<const void*>(&dfom_kernel<float, float, SHORT, false>);
 }
 
-static const void* dfom_fn(int dtype, int acc, int n, bool rows = false) {
+// Compressed-row Q and G: one variant per storage type, row form and
+// accumulation (the row length does not select a product shape).
+static const void* dfom_fn_sparse(int dtype, int acc, bool rows) {
+    if (rows)
+        return dtype == 0 ? reinterpret_cast<const void*>(&dfom_kernel<double, double, false, true, true>)
+                          : reinterpret_cast<const void*>(&dfom_kernel<float, double, false, true, true>);
+    if (dtype == 0) return reinterpret_cast<const void*>(&dfom_kernel<double, double, false, false, true>);
+    if (acc == 0) return reinterpret_cast<const void*>(&dfom_kernel<float, double, false, false, true>);
+    return reinterpret_cast<const void*>(&dfom_kernel<float, float, false, false, true>);
+}
+
+static const void* dfom_fn(int dtype, int acc, int n, bool rows = false, bool sparse = false) {
+    if (sparse) return dfom_fn_sparse(dtype, acc, rows);
     const bool sh = dtype == 0 ? short_rows<double>(n) : short_rows<float>(n);
     return sh ? dfom_fn_t<true>(dtype, acc, rows) : dfom_fn_t<false>(dtype, acc, rows);
 }
@@ -169,7 +187,11 @@ size_t dfom_static_lds_bytes() {
                              reinterpret_cast<const void*>(&lanczos_kernel<double, true>),
                              reinterpret_cast<const void*>(&lanczos_kernel<double, false>),
                              reinterpret_cast<const void*>(&lanczos_kernel<float, true>),
-                             reinterpret_cast<const void*>(&lanczos_kernel<float, false>)};
+                             reinterpret_cast<const void*>(&lanczos_kernel<float, false>),
+                             dfom_fn_sparse(0, 0, false), dfom_fn_sparse(1, 0, false), dfom_fn_sparse(1, 1, false),
+                             dfom_fn_sparse(0, 0, true), dfom_fn_sparse(1, 0, true),
+                             reinterpret_cast<const void*>(&lanczos_kernel<double, false, true>),
+                             reinterpret_cast<const void*>(&lanczos_kernel<float, false, true>)};
         size_t m = 0;
         for (const void* f : fns) {
             hipFuncAttributes a;
@@ -181,11 +203,25 @@ size_t dfom_static_lds_bytes() {
     return bytes;
 }
 
-hipError_t dfom_occupancy(int dtype, int acc, int n, int nthreads, size_t shmem, int* blocks_per_cu, bool rows) {
-    const void* f = dfom_fn(dtype, acc, n, rows);
+hipError_t dfom_occupancy(int dtype, int acc, int n, int nthreads, size_t shmem, int* blocks_per_cu, bool rows,
+                          bool sparse) {
+    const void* f = dfom_fn(dtype, acc, n, rows, sparse);
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, nthreads, shmem);
+}
+
+template <typename T>
+static void set_sparse(DevProblem<T>& P, const SparseRefs& s) {
+    P.Qrp = s.Qrp;
+    P.Qci = s.Qci;
+    P.Qv = static_cast<const T*>(s.Qv);
+    P.Grp = s.Grp;
+    P.Gci = s.Gci;
+    P.Gv = static_cast<const T*>(s.Gv);
+    P.Trp = s.Trp;
+    P.Tci = s.Tci;
+    P.Tv = static_cast<const T*>(s.Tv);
 }
 
 hipError_t launch_dfom(int dtype, int acc, const LaunchCfg& cfg, const GenericProblem& gp,
@@ -193,15 +229,17 @@ hipError_t launch_dfom(int dtype, int acc, const LaunchCfg& cfg, const GenericPr
     DevParams pr = par;
     DevWork w = W;
     const bool rows = gp.rlo != nullptr;
-    const void* f = dfom_fn(dtype, acc, gp.n, rows);
+    const void* f = dfom_fn(dtype, acc, gp.n, rows, gp.sp.Qrp != nullptr);
     if (dtype == 0) {
         DevProblem<double> P{gp.n, gp.p, (const double*)gp.Q, (const double*)gp.G, gp.q, gp.g, gp.lb, gp.ub,
                              gp.rlo, gp.rhi};
+        set_sparse(P, gp.sp);
         void* args[] = {&P, &pr, &w};
         return launch_fn(f, cfg, args);
     }
     DevProblem<float> P{gp.n, gp.p, (const float*)gp.Q, (const float*)gp.G, gp.q, gp.g, gp.lb, gp.ub,
                         gp.rlo, gp.rhi};
+    set_sparse(P, gp.sp);
     void* args[] = {&P, &pr, &w};
     return launch_fn(f, cfg, args);
 }
@@ -213,16 +251,20 @@ hipError_t launch_lanczos(int dtype, const LaunchCfg& cfg, const GenericProblem&
     if (dtype == 0) {
         DevProblem<double> P{gp.n, gp.p, (const double*)gp.Q, (const double*)gp.G, gp.q, gp.g, gp.lb, gp.ub,
                              gp.rlo, gp.rhi};
+        set_sparse(P, gp.sp);
         void* args[] = {&P, &l, &kk, &ug};
-        const void* f = short_rows<double>(gp.n) ? reinterpret_cast<const void*>(&lanczos_kernel<double, true>)
-                                                 : reinterpret_cast<const void*>(&lanczos_kernel<double, false>);
+        const void* f = gp.sp.Qrp ? reinterpret_cast<const void*>(&lanczos_kernel<double, false, true>)
+                        : short_rows<double>(gp.n) ? reinterpret_cast<const void*>(&lanczos_kernel<double, true>)
+                                                   : reinterpret_cast<const void*>(&lanczos_kernel<double, false>);
         return launch_fn(f, cfg, args);
     }
     DevProblem<float> P{gp.n, gp.p, (const float*)gp.Q, (const float*)gp.G, gp.q, gp.g, gp.lb, gp.ub,
                         gp.rlo, gp.rhi};
+    set_sparse(P, gp.sp);
     void* args[] = {&P, &l, &kk, &ug};
-    const void* f = short_rows<float>(gp.n) ? reinterpret_cast<const void*>(&lanczos_kernel<float, true>)
-                                            : reinterpret_cast<const void*>(&lanczos_kernel<float, false>);
+    const void* f = gp.sp.Qrp ? reinterpret_cast<const void*>(&lanczos_kernel<float, false, true>)
+                    : short_rows<float>(gp.n) ? reinterpret_cast<const void*>(&lanczos_kernel<float, true>)
+                                              : reinterpret_cast<const void*>(&lanczos_kernel<float, false>);
     return launch_fn(f, cfg, args);
 }
 

@@ -44,7 +44,7 @@ __device__ __forceinline__ void xsum_strided_cols(const double* base, long strid
     }
 }
 
-template <typename T, bool SHORT>
+template <typename T, bool SHORT, bool SPARSE = false>
 struct Lanczos {
     DevProblem<T> P;
     LanczosWork L;
@@ -129,6 +129,12 @@ struct Lanczos {
 
     __device__ __forceinline__ bool apply(const double* v, double* w) {
         const int n = P.n;
+        if constexpr (SPARSE) {
+            if (L.x_global) __syncthreads();   // v read in place (device-scope on a grid team)
+            else if (tm.size > 1) stage_shared(v, n, xl);
+            else stage(v, n, xl);
+            return apply_sparse(v, w);
+        }
         if (tm.size > 1) stage_shared(v, n, xl); else stage(v, n, xl);
         if (!use_gtg) {
             if (tm.size > 1) gemv_rows<T, double, 16, true, SHORT>(P.Q, n, nlo, nhi, n, xl, w, nullptr);
@@ -170,6 +176,43 @@ struct Lanczos {
                     if (lane == 0) w[j0 + c * nw] = t;
                 }
             }
+        }
+        __syncthreads();
+        return true;
+    }
+
+    // Compressed-row Q, G: w = Q v, or w = G^T W (G v) gathered along the rows
+    // of G^T (v staged in xl, or read in place when it does not fit).
+    __device__ __forceinline__ void sp_rows(const long long* rp, const int* ci, const T* val, int lo, int hi,
+                                            const double* v, double* out) const {
+        if (!L.x_global) spmv_rows<T, double>(rp, ci, val, lo, hi, [&](int j) { return xl[j]; }, out, nullptr);
+        else if (tm.size > 1) spmv_rows<T, double>(rp, ci, val, lo, hi, [&](int j) { return xload(v + j); }, out, nullptr);
+        else spmv_rows<T, double>(rp, ci, val, lo, hi, [&](int j) { return v[j]; }, out, nullptr);
+    }
+    __device__ __forceinline__ bool apply_sparse(const double* v, double* w) {
+        if (!use_gtg) {
+            sp_rows(P.Qrp, P.Qci, P.Qv, nlo, nhi, v, w);
+            __syncthreads();
+            return true;
+        }
+        sp_rows(P.Grp, P.Gci, P.Gv, plo, phi, v, L.r);
+        __syncthreads();
+        auto weight = [&](int i) {
+            double r = L.r[i];
+            if (P.rlo) {
+                const RowSides sd = row_sides(P.rlo, P.rhi, i);
+                r *= (sd.up ? 1.0 : 0.0) + (sd.dn ? 1.0 : 0.0);
+            }
+            return r;
+        };
+        if (tm.size == 1) {
+            for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) vl[i - plo] = weight(i);
+            __syncthreads();
+            spmvT_cols<T>(P.Trp, P.Tci, P.Tv, nlo, nhi, [&](int k) { return vl[k - plo]; }, nullptr, w);
+        } else {
+            for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) xstore(L.rsh + i, weight(i));
+            if (tm.sync()) return false;
+            spmvT_cols<T>(P.Trp, P.Tci, P.Tv, nlo, nhi, [&](int k) { return xload(L.rsh + k); }, nullptr, w);
         }
         __syncthreads();
         return true;

@@ -28,6 +28,7 @@ struct GenericProblem {
     const double* ub;
     const double* rlo = nullptr;   // row bounds (both or neither)
     const double* rhi = nullptr;
+    SparseRefs sp;                 // compressed-row Q, G, G^T (sp.Qrp null: dense)
 };
 
 struct LanczosWork;
@@ -114,13 +115,13 @@ size_t tile_lds_bytes(int n);
 hipError_t tile_occupancy(int dtype, size_t shmem, int* blocks_per_cu);
 hipError_t launch_tile(int dtype, int nblocks, size_t shmem, hipStream_t stream, const TileLaunch& t);
 
-size_t dfom_lds_bytes(int n, int p, int nblocks);
+size_t dfom_lds_bytes(int n, int p, int nblocks, bool x_global = false);
 // Static LDS of the solver and Lanczos kernels (largest instantiation); the
 // dynamic LDS of a launch may use what is left of the workgroup's LDS.
 size_t dfom_static_lds_bytes();
-size_t lanczos_lds_bytes(int n, int p, int nblocks, int k);
+size_t lanczos_lds_bytes(int n, int p, int nblocks, int k, bool x_global = false);
 hipError_t dfom_occupancy(int dtype, int acc, int n, int nthreads, size_t shmem, int* blocks_per_cu,
-                          bool rows = false);
+                          bool rows = false, bool sparse = false);
 hipError_t launch_dfom(int dtype, int acc, const LaunchCfg& cfg, const GenericProblem& gp,
                        const DevParams& par, const DevWork& W);
 hipError_t launch_lanczos(int dtype, const LaunchCfg& cfg, const GenericProblem& gp, const LanczosWork& L,

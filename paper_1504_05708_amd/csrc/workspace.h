@@ -25,9 +25,10 @@ struct Carve {
 
 // Vectors, partial sums, barrier words and trace of one solve on `nb`
 // workgroups (n variables, p rows, `trace` recorded outer iterations), plus
-// two staging vectors for the warm start.
+// two staging vectors for the warm start.  Compressed-row data (`sparse`)
+// gathers G^T w along rows and needs no per-workgroup partial columns.
 inline void carve_solver(Carve& c, int n, int p, int nb, int trace, DevWork* W, double** xstage,
-                         double** lstage) {
+                         double** lstage, bool sparse = false) {
     for (int i = 0; i < 3; ++i) W->xb[i] = c.take<double>(n);
     for (int i = 0; i < 3; ++i) W->qb[i] = c.take<double>(n);
     W->c = c.take<double>(n);
@@ -47,8 +48,9 @@ inline void carve_solver(Carve& c, int n, int p, int nb, int trace, DevWork* W, 
     W->lamm = c.take<double>(pp);
     W->mum = c.take<double>(pp);
     W->nu = c.take<double>(pp);
+    W->wsh = c.take<double>(pp);
     W->part = c.take<double>((size_t)2 * nb * kNP);
-    W->gtp = c.take<double>(nb > 1 ? (size_t)nb * n : 1);
+    W->gtp = c.take<double>(nb > 1 && !sparse ? (size_t)nb * n : 1);
     // a record holds lambda+, mu+, ubar and, with row bounds, lambda-, mu-
     W->trace = c.take<double>(trace > 0 ? (size_t)trace * (kTraceScalars + 4 * p + n) : 1);
     W->st = c.take<DevState>(1);

@@ -30,6 +30,7 @@ CERT, FIXED = 0, 1
 INNER_AUTO, INNER_GM, INNER_FGM, INNER_FGM_SIGMA = 0, 1, 2, 3
 ACC_F64, ACC_F32 = 0, 1
 ENGINE_AUTO, ENGINE_BLOCK, ENGINE_GRID, ENGINE_TILE = 0, 1, 2, 3
+SPX_AUTO, SPX_LDS, SPX_IN_PLACE = 0, 1, 2
 TRACE_SCALARS = 16
 
 BATCH_UNEVEN, BATCH_SHARED = 0, 1
@@ -39,7 +40,8 @@ SERVE_BATCH_NMAX = 1536
 EXPORTS = ["duq_default_options", "duq_setup", "duq_max_n", "duq_solve", "duq_get_trace", "duq_get_constants",
            "duq_destroy", "duq_last_error", "duq_strerror", "duq_solve_batch", "duq_server_create",
            "duq_register_shared", "duq_submit", "duq_poll", "duq_server_destroy", "duq_solve_static",
-           "duq_plan_params", "duq_solve_planned", "duq_tune_batch", "duq_tune_save", "duq_tune_load"]
+           "duq_plan_params", "duq_solve_planned", "duq_tune_batch", "duq_tune_save", "duq_tune_load",
+           "duq_setup_csr"]
 STATIC_SCRATCH_BYTES = 64 << 20
 
 
@@ -47,6 +49,10 @@ class DuqProblem(Structure):
     _fields_ = [("n", c_int32), ("p", c_int32), ("dtype", c_int32), ("memspace", c_int32),
                 ("Q", c_void_p), ("G", c_void_p), ("q", c_void_p), ("g", c_void_p),
                 ("lb", c_void_p), ("ub", c_void_p), ("rlo", c_void_p), ("rhi", c_void_p)]
+
+
+class DuqCsr(Structure):
+    _fields_ = [("rows", c_int32), ("cols", c_int32), ("rowptr", c_void_p), ("col", c_void_p), ("val", c_void_p)]
 
 
 class DuqOptions(Structure):
@@ -57,7 +63,7 @@ class DuqOptions(Structure):
                 ("rho", c_double), ("lam_min", c_double), ("lam_max", c_double),
                 ("G_norm2", c_double), ("safety", c_double), ("switch_factor", c_double),
                 ("switch_stall", c_int32), ("serve_slice", c_int32), ("out_memspace", c_int32),
-                ("batch_wpc", c_int32), ("sigma_in", c_double), ("reserved", c_int32 * 2)]
+                ("batch_wpc", c_int32), ("sigma_in", c_double), ("sparse_x", c_int32), ("reserved", c_int32 * 1)]
 
 
 class DuqResult(Structure):
@@ -126,6 +132,9 @@ def lib() -> ctypes.CDLL:
     L.duq_default_options.restype = None
     L.duq_setup.argtypes = [POINTER(DuqProblem), POINTER(DuqOptions), c_void_p, POINTER(c_void_p)]
     L.duq_setup.restype = c_int32
+    L.duq_setup_csr.argtypes = [POINTER(DuqProblem), POINTER(DuqCsr), POINTER(DuqCsr), POINTER(DuqOptions), c_void_p,
+                                POINTER(c_void_p)]
+    L.duq_setup_csr.restype = c_int32
     L.duq_solve.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(DuqResult)]
     L.duq_solve.restype = c_int32
     L.duq_max_n.argtypes = [c_int32, c_int32, POINTER(c_int32)]
@@ -212,16 +221,37 @@ def _stream_of(t):
     return c_void_p(None)
 
 
+def _csr_parts(M, dtype=None):
+    """(rows, cols, row offsets int64, column indices int32, values) of a
+    compressed-row matrix: an object with rowptr/col/val/rows/cols, or one
+    with indptr/indices/data/shape (scipy's CSR layout)."""
+    if hasattr(M, "rowptr"):
+        rows, cols, rp, ci, v = M.rows, M.cols, M.rowptr, M.col, M.val
+    else:
+        (rows, cols), rp, ci, v = M.shape, M.indptr, M.indices, M.data
+    v = np.ascontiguousarray(v, dtype=dtype if dtype is not None else v.dtype)
+    return (int(rows), int(cols), np.ascontiguousarray(rp, dtype=np.int64), np.ascontiguousarray(ci, dtype=np.int32), v)
+
+
+def _is_csr(M) -> bool:
+    return hasattr(M, "rowptr") or hasattr(M, "indptr")
+
+
 class Solver:
     """One QP set up on the device (duq_setup) and solved with duq_solve.
 
     Q, G: NumPy float64/float32 arrays (copied) or torch tensors on the GPU
-    (borrowed: they must outlive the solver).  q, g, lb, ub: float64 of the
-    same kind.  rlo, rhi (optional, both or neither): row bounds
-    rlo <= G u + g <= rhi (equality where rlo = rhi, +-inf for no side)."""
+    (borrowed: they must outlive the solver), or both compressed-row matrices
+    on the host (duq_setup_csr; see _csr_parts for the accepted forms).
+    q, g, lb, ub: float64 of the same kind.  rlo, rhi (optional, both or
+    neither): row bounds rlo <= G u + g <= rhi (equality where rlo = rhi,
+    +-inf for no side)."""
 
     def __init__(self, Q, q, G, g, lb, ub, rlo=None, rhi=None, **opts):
         self._keep = []
+        if _is_csr(Q):
+            self._setup_csr(Q, q, G, g, lb, ub, rlo, rhi, opts)
+            return
         dev = hasattr(Q, "data_ptr")
         if dev:
             import torch
@@ -252,6 +282,34 @@ class Solver:
         self._h = h
         if not dev:
             self._keep = []   # host data was copied
+
+    def _setup_csr(self, Q, q, G, g, lb, ub, rlo, rhi, opts):
+        nq, qcols, qrp, qci, qv = _csr_parts(Q)
+        if qv.dtype not in (np.float64, np.float32):
+            qv = qv.astype(np.float64)
+        dt = F64 if qv.dtype == np.float64 else F32
+        cg = None
+        p = 0
+        if G is not None:
+            p, gcols, grp, gci, gv = _csr_parts(G, qv.dtype)
+            cg = DuqCsr(p, gcols, _ptr(grp), _ptr(gci), _ptr(gv))
+        g = np.zeros(0) if g is None else g
+        q, g, lb, ub = (np.ascontiguousarray(v, dtype=np.float64) for v in (q, g, lb, ub))
+        if rlo is not None:
+            rlo, rhi = (np.ascontiguousarray(v, dtype=np.float64) for v in (rlo, rhi))
+        self.n, self.p = nq, p
+        self.rows = rlo is not None
+        cq = DuqCsr(nq, qcols, _ptr(qrp), _ptr(qci), _ptr(qv))
+        prob = DuqProblem(nq, p, dt, HOST, None, None, _ptr(q), _ptr(g) if p else None, _ptr(lb), _ptr(ub),
+                          _ptr(rlo), _ptr(rhi))
+        self.opts = default_options(**opts)
+        h = c_void_p()
+        rc = lib().duq_setup_csr(ctypes.byref(prob), ctypes.byref(cq), ctypes.byref(cg) if cg is not None else None,
+                                 ctypes.byref(self.opts),
+                                 c_void_p(None), ctypes.byref(h))
+        if rc != DUQ_OK:
+            raise DuqError(rc, last_error())
+        self._h = h
 
     def solve(self, x0=None, lam0=None, check=True):
         x = np.empty(self.n)

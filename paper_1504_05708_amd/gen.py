@@ -199,6 +199,118 @@ def random_rows_qp(n: int, p: int, seed=0, reg: float = 0.1) -> QP:
     return QP(Q, q, G, g, -np.ones(n), np.ones(n), dict(kind="rows", seed=seed), rlo, rhi)
 
 
+@dataclass
+class CSR:
+    """A matrix in compressed sparse row form (row pointers int64, column
+    indices int32 in ascending order within each row, values)."""
+    rows: int
+    cols: int
+    rowptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowptr[-1])
+
+    def dense(self) -> np.ndarray:
+        """The dense matrix; a repeated index in a row adds its values."""
+        M = np.zeros((self.rows, self.cols), dtype=np.float64)
+        rows = np.repeat(np.arange(self.rows), np.diff(self.rowptr))
+        np.add.at(M, (rows, self.col), self.val.astype(np.float64))
+        return M
+
+
+def to_csr(M: np.ndarray, dtype=np.float64) -> CSR:
+    """The nonzero entries of a dense matrix, row by row."""
+    rows, cols = M.shape
+    nzr, nzc = np.nonzero(M)
+    rowptr = np.zeros(rows + 1, np.int64)
+    np.add.at(rowptr, nzr + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    return CSR(rows, cols, rowptr, nzc.astype(np.int32), M[nzr, nzc].astype(dtype))
+
+
+@dataclass
+class SparseQP:
+    """A QP with compressed-row Q (n x n) and G (p x n); the vectors as in QP."""
+    Q: CSR
+    q: np.ndarray
+    G: CSR
+    g: np.ndarray
+    lb: np.ndarray
+    ub: np.ndarray
+    meta: dict
+
+    @property
+    def n(self) -> int:
+        return self.Q.rows
+
+    @property
+    def p(self) -> int:
+        return self.G.rows
+
+    def dense(self) -> QP:
+        return QP(self.Q.dense(), self.q, self.G.dense(), self.g, self.lb, self.ub, dict(self.meta))
+
+
+def _routes(rng, n: int, p: int, k: int) -> np.ndarray:
+    """n rows of k distinct link ids in [0, p): redraw the rows that repeat."""
+    R = rng.integers(0, p, size=(n, k))
+    while True:
+        S = np.sort(R, axis=1)
+        bad = (np.diff(S, axis=1) == 0).any(axis=1) if k > 1 else np.zeros(n, bool)
+        if not bad.any():
+            return S
+        R = S
+        R[bad] = rng.integers(0, p, size=(int(bad.sum()), k))
+
+
+def sparse_num_qp(n: int, p: int, seed=0, path_len: int = 8, band: int = 2, cap_slack: float = 0.3) -> SparseQP:
+    """A sparse QP shaped like network utility maximisation (the sparse
+    application Sec. 2 and Sec. 5.1 name): n flows with rates u in [0, 1], p
+    links; G (p x n) is the 0/1 routing matrix, each flow crossing `path_len`
+    distinct random links; G u <= c with c = G x0 + slack (x0 ~ U(0.2, 0.6),
+    slack ~ U(0, cap_slack)), written as G u + g <= 0 with g = -c.  The
+    objective is a concave quadratic utility to maximise, i.e. F = 1/2 u^T Q u
+    + q^T u with Q = diag(d) + a symmetric band coupling neighbouring flows
+    (d ~ U(1, 2), off-diagonals ~ U(-0.1, 0.1) within `band`, Q > 0 by
+    diagonal dominance) and q ~ -U(0.5, 1.5).  Draw order: routes (rows of
+    link ids, redrawn where a flow repeats a link), x0, slack, d, the
+    off-diagonals of distance 1..band, q.  Built in compressed-row form
+    without dense matrices, so it serves sizes far beyond dense memory."""
+    if path_len > p:
+        raise ValueError("path_len must not exceed p")
+    rng = _rng(seed)
+    R = _routes(rng, n, p, path_len)
+    x0 = rng.uniform(0.2, 0.6, n)
+    slack = rng.uniform(0.0, cap_slack, p)
+    d = rng.uniform(1.0, 2.0, n)
+    offs = [rng.uniform(-0.1, 0.1, n - k) if n > k else np.zeros(0) for k in range(1, band + 1)]
+    q = -rng.uniform(0.5, 1.5, n)
+    # G: entry (link, flow) = 1, rows ordered by link, flows ascending inside
+    links = R.ravel()
+    flows = np.repeat(np.arange(n, dtype=np.int64), path_len)
+    order = np.lexsort((flows, links))
+    grp = np.zeros(p + 1, np.int64)
+    np.add.at(grp, links + 1, 1)
+    G = CSR(p, n, np.cumsum(grp), flows[order].astype(np.int32), np.ones(links.size))
+    g = -(np.bincount(links, weights=x0[flows], minlength=p) + slack)
+    # Q: band rows, columns ascending
+    rows, cols, vals = [np.arange(n)], [np.arange(n)], [d]
+    for k, off in enumerate(offs, start=1):
+        i = np.arange(n - k)
+        rows += [i, i + k]
+        cols += [i + k, i]
+        vals += [off, off]
+    r, c, v = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    o = np.lexsort((c, r))
+    qrp = np.zeros(n + 1, np.int64)
+    np.add.at(qrp, r + 1, 1)
+    Qm = CSR(n, n, np.cumsum(qrp), c[o].astype(np.int32), v[o])
+    return SparseQP(Qm, q, G, g, np.zeros(n), np.ones(n), dict(kind="num", seed=seed, path_len=path_len, band=band))
+
+
 def config0() -> QP:
     """Small dense QP: n=50, p=25, reg 0.1, seed 0."""
     return random_dense_qp(50, 25, seed=0, reg=0.1)
