@@ -125,8 +125,9 @@ typedef struct duq_options {
                                known for the batch's sizes, else the most that fit */
     double sigma_in;        /* strong convexity of L_rho(., mu), or <= 0 (above) */
     int32_t sparse_x;       /* duq_setup_csr: where products read x: DUQ_SPX_AUTO
-                               (staged in LDS when it fits, else in place),
-                               DUQ_SPX_LDS, DUQ_SPX_IN_PLACE (device memory)  */
+                               (in place on the grid engine; staged in LDS on
+                               the block engine when it fits), DUQ_SPX_LDS,
+                               DUQ_SPX_IN_PLACE (device memory)               */
     int32_t reserved[1];
 } duq_options;
 
@@ -194,12 +195,13 @@ typedef struct duq_csr {
  * duq_solve_planned on the handle.  Every row an equality with rho > 0: the inner
  * products stay Q u and G^T (G u) (no formed Q + rho G^T G) and the inner
  * strong convexity is lambda_min(Q) unless opts->sigma_in is given.  Each
- * product row is summed by sixteen lanes in a fixed order, so a solve is
- * reproducible run to run.  The products read x from a copy staged in LDS
- * (the LDS bound on n of duq_setup) or, with opts->sparse_x IN_PLACE (AUTO
- * when the copy does not fit), from device memory, which leaves n bounded
- * by device memory only; the LDS then holds the engine's share of the p
- * rows (block engine: all p).
+ * product row is summed by 2^k lanes in a fixed order (k per matrix from its
+ * mean row length), so a solve is reproducible run to run.  The products
+ * read x from a copy staged in LDS (the LDS bound on n of duq_setup) or,
+ * with opts->sparse_x IN_PLACE (AUTO on the grid engine or when the copy
+ * does not fit), from device memory, which leaves n bounded by device
+ * memory only; the LDS then holds the engine's share of the p rows (block
+ * engine: all p).
  * Errors: DUQ_EINVAL (null arrays, shapes other than n x n and p x n,
  * offsets, an index out of range, a non-finite value, memspace),
  * DUQ_ENOMEM, DUQ_EDEVICE.                                                  */

@@ -303,25 +303,38 @@ __device__ __forceinline__ void gemvT_reduce(const double* part, int nb, int n, 
 // Sparse rows (Sec. 5.1: with sparse Q and G the products cost their
 // nonzeros): out[r] = sum_k val[k] x[col[k]] + add[r] for rows [rlo, rhi) of
 // a compressed-row matrix, x read through `xa` (LDS, or device memory when x
-// does not fit).  Sixteen lanes per row, four rows per wavefront per trip; a
-// row's lanes take its nonzeros in a fixed stride and reduce by a butterfly,
-// so the sum order depends on the row only.
+// does not fit).  2^lg lanes per row (chosen per matrix from its mean row
+// length so a lane takes about four nonzeros), 64 / 2^lg rows per wavefront
+// per trip.  A lane takes its row's nonzeros at stride 2^lg, four loads in
+// flight at a time, adding them in index order; the lanes of a row then
+// reduce by a butterfly.  The sum order depends on the row and lg only.
 template <typename T, typename Acc, typename X>
 __device__ __forceinline__ void spmv_rows(const long long* rp, const int* ci, const T* val, int rlo, int rhi,
-                                          X xa, double* out, const double* add) {
+                                          int lg, X xa, double* out, const double* add) {
+    const int L = 1 << lg;
+    const int rpw = kWave >> lg;
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
-    const int sub = lane >> 4, sl = lane & 15;
-    for (int r0 = rlo + wid * 4; r0 < rhi; r0 += nw * 4) {
+    const int sub = lane >> lg, sl = lane & (L - 1);
+    for (int r0 = rlo + wid * rpw; r0 < rhi; r0 += nw * rpw) {
         const int r = r0 + sub;
         Acc s = 0;
         if (r < rhi) {
             const long long e = rp[r + 1];
-            for (long long k = rp[r] + sl; k < e; k += 16) s += (Acc)val[k] * (Acc)xa(ci[k]);
+            long long k = rp[r] + sl;
+            for (; k + 3 * L < e; k += 4 * L) {
+                const int c0 = ci[k], c1 = ci[k + L], c2 = ci[k + 2 * L], c3 = ci[k + 3 * L];
+                const Acc v0 = (Acc)val[k], v1 = (Acc)val[k + L], v2 = (Acc)val[k + 2 * L], v3 = (Acc)val[k + 3 * L];
+                const Acc x0 = (Acc)xa(c0), x1 = (Acc)xa(c1), x2 = (Acc)xa(c2), x3 = (Acc)xa(c3);
+                s += v0 * x0;
+                s += v1 * x1;
+                s += v2 * x2;
+                s += v3 * x3;
+            }
+            for (; k < e; k += L) s += (Acc)val[k] * (Acc)xa(ci[k]);
         }
-#pragma unroll
-        for (int off = 8; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
+        for (int off = L >> 1; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
         if (sl == 0 && r < rhi) out[r] = (double)s + (add ? add[r] : 0.0);
     }
 }
@@ -331,22 +344,8 @@ __device__ __forceinline__ void spmv_rows(const long long* rp, const int* ci, co
 // with the weights w read through `wt` (LDS or the team-visible buffer).
 template <typename T, typename W>
 __device__ __forceinline__ void spmvT_cols(const long long* rp, const int* ci, const T* val, int clo, int chi,
-                                           W wt, const double* add, double* z) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x >> 6;
-    const int nw = blockDim.x >> 6;
-    const int sub = lane >> 4, sl = lane & 15;
-    for (int j0 = clo + wid * 4; j0 < chi; j0 += nw * 4) {
-        const int j = j0 + sub;
-        double s = 0.0;
-        if (j < chi) {
-            const long long e = rp[j + 1];
-            for (long long k = rp[j] + sl; k < e; k += 16) s += (double)val[k] * wt(ci[k]);
-        }
-#pragma unroll
-        for (int off = 8; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
-        if (sl == 0 && j < chi) z[j] = s + (add ? add[j] : 0.0);
-    }
+                                           int lg, W wt, const double* add, double* z) {
+    spmv_rows<T, double>(rp, ci, val, clo, chi, lg, wt, z, add);
 }
 
 __device__ __forceinline__ void stage(const double* src, int len, double* dst) {
@@ -444,22 +443,23 @@ struct Dfom {
     // Compressed-row product over rows [lo, hi) with x from LDS or, when it
     // does not fit there, from the rotating buffer itself (device-scope loads
     // on a grid team: other workgroups wrote it).
-    __device__ __forceinline__ void sp_rows(const long long* rp, const int* ci, const T* v, int lo, int hi,
+    __device__ __forceinline__ void sp_rows(const long long* rp, const int* ci, const T* v, int lo, int hi, int lg,
                                             double* out, const double* add) const {
-        if (!par.x_global) spmv_rows<T, Acc>(rp, ci, v, lo, hi, [&](int j) { return xl[j]; }, out, add);
-        else if (tm.size > 1) spmv_rows<T, Acc>(rp, ci, v, lo, hi, [&](int j) { return xload(xsrc + j); }, out, add);
-        else spmv_rows<T, Acc>(rp, ci, v, lo, hi, [&](int j) { return xsrc[j]; }, out, add);
+        if (!par.x_global) spmv_rows<T, Acc>(rp, ci, v, lo, hi, lg, [&](int j) { return xl[j]; }, out, add);
+        else if (tm.size > 1)
+            spmv_rows<T, Acc>(rp, ci, v, lo, hi, lg, [&](int j) { return xload(xsrc + j); }, out, add);
+        else spmv_rows<T, Acc>(rp, ci, v, lo, hi, lg, [&](int j) { return xsrc[j]; }, out, add);
     }
 
     // Products over owned rows: streamed (non-temporal) on a grid team,
     // cached inside a single workgroup.
     __device__ __forceinline__ void prodQ(double* out) const {
-        if constexpr (SPARSE) sp_rows(P.Qrp, P.Qci, P.Qv, nlo, nhi, out, nullptr);
+        if constexpr (SPARSE) sp_rows(P.Qrp, P.Qci, P.Qv, nlo, nhi, P.Qlg, out, nullptr);
         else if (tm.size > 1) gemv_rows<T, Acc, 16, true, SHORT>(P.Q, P.n, nlo, nhi, P.n, xl, out, nullptr);
         else gemv_rows<T, Acc, 16, false, SHORT>(P.Q, P.n, nlo, nhi, P.n, xl, out, nullptr);
     }
     __device__ __forceinline__ void prodG(double* out, const double* add) const {
-        if constexpr (SPARSE) sp_rows(P.Grp, P.Gci, P.Gv, plo, phi, out, add);
+        if constexpr (SPARSE) sp_rows(P.Grp, P.Gci, P.Gv, plo, phi, P.Glg, out, add);
         else if (tm.size > 1) gemv_rows<T, Acc, 8, true, SHORT>(P.G, P.n, plo, phi, P.n, xl, out, add);
         else gemv_rows<T, Acc, 8, false, SHORT>(P.G, P.n, plo, phi, P.n, xl, out, add);
     }
@@ -520,11 +520,11 @@ struct Dfom {
             if (tm.size == 1) {
                 for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) vl[i - plo] = wt(i);
                 __syncthreads();
-                spmvT_cols<T>(P.Trp, P.Tci, P.Tv, nlo, nhi, [&](int k) { return vl[k - plo]; }, add, z);
+                spmvT_cols<T>(P.Trp, P.Tci, P.Tv, nlo, nhi, P.Tlg, [&](int k) { return vl[k - plo]; }, add, z);
             } else {
                 for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) xstore(W.wsh + i, wt(i));
                 if (tm.sync()) return false;
-                spmvT_cols<T>(P.Trp, P.Tci, P.Tv, nlo, nhi, [&](int k) { return xload(W.wsh + k); }, add, z);
+                spmvT_cols<T>(P.Trp, P.Tci, P.Tv, nlo, nhi, P.Tlg, [&](int k) { return xload(W.wsh + k); }, add, z);
             }
             __syncthreads();
             return true;

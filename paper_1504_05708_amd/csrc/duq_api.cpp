@@ -336,10 +336,13 @@ static int setup_impl(const duq_problem* pr, const duq_csr* Qs, const duq_csr* G
     if ((rc = device_info(&di))) return rc;
     int engine = opts->engine;
     if (engine == DUQ_ENGINE_AUTO) engine = (n <= 1536) ? DUQ_ENGINE_BLOCK : DUQ_ENGINE_GRID;
-    // compressed-row data reads x in place when asked, or when it does not fit in LDS
+    // compressed-row data reads x in place when asked, and by default on the
+    // grid engine (a product reads a few entries of x per row, where staging
+    // all of x would read n entries per workgroup) or when x does not fit in LDS
     const bool x_global =
         sparse && (opts->sparse_x == DUQ_SPX_IN_PLACE ||
-                   (opts->sparse_x == DUQ_SPX_AUTO && dfom_lds_bytes(n, p, solver_blocks(di, n, engine)) > di.lds_max));
+                   (opts->sparse_x == DUQ_SPX_AUTO &&
+                    (engine == DUQ_ENGINE_GRID || dfom_lds_bytes(n, p, solver_blocks(di, n, engine)) > di.lds_max)));
     if (dfom_lds_bytes(n, p, solver_blocks(di, n, engine), x_global) > di.lds_max)
         return too_large(di, n, p, engine);
 
@@ -699,6 +702,17 @@ int upload_sparse(duq_handle* h, const duq_problem* pr, const duq_csr* Qs, const
     }
     if (e != hipSuccess)
         return fail(DUQ_EDEVICE, std::string("copy of sparse problem data: ") + hipGetErrorString(e));
+    // lanes per row: the power of two that leaves a lane about four nonzeros
+    // of a mean row (1..64)
+    auto lanes_lg = [](long long nnz, int rows) {
+        const double avg = rows > 0 ? (double)nnz / rows : 0.0;
+        int lg = 0;
+        while (lg < 6 && 4.0 * (double)(2 << lg) <= avg) ++lg;
+        return lg;
+    };
+    sp.Qlg = lanes_lg(nq, n);
+    sp.Glg = lanes_lg(ng, p);
+    sp.Tlg = lanes_lg(ng, n);
     h->sparse = true;
     h->sp = sp;
     h->nnzQ = nq;

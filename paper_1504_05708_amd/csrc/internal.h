@@ -48,6 +48,7 @@ struct DevProblem {
     const long long* Trp = nullptr;
     const int* Tci = nullptr;
     const T* Tv = nullptr;
+    int Qlg = 0, Glg = 0, Tlg = 0;   // log2 of the lanes per row of each product
 };
 
 // Type-erased compressed-row arrays of a sparse problem (host runtime).
@@ -61,6 +62,7 @@ struct SparseRefs {
     const long long* Trp = nullptr;
     const int* Tci = nullptr;
     const void* Tv = nullptr;
+    int Qlg = 0, Glg = 0, Tlg = 0;
 };
 
 // Per-solve parameters derived on the host from the options and constants.

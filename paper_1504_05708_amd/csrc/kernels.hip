@@ -222,6 +222,9 @@ static void set_sparse(DevProblem<T>& P, const SparseRefs& s) {
     P.Trp = s.Trp;
     P.Tci = s.Tci;
     P.Tv = static_cast<const T*>(s.Tv);
+    P.Qlg = s.Qlg;
+    P.Glg = s.Glg;
+    P.Tlg = s.Tlg;
 }
 
 hipError_t launch_dfom(int dtype, int acc, const LaunchCfg& cfg, const GenericProblem& gp,

@@ -183,19 +183,20 @@ struct Lanczos {
 
     // Compressed-row Q, G: w = Q v, or w = G^T W (G v) gathered along the rows
     // of G^T (v staged in xl, or read in place when it does not fit).
-    __device__ __forceinline__ void sp_rows(const long long* rp, const int* ci, const T* val, int lo, int hi,
+    __device__ __forceinline__ void sp_rows(const long long* rp, const int* ci, const T* val, int lo, int hi, int lg,
                                             const double* v, double* out) const {
-        if (!L.x_global) spmv_rows<T, double>(rp, ci, val, lo, hi, [&](int j) { return xl[j]; }, out, nullptr);
-        else if (tm.size > 1) spmv_rows<T, double>(rp, ci, val, lo, hi, [&](int j) { return xload(v + j); }, out, nullptr);
-        else spmv_rows<T, double>(rp, ci, val, lo, hi, [&](int j) { return v[j]; }, out, nullptr);
+        if (!L.x_global) spmv_rows<T, double>(rp, ci, val, lo, hi, lg, [&](int j) { return xl[j]; }, out, nullptr);
+        else if (tm.size > 1)
+            spmv_rows<T, double>(rp, ci, val, lo, hi, lg, [&](int j) { return xload(v + j); }, out, nullptr);
+        else spmv_rows<T, double>(rp, ci, val, lo, hi, lg, [&](int j) { return v[j]; }, out, nullptr);
     }
     __device__ __forceinline__ bool apply_sparse(const double* v, double* w) {
         if (!use_gtg) {
-            sp_rows(P.Qrp, P.Qci, P.Qv, nlo, nhi, v, w);
+            sp_rows(P.Qrp, P.Qci, P.Qv, nlo, nhi, P.Qlg, v, w);
             __syncthreads();
             return true;
         }
-        sp_rows(P.Grp, P.Gci, P.Gv, plo, phi, v, L.r);
+        sp_rows(P.Grp, P.Gci, P.Gv, plo, phi, P.Glg, v, L.r);
         __syncthreads();
         auto weight = [&](int i) {
             double r = L.r[i];
@@ -208,11 +209,11 @@ struct Lanczos {
         if (tm.size == 1) {
             for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) vl[i - plo] = weight(i);
             __syncthreads();
-            spmvT_cols<T>(P.Trp, P.Tci, P.Tv, nlo, nhi, [&](int k) { return vl[k - plo]; }, nullptr, w);
+            spmvT_cols<T>(P.Trp, P.Tci, P.Tv, nlo, nhi, P.Tlg, [&](int k) { return vl[k - plo]; }, nullptr, w);
         } else {
             for (int i = plo + (int)threadIdx.x; i < phi; i += blockDim.x) xstore(L.rsh + i, weight(i));
             if (tm.sync()) return false;
-            spmvT_cols<T>(P.Trp, P.Tci, P.Tv, nlo, nhi, [&](int k) { return xload(L.rsh + k); }, nullptr, w);
+            spmvT_cols<T>(P.Trp, P.Tci, P.Tv, nlo, nhi, P.Tlg, [&](int k) { return xload(L.rsh + k); }, nullptr, w);
         }
         __syncthreads();
         return true;
