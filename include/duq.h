@@ -60,6 +60,7 @@ enum { DUQ_ACC_F64 = 0, DUQ_ACC_F32 = 1 };                    /* product accumul
 enum { DUQ_ENGINE_AUTO = 0, DUQ_ENGINE_BLOCK = 1, DUQ_ENGINE_GRID = 2,
        DUQ_ENGINE_TILE = 3 };   /* TILE: shared batches only, see duq_solve_batch */
 enum { DUQ_SPX_AUTO = 0, DUQ_SPX_LDS = 1, DUQ_SPX_IN_PLACE = 2 };  /* options.sparse_x */
+enum { DUQ_LB_AUTO = 0, DUQ_LB_SIGMA = 1, DUQ_LB_SIGMA_FREE = 2 };  /* options.lb_cert */
 
 /* ---- problem data (Sec. 2, eq. original_primal) ------------------------- *
  * Constraints: G u + g <= 0 (K = R^p_-) when rlo and rhi are NULL.  With
@@ -128,7 +129,15 @@ typedef struct duq_options {
                                (in place on the grid engine; staged in LDS on
                                the block engine when it fits), DUQ_SPX_LDS,
                                DUQ_SPX_IN_PLACE (device memory)               */
-    int32_t reserved[1];
+    int32_t lb_cert;        /* inner gap that enters the dual lower bound LB:
+                               DUQ_LB_SIGMA (= AUTO): min(FW, ||pi||^2/(2 sigma)),
+                               as the stopping test; valid when sigma is at
+                               most the true strong convexity (an estimated
+                               lambda_min is a Ritz value / safety: a margin,
+                               not a bound).  DUQ_LB_SIGMA_FREE: the FW gap (or
+                               the gradient-mapping bound without its sigma
+                               term), valid for any sigma; linear in the
+                               gradient, so LB converges more slowly       */
 } duq_options;
 
 /* ---- per-solve result --------------------------------------------------- *

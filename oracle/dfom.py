@@ -42,6 +42,12 @@ design notes):
         ||lambda^k|| ||[Gx+g]_+|| <= eps_out max(1, |F(x)|),
     with LB = max_j (dbar_j - gap_j) over multipliers where weak duality
     holds (mu^j >= 0 when rho = 0, every mu^j when rho > 0).
+  * The ||pi||^2/(2 sigma) and gradient-mapping sigma terms bound the inner
+    gap only when sigma is a true lower bound on the strong convexity.  An
+    estimated sigma (a Lanczos Ritz value lies above lambda_min) may be too
+    large, so with Options.lb_sigma_free the gap that enters LB is the
+    sigma-free part (the FW gap, or the gradient-mapping bound without the
+    sigma term); the inner stopping test keeps the sigma form.
   * Last iterate of DFGM is u(lambda^k) (eq. last_primal): when ubar^k
     passes the test, one more inner solve at lambda^k, warm-started from
     ubar^k, is tested and returned if it passes; otherwise the iteration
@@ -97,6 +103,7 @@ class Options:
     lam_max: Optional[float] = None
     G_norm2: Optional[float] = None
     log_vectors: int = 0          # outer iterations whose vectors are logged
+    lb_sigma_free: bool = False   # LB from sigma-free inner certificates (sigma estimated)
 
 
 @dataclass
@@ -311,10 +318,13 @@ def _inner_beta_schedule(variant: int, sigma: float, beta_in: float):
 
 
 def fom_inner(Q, q, G, g, lb, ub, mu, rho: float, c: Constants, x0,
-              eps_in: float, rule: int = CERT, variant: int = INNER_AUTO, eq=None):
+              eps_in: float, rule: int = CERT, variant: int = INNER_AUTO, eq=None,
+              sigma_free: bool = False):
     """Approximate u(mu) by Algorithm FOM(L_rho(., mu), U) from x^0 = y^1 = x0.
 
-    Returns (x, steps, gap) with gap the certificate value of x."""
+    Returns (x, steps, gap) with gap the certificate value of x; with
+    sigma_free also the certificate of x without its sigma term (valid for
+    any strong convexity constant): (x, steps, gap, gap_sigma_free)."""
     L, sigma, k_max = c.L_in, c.sigma_in, c.k_in_max
     betas = _inner_beta_schedule(variant, sigma, c.beta_in)
 
@@ -332,9 +342,10 @@ def fom_inner(Q, q, G, g, lb, ub, mu, rho: float, c: Constants, x0,
         x_prev = x = x0.copy()
         t = 0
         while True:
-            gap = inner_certificate(x, grad(x), lb, ub, sigma)
+            gx = grad(x)
+            gap = inner_certificate(x, gx, lb, ub, sigma)
             if done(gap, t):
-                return x, t, gap
+                return (x, t, gap, inner_certificate(x, gx, lb, ub, 0.0)) if sigma_free else (x, t, gap)
             if t == 0:
                 y = x                                   # y^1 = x^0
             else:
@@ -351,12 +362,13 @@ def fom_inner(Q, q, G, g, lb, ub, mu, rho: float, c: Constants, x0,
         if t == 0:
             gap = inner_certificate(x0, gy, lb, ub, sigma)
             if rule == CERT and gap <= eps_in:
-                return x0.copy(), 0, gap
+                return ((x0.copy(), 0, gap, inner_certificate(x0, gy, lb, ub, 0.0)) if sigma_free
+                        else (x0.copy(), 0, gap))
         x = np.clip(y - gy / L, lb, ub)
         t += 1
         gap = gradmap_certificate(y, x, L, lb, ub, sigma)
         if done(gap, t):
-            return x, t, gap
+            return (x, t, gap, gradmap_certificate(y, x, L, lb, ub, 0.0)) if sigma_free else (x, t, gap)
         y = x + next(betas) * (x - x_prev)
         x_prev = x
 
@@ -439,13 +451,15 @@ def dfom_solve(qp, opts: Options, consts: Optional[Constants] = None,
                 return Result(x_warm.copy(), mu.copy(), Fx, LB, feas, STATUS_INFEASIBLE,
                               k, inner_total, c, log)
         # Step 1: ubar^k approximately minimises L_rho(., mu^k) over U
-        u, t, gap = fom_inner(Q, q, G, g, lb, ub, mu, rho, c, x_warm,
-                              opts.eps_in, opts.inner_rule, opts.inner_variant, eq)
+        u, t, gap, gap_lb = fom_inner(Q, q, G, g, lb, ub, mu, rho, c, x_warm, opts.eps_in, opts.inner_rule,
+                                      opts.inner_variant, eq, sigma_free=True)
+        if not opts.lb_sigma_free:
+            gap_lb = gap
         inner_total += t
         dg = dual_gradient(G, g, u, mu, rho, eq)
         dbar = lagrangian(Q, q, G, g, u, mu, rho, eq)
         if rho > 0.0 or in_Kd(mu):                 # weak duality holds at mu^k
-            LB = max(LB, dbar - gap)
+            LB = max(LB, dbar - gap_lb)
         # Step 2: projected inexact dual gradient step
         lam_k = proj_Kd(mu + c.alpha * dg)
         # Step 3: momentum (DGM: theta = 1; DFGM: theta rule)
@@ -468,11 +482,13 @@ def dfom_solve(qp, opts: Options, consts: Optional[Constants] = None,
         result_x = cand
         if ok and opts.output == LAST and opts.method == DFGM:
             # last primal iterate u(lambda^k), eq. last_primal
-            u2, t2, gap2 = fom_inner(Q, q, G, g, lb, ub, lam_k, rho, c, u,
-                                     opts.eps_in, opts.inner_rule, opts.inner_variant, eq)
+            u2, t2, gap2, gap2_lb = fom_inner(Q, q, G, g, lb, ub, lam_k, rho, c, u, opts.eps_in, opts.inner_rule,
+                                              opts.inner_variant, eq, sigma_free=True)
+            if not opts.lb_sigma_free:
+                gap2_lb = gap2
             inner_total += t2
             if rho > 0.0 or in_Kd(lam_k):
-                LB = max(LB, lagrangian(Q, q, G, g, u2, lam_k, rho, eq) - gap2)
+                LB = max(LB, lagrangian(Q, q, G, g, u2, lam_k, rho, eq) - gap2_lb)
             ok, Fx, feas = _outer_test(Q, q, G, g, u2, lam_k, LB, opts.eps_out, gnorm, eq)
             entry.update(extra_t=t2, extra_gap=gap2, LB=LB, F2=Fx, feas2=feas, passed2=ok)
             result_x = u2

@@ -23,6 +23,7 @@ namespace duq {
 int set_error(int code, const std::string& msg);
 int device_cus();
 void handle_params(duq_handle* h, DevParams* par);
+int resolve_lb_cert(int opt);
 int derive_params(int p, double lam_min, double lam_max, double g2, double D_U, const duq_options& o,
                   DevParams* par, double sigma);
 }
@@ -454,6 +455,7 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
     par.eps_out = o->eps_out;
     par.eps_in = o->eps_in;
     par.rho = o->rho;
+    par.lb_cert = resolve_lb_cert(o->lb_cert);
     L.base = par;
     L.max_inner = o->max_inner;
     L.lanczos_k = k_req;

@@ -419,6 +419,8 @@ struct Dfom {
     double* tl;              // LDS: blockDim*4 doubles for short-row G^T v
     int pp;                  // ping-pong index of the partial buffer
     long long gt_rows;       // rows of G touched by transposed products
+    double glb;              // sigma-free certificate of the last inner answer (enters LB
+                             // when par.lb_cert == 2)
 
     // Rotating buffers selected without runtime-indexed arrays (which would
     // force the pointer tables into scratch memory).
@@ -433,6 +435,10 @@ struct Dfom {
     __device__ __forceinline__ void stage_x(const double* src) {
         if constexpr (SPARSE) {
             if (par.x_global) {
+                // read in place: device-scope loads on a grid team.  (Plain
+                // loads after an agent-scope acquire, which would let the
+                // gathers share the XCD's L2, measured slower: the acquire
+                // invalidates L1 and L2 for every wave.)
                 xsrc = src;
                 __syncthreads();
                 return;
@@ -604,6 +610,7 @@ struct Dfom {
             }
             if (!allreduce<2>(acc)) return -1;
             gap = gap_from(acc[0], acc[1]);
+            glb = acc[0];
             if (!(gap == gap)) return -2;
             if ((par.inner_rule == 0 && gap <= par.eps_in) || t >= par.k_in_max) return t;
             if (t > 0 && par.inner_variant == 2) th = 0.5 * (1.0 + sqrt(1.0 + 4.0 * th * th));
@@ -670,10 +677,12 @@ struct Dfom {
             if (!allreduce<4>(acc)) return -1;
             if (t == 0) {
                 gap = gap_from(acc[0], acc[1]);
+                glb = acc[0];
                 if (!(gap == gap)) return -2;
                 if (par.inner_rule == 0 && gap <= par.eps_in) return 0;
             }
             double g2 = acc[2] - acc[3] / (2.0 * par.L);
+            glb = g2;
             if (par.sigma > 0.0) g2 = fmin(g2, 0.5 * acc[3] * (1.0 / par.sigma - 1.0 / par.L));
             gap = g2;
             if (!(gap == gap)) return -2;
@@ -1024,7 +1033,7 @@ struct Dfom {
             const double Fu = 0.5 * a[0] + a[1];
             const double dbar = par.rho > 0.0 ? Fu + 0.5 * par.rho * a[2] - a[3] / (2.0 * par.rho)
                                               : Fu + a[2];
-            if (par.rho > 0.0 || a[7] == 0.0) LB = fmax(LB, dbar - gap);
+            if (par.rho > 0.0 || a[7] == 0.0) LB = fmax(LB, dbar - (par.lb_cert == 2 ? glb : gap));
             S = Sn;
             double F, feas;
             if (par.output == 0) {
@@ -1082,7 +1091,7 @@ struct Dfom {
                 const double F2 = 0.5 * b[0] + b[1];
                 const double d2 = par.rho > 0.0 ? F2 + 0.5 * par.rho * b[2] - b[3] / (2.0 * par.rho)
                                                 : F2 + b[2];
-                if (par.rho > 0.0 || a[10] == 0.0) LB = fmax(LB, d2 - gap2);
+                if (par.rho > 0.0 || a[10] == 0.0) LB = fmax(LB, d2 - (par.lb_cert == 2 ? glb : gap2));
                 const double feas2 = sqrt(b[4]);
                 const bool ok2 = outer_ok(F2, feas2, lnorm, LB, gnorm);
                 ex[0] = t2; ex[1] = gap2; ex[2] = F2; ex[3] = feas2; ex[4] = ok2 ? 1.0 : 0.0;

@@ -227,6 +227,7 @@ int validate_common(const duq_problem* pr, const duq_options* o, bool sparse) {
         return fail(DUQ_EINVAL, "negative count");
     if (!(o->safety >= 1.0)) return fail(DUQ_EINVAL, "safety must be >= 1");
     if (o->sparse_x < DUQ_SPX_AUTO || o->sparse_x > DUQ_SPX_IN_PLACE) return fail(DUQ_EINVAL, "bad sparse_x");
+    if (o->lb_cert < DUQ_LB_AUTO || o->lb_cert > DUQ_LB_SIGMA_FREE) return fail(DUQ_EINVAL, "bad lb_cert");
     return DUQ_OK;
 }
 
@@ -269,6 +270,15 @@ int estimate_constants(duq_handle* h, const DeviceInfo& di);
 // the options: L_d = ||G||^2/(lam_min + rho ||G||^2) (Sec. 2 eq. Ld), step
 // 1/(2 L_d); L_in = lam_max + rho ||G||^2, sigma_in = lam_min (Sec. 3 Step 1);
 // the inner cap k_in of Sec. 5 (natural log, rounded up) unless max_inner > 0.
+// The inner gap entering LB (options.lb_cert): AUTO is the sigma form, the
+// one the stopping test uses.  It is a valid bound when sigma is at most the
+// strong convexity of the inner problem; an estimated lambda_min (a Lanczos
+// Ritz value, which lies above lambda_min, divided by the safety factor) is a
+// margin, not a bound, and SIGMA_FREE (the FW gap, linear rather than
+// quadratic in the gradient, so LB converges more slowly) is valid for any
+// sigma.
+int resolve_lb_cert(int opt) { return opt == DUQ_LB_AUTO ? DUQ_LB_SIGMA : opt; }
+
 int derive_params(int p, double lam_min, double lam_max, double g2, double D_U, const duq_options& o,
                   DevParams* par, double sigma) {
     const double rho = o.rho;
@@ -303,6 +313,7 @@ int derive_params(int p, double lam_min, double lam_max, double g2, double D_U, 
     par->eps_out = o.eps_out;
     par->eps_in = o.eps_in;
     par->rho = o.rho;
+    par->lb_cert = resolve_lb_cert(o.lb_cert);
     return DUQ_OK;
 }
 }
@@ -846,6 +857,7 @@ extern "C" int duq_solve(duq_handle* h, const double* x0, const double* lam0, do
     par.beta_in = h->beta_in;
     par.eqform = h->eqform ? 1 : 0;
     par.x_global = h->x_global ? 1 : 0;
+    par.lb_cert = resolve_lb_cert(o.lb_cert);
     GenericProblem gp{n, p, h->eqform ? h->dH : h->dQ, h->dG, h->dq, h->dg, h->dlb, h->dub, h->drlo, h->drhi};
     gp.sp = h->sp;
     DevState st;
@@ -941,6 +953,7 @@ int handle_slice(duq_handle* h, bool first, int slice, int k_done, DevState* st_
     par.L = h->L_in;
     par.sigma = h->sigma;
     par.beta_in = h->beta_in;
+    par.lb_cert = resolve_lb_cert(o.lb_cert);
     GenericProblem gp{h->n, h->p, h->dQ, h->dG, h->dq, h->dg, h->dlb, h->dub};
     gp.sp = h->sp;
     HIP_TRY(launch_dfom(h->dtype, DUQ_ACC_F64, h->cfg, gp, par, h->W));
@@ -979,6 +992,7 @@ void handle_params(duq_handle* h, DevParams* par) {
     par->L = h->L_in;
     par->sigma = h->sigma;
     par->beta_in = h->beta_in;
+    par->lb_cert = resolve_lb_cert(o.lb_cert);
 }
 
 // Constants and engine of a handle, for reporting.

@@ -85,6 +85,7 @@ struct DevParams {
     int eqform;        // every row an equality and rho > 0: Q holds Q + rho G^T G
                        // (Sec. 5.1), the inner loop is the rho = 0 one
     int x_global;      // sparse data: x read in place from its buffer, not staged in LDS
+    int lb_cert;       // inner gap entering LB: 1 sigma form, 2 sigma-free
     double eps_out;    // outer tolerance used by this launch
     double eps_in;
     double rho;

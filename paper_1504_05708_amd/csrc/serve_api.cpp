@@ -32,6 +32,7 @@ int device_cus();
 int handle_slice(duq_handle* h, bool first, int slice, int k_done, DevState* st_host);
 int handle_barrier_error(duq_handle* h, unsigned* flag);
 int handle_outputs(duq_handle* h, double* x, double* lam);
+int resolve_lb_cert(int opt);
 void handle_info(duq_handle* h, double* lam_min, double* lam_max, double* g2, int* engine);
 }  // namespace duq
 
@@ -392,6 +393,7 @@ int round(duq_server* s) {
     par.eps_out = s->opts.eps_out;
     par.eps_in = s->opts.eps_in;
     par.rho = s->opts.rho;
+    par.lb_cert = resolve_lb_cert(s->opts.lb_cert);
     for (Group& gr : grp) {
         if (gr.r.empty()) continue;
         const int B = (int)gr.r.size();

@@ -351,7 +351,9 @@ struct Tile {
                 } else if ((par.inner_rule == 0 && gap <= par.eps_in) || t >= par.k_in_max) {
                     run = false;
                     t_out = t;
-                    gap_out = gap;
+                    // the gap that enters LB: the stopping certificate, or its
+                    // sigma-free part (FW gap) when sigma is an estimate
+                    gap_out = par.lb_cert == 2 ? acc[0] : gap;
                 }
             }
             if (!__any(run)) break;   // every wave holds all 16 columns: same decision

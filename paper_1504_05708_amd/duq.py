@@ -31,6 +31,7 @@ INNER_AUTO, INNER_GM, INNER_FGM, INNER_FGM_SIGMA = 0, 1, 2, 3
 ACC_F64, ACC_F32 = 0, 1
 ENGINE_AUTO, ENGINE_BLOCK, ENGINE_GRID, ENGINE_TILE = 0, 1, 2, 3
 SPX_AUTO, SPX_LDS, SPX_IN_PLACE = 0, 1, 2
+LB_AUTO, LB_SIGMA, LB_SIGMA_FREE = 0, 1, 2
 TRACE_SCALARS = 16
 
 BATCH_UNEVEN, BATCH_SHARED = 0, 1
@@ -63,7 +64,7 @@ class DuqOptions(Structure):
                 ("rho", c_double), ("lam_min", c_double), ("lam_max", c_double),
                 ("G_norm2", c_double), ("safety", c_double), ("switch_factor", c_double),
                 ("switch_stall", c_int32), ("serve_slice", c_int32), ("out_memspace", c_int32),
-                ("batch_wpc", c_int32), ("sigma_in", c_double), ("sparse_x", c_int32), ("reserved", c_int32 * 1)]
+                ("batch_wpc", c_int32), ("sigma_in", c_double), ("sparse_x", c_int32), ("lb_cert", c_int32)]
 
 
 class DuqResult(Structure):

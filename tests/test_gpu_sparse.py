@@ -109,6 +109,27 @@ def test_sparse_in_place_augmented_fp32(engine):
                      sparse_x=duq.SPX_IN_PLACE)
 
 
+@pytest.mark.parametrize("n,p", [(4000, 1500), (16000, 5000)])
+def test_sparse_in_place_bitwise_equals_lds(n, p):
+    # the two ways of reading x (a staged LDS copy; plain loads of the buffer
+    # itself after an acquire) feed the same sums in the same order: every
+    # traced iterate must be bitwise equal, so a stale read would show here
+    print(f"[case] sparse in place vs LDS n={n}", flush=True)
+    sq = gen.sparse_num_qp(n, p, seed=414)
+    K = 150
+    out = []
+    for mode in (duq.SPX_LDS, duq.SPX_IN_PLACE):
+        with duq.Solver(sq.Q, sq.q, sq.G, sq.g, sq.lb, sq.ub, eps_out=1e-13, eps_in=1e-8, max_outer=K,
+                        trace_outer=K, engine=duq.ENGINE_GRID, sparse_x=mode, rho=0.0) as s:
+            x, lam, res = s.solve(check=False)
+            out.append((x, lam, res, s.trace(K)))
+    (x0, l0, r0, t0), (x1, l1, r1, t1) = out
+    assert r0["outer_iters"] == r1["outer_iters"] == K and r0["inner_iters"] == r1["inner_iters"]
+    assert np.array_equal(x0, x1) and np.array_equal(l0, l1)
+    for key in ("lam", "mu", "u", "scalars"):
+        assert np.array_equal(t0[key], t1[key]), key
+
+
 def test_sparse_in_place_grid_medium_parity():
     print("[case] sparse in place grid n=4000", flush=True)
     sq = gen.sparse_num_qp(4000, 1500, seed=403)

@@ -934,3 +934,55 @@ def test_planned_solve_doubles_R_until_the_test_passes():
     assert r.status == dfom.STATUS_OK and r.rounds > 1
     assert [p.k_out for p in r.plans] == sorted(p.k_out for p in r.plans)
     assert abs(r.F - fstar) <= 1e-3 * max(1.0, abs(fstar))
+
+
+# ----------------------------------------------------------------------------
+# LB with an estimated (possibly too large) strong convexity constant
+# ----------------------------------------------------------------------------
+
+def test_sigma_free_lower_bound_stays_below_fstar():
+    # An estimate of lambda_min(Q) from above (a Ritz value) makes the
+    # ||pi||^2/(2 sigma) certificate too small, and LB = dbar - gap can then
+    # pass F*: with sigma three times too large that happens on these seeds.
+    # The sigma-free certificate (FW gap) bounds L(u, mu) - d(mu) for any
+    # sigma, so weak duality LB <= d(mu) <= F* holds at every iteration.
+    from oracle.ipm import ipm_qp
+    crossed = 0
+    for seed in (100, 103):
+        qp = gen.random_dense_qp(30, 15, seed=seed, reg=0.01)
+        ev = np.linalg.eigvalsh(qp.Q)
+        fstar = ipm_qp(qp.Q, qp.q, qp.G, qp.g, qp.lb, qp.ub)[1]
+        c = dfom.problem_constants(qp.Q, qp.G, qp.lb, qp.ub, 0.0, 1e-6, lam_min=3.0 * ev[0], lam_max=ev[-1])
+        for free in (False, True):
+            r = dfom.dfom_solve(qp, dfom.Options(eps_out=1e-6, eps_in=1e-6, max_outer=3000, lb_sigma_free=free),
+                                consts=c)
+            top = max(e["LB"] for e in r.log) - fstar
+            if free:
+                assert top <= 1e-10 * max(1.0, abs(fstar)), (seed, top)
+            else:
+                crossed += top > 1e-8
+    assert crossed == 2   # the failure the sigma-free bound prevents is real on these inputs
+
+
+def test_sigma_free_certificates_bound_the_true_gap():
+    # at random box points the sigma-free forms bound phi(x) - min phi (exact
+    # minimum by box_qp_exact) whatever sigma is claimed
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        n = 6
+        A = rng.standard_normal((n, n))
+        Q = A.T @ A / n + 0.05 * np.eye(n)
+        q = rng.standard_normal(n)
+        lb, ub = -np.ones(n), np.ones(n)
+        xstar = box_qp_exact(Q, q, lb, ub)[0]
+        fmin = 0.5 * xstar @ Q @ xstar + q @ xstar
+        x = rng.uniform(-1, 1, n)
+        x[rng.random(n) < 0.3] = 1.0
+        gx = Q @ x + q
+        true_gap = 0.5 * x @ Q @ x + q @ x - fmin
+        assert dfom.inner_certificate(x, gx, lb, ub, 0.0) >= true_gap - 1e-12
+        L = float(np.linalg.eigvalsh(Q)[-1])
+        y = rng.uniform(-1, 1, n)
+        xn = np.clip(y - (Q @ y + q) / L, lb, ub)
+        gap_n = 0.5 * xn @ Q @ xn + q @ xn - fmin
+        assert dfom.gradmap_certificate(y, xn, L, lb, ub, 0.0) >= gap_n - 1e-12
