@@ -986,3 +986,36 @@ def test_sigma_free_certificates_bound_the_true_gap():
         xn = np.clip(y - (Q @ y + q) / L, lb, ub)
         gap_n = 0.5 * xn @ Q @ xn + q @ xn - fmin
         assert dfom.gradmap_certificate(y, xn, L, lb, ub, 0.0) >= gap_n - 1e-12
+
+
+def test_inner_fgm_matches_three_sequence_form():
+    # Without active bounds, FOM with the theta rule (Sec. 2.1) is the same
+    # method as the estimate-sequence form of Nesterov's accelerated gradient
+    # (an auxiliary sequence z: y_k = (1 - 1/theta_k) x_{k-1} + z_{k-1}/theta_k,
+    # x_k = y_k - grad/L, z_k = z_{k-1} - (theta_k / L) grad).  Iterates
+    # agree to rounding, which fixes the momentum (theta_k - 1)/theta_{k+1}
+    # exactly, where the rate bounds leave room for near variants.
+    rng = np.random.default_rng(91)
+    n = 8
+    A = rng.standard_normal((n, n))
+    Q = A.T @ A / n + 1e-3 * np.eye(n)
+    q = rng.standard_normal(n)
+    lb, ub = np.full(n, -1e3), np.full(n, 1e3)
+    G, g = np.zeros((0, n)), np.zeros(0)
+    x0 = rng.uniform(-1, 1, n)
+    L = float(np.linalg.eigvalsh(Q)[-1])
+    xs, z, th = [x0], x0.copy(), 1.0
+    x = x0.copy()
+    for k in range(1, 41):
+        y = (1.0 - 1.0 / th) * x + z / th
+        gr = Q @ y + q
+        x = y - gr / L
+        z = z - (th / L) * gr
+        xs.append(x)
+        th = 0.5 * (1.0 + math.sqrt(1.0 + 4.0 * th * th))
+    for k in (1, 2, 3, 5, 10, 20, 40):
+        c = problem_constants(Q, G, lb, ub, 0.0, 1e-300, lam_min=0.0, lam_max=L, G_norm2=0.0, max_inner=k)
+        xk, t, _ = fom_inner(Q, q, G, g, lb, ub, np.zeros(0), 0.0, c, x0, 1e-300, rule=FIXED,
+                             variant=dfom.INNER_FGM)
+        assert t == k and np.max(np.abs(xk)) < 1e3
+        np.testing.assert_allclose(xk, xs[k], rtol=0, atol=1e-11 * max(1.0, np.max(np.abs(xs[k]))))
