@@ -62,7 +62,7 @@ def parse():
                     help="single large QP (default), uneven batch, or shared-Hessian MPC batch")
     ap.add_argument("--batch", type=int, default=None, help="instances of a batch workload")
     ap.add_argument("--plain-sample", type=int, default=48)
-    ap.add_argument("--batch-max-outer", type=int, default=20000,
+    ap.add_argument("--batch-max-outer", type=int, default=5000,
                     help="outer iteration cap per instance in the batched forms")
     ap.add_argument("--gen-workers", type=int, default=16,
                     help="processes generating uneven instances (1: in-process, e.g. under a profiler)")
@@ -72,6 +72,10 @@ def parse():
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
     ap.add_argument("--large-frac", type=float, default=0.01, help="serve: share of n=4096 requests")
     ap.add_argument("--slice", type=int, default=16, help="serve: outer iterations per round")
+    ap.add_argument("--serve-protocol", action="store_true",
+                    help="serve: measure the saturation rate first, then serve at --load-frac of it")
+    ap.add_argument("--sat-window", type=float, default=10.0, help="serve: seconds of the saturation run")
+    ap.add_argument("--load-frac", type=float, default=0.8, help="serve: offered share of the saturation rate")
     ap.add_argument("--sparse-n", type=int, default=2_000_000, help="sparse: flows (variables)")
     ap.add_argument("--sparse-p", type=int, default=500_000, help="sparse: links (rows of G)")
     ap.add_argument("--print-source-hash", action="store_true", help="hashes of the profiled kernels' sources")
@@ -697,6 +701,27 @@ def batch_result(a, workload, B, steps, warmup, precision, with_cpu, oracle_samp
 
 
 def bench_serve(a):
+    """--workload serve: the offered rate --rate for --duration seconds, or
+    with --serve-protocol the capacity of one GPU: a saturation run (offered
+    rate far above capacity, --sat-window seconds; the sustained rate is the
+    completions over the span) and then a run at --load-frac of that rate
+    for --duration seconds, whose latencies are the service's own."""
+    if not a.serve_protocol:
+        print(json.dumps(serve_run(a, a.rate, a.duration)), flush=True)
+        return
+    sat = serve_run(a, a.rate, a.sat_window)
+    rate = round(a.load_frac * sat["value"], 1)
+    run = serve_run(a, rate, a.duration)
+    run["saturation"] = {"offered_per_s": sat["offered_per_s"], "sustained_solves_per_s": sat["value"],
+                         "window_s": a.sat_window, "requests": sat["config"]["requests"],
+                         "latency_ms": sat["latency_ms"], "solve": sat["solve"]}
+    run["config"]["workload"] = (f"serving at {a.load_frac:.0%} of the saturation rate measured first "
+                                 f"({sat['value']:g}/s sustained against {a.rate:g}/s offered for {a.sat_window:g} s): "
+                                 + run["config"]["workload"])
+    print(json.dumps(run), flush=True)
+
+
+def serve_run(a, rate, duration):
     """Serving loop: Poisson arrivals of a request mix, submitted from one host
     thread to duq_submit, collected with duq_poll.  Mix: `large_frac` dense QPs
     n=4096, p=2048 (config-1 generator; a pool of 8 (Q, G) made before the
@@ -718,9 +743,9 @@ def bench_serve(a):
     rng = np.random.default_rng(4)
     t0 = time.time()
     # arrivals and classes
-    gaps = rng.exponential(1.0 / a.rate, int(a.rate * a.duration * 1.5) + 16)
+    gaps = rng.exponential(1.0 / rate, int(rate * duration * 1.5) + 16)
     arr = np.cumsum(gaps)
-    arr = arr[arr < a.duration]
+    arr = arr[arr < duration]
     R = len(arr)
     u = rng.uniform(size=R)
     cls = np.where(u < a.large_frac, 2, np.where(u < a.large_frac + (1 - a.large_frac) / 2, 0, 1))
@@ -791,7 +816,7 @@ def bench_serve(a):
         if now - last_print > 10:
             print(f"[serve] t={now - t_start:.0f}s done {R - len(pending)}/{R}", file=sys.stderr, flush=True)
             last_print = now
-        if now - t_start > a.duration + 240:
+        if now - t_start > duration + 240:
             break
         time.sleep(0.01)
     th.join()
@@ -840,7 +865,7 @@ def bench_serve(a):
         "speedup_vs_plain": None,
         "warmup": 1, "ms_per_step": round(span * 1e3, 1), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if a.precision == "f64" else "f32-storage/f64", "data": "synthetic",
-        "config": {"workload": f"serving: Poisson arrivals {a.rate:g}/s for {a.duration:g} s (seed 4); "
+        "config": {"workload": f"serving: Poisson arrivals {rate:g}/s for {duration:g} s (seed 4); "
                                f"{a.large_frac:.0%} dense n=4096 p=2048 (pool of 8, fresh q,g), rest half uneven "
                                f"n~U{{20..512}} and half MPC on 8 registered systems (seeds 40..47, fresh x0); "
                                f"matrices {a.precision}; {a.method.upper()}-{a.output} eps_out={a.eps_out:g} "
@@ -850,13 +875,13 @@ def bench_serve(a):
                        "by_class": by},
         "solve": {"completed": len(done), "ok": ok, "failed": len(done) - ok, "max_cert_subopt_rel": cert,
                   "max_feas_abs": max(results[i][3]["feas"] for i in done)},
-        "offered_per_s": round(R / a.duration, 1),
+        "offered_per_s": round(R / duration, 1),
         "plain_solves_per_s": round(len(done) / sum(plain_s.get(reqs[i][0], 0.0) for i in done), 2),
         "plain_seconds_per_request": {k: round(v, 4) for k, v in plain_s.items()},
         "gen_seconds": round(gen_s, 1),
     }
     line["speedup_vs_plain"] = round(line["value"] / line["plain_solves_per_s"], 1)
-    print(json.dumps(line), flush=True)
+    return line
 
 
 # ----------------------------------------------------------------------------

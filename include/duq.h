@@ -49,7 +49,7 @@ extern "C" {
                                 last iterate (rho = 0)                             */
 
 /* ---- enumerations ------------------------------------------------------ */
-enum { DUQ_F64 = 0, DUQ_F32 = 1, DUQ_BF16 = 2 };            /* storage of Q, G   */
+enum { DUQ_F64 = 0, DUQ_F32 = 1 };   /* storage of Q, G (FP64 arithmetic on either) */
 enum { DUQ_HOST = 0, DUQ_DEVICE = 1 };                        /* memspace          */
 enum { DUQ_DGM = 0, DUQ_DFGM = 1 };                           /* outer method, Sec. 3 */
 enum { DUQ_LAST = 0, DUQ_AVG = 1 };                           /* primal output, Sec. 4 */

@@ -232,6 +232,41 @@ struct Lanczos {
         return cnt;
     }
 
+    // Residual of the Ritz pair at x (an extreme eigenvalue of the m x m
+    // tridiagonal a, b[1..m-1]): |b_m s_m| + ||(T - x) s|| for s the unit
+    // eigenvector of T, found by two steps of inverse iteration with the
+    // shift x - d (below the smallest eigenvalue: T - shift I is positive
+    // definite, so the tridiagonal elimination needs no pivoting) or x + d
+    // (above the largest: negative definite).  A Ritz pair (x, V s) with
+    // residual r has an eigenvalue of the operator in [x - r, x + r].
+    __device__ static double ritz_residual(const double* a, const double* b, int m, double x, double shift,
+                                           double* y, double* cp) {
+        for (int i = 0; i < m; ++i) y[i] = 1.0;
+        for (int it = 0; it < 2; ++it) {
+            // (T - shift I) y_new = y: elimination in place (y holds the
+            // modified right-hand side), then back substitution
+            double den = a[0] - shift;
+            cp[0] = m > 1 ? b[1] / den : 0.0;
+            y[0] = y[0] / den;
+            for (int i = 1; i < m; ++i) {
+                den = (a[i] - shift) - b[i] * cp[i - 1];
+                cp[i] = i + 1 < m ? b[i + 1] / den : 0.0;
+                y[i] = (y[i] - b[i] * y[i - 1]) / den;
+            }
+            for (int i = m - 2; i >= 0; --i) y[i] -= cp[i] * y[i + 1];
+            double nrm = 0.0;
+            for (int i = 0; i < m; ++i) nrm += y[i] * y[i];
+            nrm = sqrt(nrm);
+            for (int i = 0; i < m; ++i) y[i] /= nrm;
+        }
+        double res2 = 0.0;
+        for (int i = 0; i < m; ++i) {
+            const double ti = (a[i] - x) * y[i] + (i > 0 ? b[i] * y[i - 1] : 0.0) + (i + 1 < m ? b[i + 1] * y[i + 1] : 0.0);
+            res2 += ti * ti;
+        }
+        return fabs(b[m] * y[m - 1]) + sqrt(res2);
+    }
+
     __device__ __forceinline__ void run() {
         const int n = P.n;
         double* a = L.ab;        // written by rank 0 only, read back by it
@@ -306,6 +341,16 @@ struct Lanczos {
             }
             L.out[1] = 0.5 * (x0 + x1);
             L.out[2] = m;
+            // bounds from the Ritz residuals: lambda_min >= theta_min - r_min
+            // (the eigenvalue within r of theta_min, the smallest one once the
+            // start vector has a component along it; floored at a tenth of
+            // theta_min), lambda_max <= theta_max + r_max
+            const double d = 1e-10 * fmax(fabs(lo), fabs(hi)) + 1e-300;
+            const double rlo = ritz_residual(a, b, m, L.out[0], L.out[0] - d, hl, tl);
+            const double rhi = ritz_residual(a, b, m, L.out[1], L.out[1] + d, hl, tl);
+            L.out[3] = rlo;
+            L.out[0] = fmax(L.out[0] - rlo, 0.1 * L.out[0]);
+            L.out[1] = L.out[1] + rhi;
         }
     }
 

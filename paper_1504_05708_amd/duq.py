@@ -22,7 +22,7 @@ DUQ_OK, DUQ_EINVAL, DUQ_ENOMEM, DUQ_EDEVICE, DUQ_EMAXITER, DUQ_ENUMERIC, DUQ_EAG
 DUQ_EINFEASIBLE = -8
 # outcomes of a solve that still write x and the multipliers
 SOLVE_OUTCOMES = (DUQ_OK, DUQ_EMAXITER, DUQ_EINFEASIBLE)
-F64, F32, BF16 = 0, 1, 2
+F64, F32 = 0, 1
 HOST, DEVICE = 0, 1
 DGM, DFGM = 0, 1
 LAST, AVG = 0, 1
