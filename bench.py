@@ -75,7 +75,8 @@ def parse():
     ap.add_argument("--serve-protocol", action="store_true",
                     help="serve: measure the saturation rate first, then serve at --load-frac of it")
     ap.add_argument("--sat-window", type=float, default=10.0, help="serve: seconds of the saturation run")
-    ap.add_argument("--load-frac", type=float, default=0.8, help="serve: offered share of the saturation rate")
+    ap.add_argument("--load-fracs", default="0.8,0.5,0.25",
+                    help="serve: offered shares of the saturation rate, one run each")
     ap.add_argument("--sparse-n", type=int, default=2_000_000, help="sparse: flows (variables)")
     ap.add_argument("--sparse-p", type=int, default=500_000, help="sparse: links (rows of G)")
     ap.add_argument("--print-source-hash", action="store_true", help="hashes of the profiled kernels' sources")
@@ -703,25 +704,35 @@ def batch_result(a, workload, B, steps, warmup, precision, with_cpu, oracle_samp
 def bench_serve(a):
     """--workload serve: the offered rate --rate for --duration seconds, or
     with --serve-protocol the capacity of one GPU: a saturation run (offered
-    rate far above capacity, --sat-window seconds; the sustained rate is the
-    completions over the span) and then a run at --load-frac of that rate
-    for --duration seconds, whose latencies are the service's own."""
+    rate far above capacity for --sat-window seconds; the sustained rate is
+    the completions over the span the server stayed busy, drain included),
+    then a run of --duration seconds at each fraction in --load-fracs of that
+    rate, whose latencies are the service's own when it keeps up (the drain
+    time after the last arrival shows whether it did)."""
     if not a.serve_protocol:
         print(json.dumps(serve_run(a, a.rate, a.duration)), flush=True)
         return
     sat = serve_run(a, a.rate, a.sat_window)
-    rate = round(a.load_frac * sat["completed_in_window_per_s"], 1)
-    run = serve_run(a, rate, a.duration)
-    run["saturation"] = {"offered_per_s": sat["offered_per_s"],
-                         "sustained_solves_per_s": sat["completed_in_window_per_s"],
-                         "drain_s_after_last_arrival": sat["drain_s_after_last_arrival"],
-                         "window_s": a.sat_window, "requests": sat["config"]["requests"],
-                         "latency_ms": sat["latency_ms"], "solve": sat["solve"]}
-    run["config"]["workload"] = (f"serving at {a.load_frac:.0%} of the saturation rate measured first "
-                                 f"({sat['completed_in_window_per_s']:g}/s completed while {a.rate:g}/s arrived "
-                                 f"for {a.sat_window:g} s): "
-                                 + run["config"]["workload"])
-    print(json.dumps(run), flush=True)
+    loads = []
+    for frac in [float(f) for f in a.load_fracs.split(",")]:
+        rate = round(frac * sat["value"], 1)
+        r = serve_run(a, rate, a.duration)
+        loads.append({"load_frac": frac, "offered_per_s": r["offered_per_s"], "solves_per_s": r["value"],
+                      "drain_s_after_last_arrival": r["drain_s_after_last_arrival"], "latency_ms": r["latency_ms"],
+                      "solve": r["solve"], "requests": r["config"]["requests"]})
+        if len(loads) == 1:
+            line = r
+    line["saturation"] = {"offered_per_s": sat["offered_per_s"], "sustained_solves_per_s": sat["value"],
+                          "completed_in_window_per_s": sat["completed_in_window_per_s"],
+                          "drain_s_after_last_arrival": sat["drain_s_after_last_arrival"],
+                          "window_s": a.sat_window, "requests": sat["config"]["requests"],
+                          "latency_ms": sat["latency_ms"], "solve": sat["solve"]}
+    line["loads"] = loads
+    line["config"]["workload"] = (f"serving at fractions {a.load_fracs} of the sustained rate of a saturation run "
+                                  f"({sat['value']:g}/s: all of {a.rate:g}/s offered for {a.sat_window:g} s, "
+                                  f"completions over the busy span); the top-level figures are those of the first "
+                                  f"fraction: " + line["config"]["workload"])
+    print(json.dumps(line), flush=True)
 
 
 def serve_run(a, rate, duration):
