@@ -582,12 +582,14 @@ def batch_result(a, workload, B, steps, warmup, precision, with_cpu, oracle_samp
         alg += ((r["inner_iters"] + 1) * n * n + (r["outer_iters"] + extra) * p * n + r["gt_rows"] * n + lz) * s_bytes
     achieved = alg / (kern_ms * 1e-3) / 1e9
     if engine == duq.ENGINE_TILE:
-        # matrix-core kernel: algorithmic FP64 flops of the Q, G and G^T products
+        # matrix-core kernel: algorithmic FP64 flops of the Q products (inner
+        # steps + warm start), the G products (one per outer iteration and per
+        # last-iterate solve) and the G^T rows with a nonzero multiplier
         flops = 0.0
         for i, r in enumerate(res):
             n, p = float(ns[i]), float(ps[i])
-            n_gt = r["gt_rows"] / p if p else 0.0
-            flops += 2.0 * n * n * (r["inner_iters"] + 1) + 2.0 * 2.0 * p * n * n_gt
+            flops += (2.0 * n * n * (r["inner_iters"] + 1) + 2.0 * p * n * (r["outer_iters"] + extra)
+                      + 2.0 * n * r["gt_rows"])
         tf = flops / (kern_ms * 1e-3) / 1e12
         tr = (measured_traffic("dfom_tile_kernel_mpc4096_f64.txt", "dfom_tile_kernel")
               if (workload == "mpc" and precision == "f64" and B == 4096) else None)
@@ -595,7 +597,7 @@ def batch_result(a, workload, B, steps, warmup, precision, with_cpu, oracle_samp
                 "frac": round(tf / FP64_MFMA_PEAK_TFS, 4), "traffic": tr, "kernel": "dfom_tile_kernel",
                 "alg_flops_per_launch": flops, "launch_ms": round(kern_ms, 3),
                 "note": "FP64 MFMA 16x16x4; Q held in registers, X through LDS, G through L2; flops of masked (finished) "
-                        "columns and of padding are not counted"}
+                        "columns, of padding and of G^T products skipped for zero multipliers are not counted"}
     else:
         tr = (measured_traffic(f"dfom_batch_kernel_uneven{B}_{precision}.txt", "dfom_batch_kernel")
               if workload == "uneven" else None)
