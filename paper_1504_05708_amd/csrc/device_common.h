@@ -12,18 +12,61 @@ constexpr int kWave = 64;
 constexpr int kMaxWaves = 16;            // blocks of at most 1024 threads
 constexpr int kTlDoubles = 512 * 4;      // short-row G^T v scratch: blockDim (<= 512) x 4
 
-__device__ __forceinline__ double wave_sum(double v) {
-    // xor butterfly: every lane ends with the bitwise-identical total
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+// Lane exchanges of the xor butterfly in VALU registers (no LDS round trip):
+// lanes l and l ^ 32 (l ^ 16) by the row swaps of gfx950, which leave each
+// lane with its own value and its partner's; l ^ 8 by DPP row_ror:8, l ^ 4
+// by row_half_mirror then quad_perm [3,2,1,0], l ^ 2 and l ^ 1 by quad_perm.
+template <int CTRL>
+__device__ __forceinline__ int dpp_lane(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_lane(double v) {
+    const int lo = dpp_lane<CTRL>((int)__double2loint(v)), hi = dpp_lane<CTRL>((int)__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_lane(float v) {
+    return __int_as_float(dpp_lane<CTRL>(__float_as_int(v)));
+}
+__device__ __forceinline__ double swap_sum32(double v) {
+    const unsigned lo = __double2loint(v), hi = __double2hiint(v);
+    const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+}
+__device__ __forceinline__ double swap_sum16(double v) {
+    const unsigned lo = __double2loint(v), hi = __double2hiint(v);
+    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+}
+__device__ __forceinline__ float swap_sum32(float v) {
+    const unsigned u = __float_as_uint(v);
+    const auto a = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    return __uint_as_float(a[0]) + __uint_as_float(a[1]);
+}
+__device__ __forceinline__ float swap_sum16(float v) {
+    const unsigned u = __float_as_uint(v);
+    const auto a = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    return __uint_as_float(a[0]) + __uint_as_float(a[1]);
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+// xor butterfly (offsets 32, 16, ..., 1): every lane ends with the
+// bitwise-identical total, each step adding a lane's value and its
+// partner's.
+template <typename F>
+__device__ __forceinline__ F wave_sum_t(F v) {
+    v = swap_sum32(v);
+    v = swap_sum16(v);
+    v += dpp_lane<0x128>(v);                    // l ^ 8
+    v += dpp_lane<0x1B>(dpp_lane<0x141>(v));    // l ^ 4
+    v += dpp_lane<0x4E>(v);                     // l ^ 2
+    v += dpp_lane<0xB1>(v);                     // l ^ 1
     return v;
 }
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_t(v); }
+__device__ __forceinline__ float wave_sum(float v) { return wave_sum_t(v); }
 
 // Sum K values over the block in a fixed order; every thread receives the
 // totals.  `scratch` holds kMaxWaves*K doubles of LDS.
