@@ -112,6 +112,11 @@ inline void fill_tile_args(A& a, const TileLaunch& t) {
 
 constexpr int kTileMaxN = 128;   // two row tiles of 16 per wave
 size_t tile_lds_bytes(int n);
+// Serving: q, g of the requests in `inst` (device table) gathered into B x n
+// and B x p arrays; X, Lam (B x n, B x p) scattered to the requests' x, lambda.
+hipError_t launch_serve_gather(const ServeInst* inst, int B, int n, int p, double* q, double* g, hipStream_t s);
+hipError_t launch_serve_scatter(const ServeInst* inst, int B, int n, int p, const double* X, const double* Lam,
+                                hipStream_t s);
 hipError_t tile_occupancy(int dtype, size_t shmem, int* blocks_per_cu);
 hipError_t launch_tile(int dtype, int nblocks, size_t shmem, hipStream_t stream, const TileLaunch& t);
 

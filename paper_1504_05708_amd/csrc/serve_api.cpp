@@ -34,6 +34,7 @@ int handle_barrier_error(duq_handle* h, unsigned* flag);
 int handle_outputs(duq_handle* h, double* x, double* lam);
 int resolve_lb_cert(int opt);
 void handle_info(duq_handle* h, double* lam_min, double* lam_max, double* g2, int* engine);
+void handle_params(duq_handle* h, DevParams* par);
 }  // namespace duq
 
 namespace {
@@ -97,6 +98,8 @@ struct Shared {
     const void* G;
     const double *lb, *ub;
     double lam_min, lam_max, g2;
+    DevParams par{};   // derived once at registration
+    bool tile = false; // its requests run on the MFMA tiles (rho = 0, n <= kTileMaxN)
 };
 
 enum { ST_PENDING = 0, ST_ACTIVE = 1, ST_DONE = 2 };
@@ -167,6 +170,8 @@ struct duq_server {
     std::vector<Req*> active;
     void* meta = nullptr;       // device: inst table, order, results, queue
     size_t meta_cap = 0;
+    void* tile_ws = nullptr;    // device: gathered q, g, tile outputs and state
+    size_t tile_ws_cap = 0;
     char* hmeta = nullptr;      // pinned host mirror
     size_t hmeta_cap = 0;
 };
@@ -352,18 +357,30 @@ struct Group {
     size_t o_inst, o_order, o_res, o_queue;
 };
 
+// Requests against one shared system on the MFMA tiles.
+struct TileGroup {
+    int sid;
+    std::vector<Req*> r;
+    size_t o_inst, o_res, o_queue;                  // metadata (and its host mirror)
+    size_t w_q, w_g, w_x, w_l, w_dual, w_prim;       // tile workspace
+};
+
 // One round: launches, state copies, one synchronisation, retirement.
 int round(duq_server* s) {
     std::vector<Req*> act;
+    std::vector<Shared> shs;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         act = s->active;
+        shs = s->shared;
     }
     Group grp[4] = {{DUQ_F64, false, {}, 0, 0, 0, 0}, {DUQ_F64, true, {}, 0, 0, 0, 0},
                     {DUQ_F32, false, {}, 0, 0, 0, 0}, {DUQ_F32, true, {}, 0, 0, 0, 0}};
     std::vector<Req*> large;
+    std::map<int, std::vector<Req*>> by_sys;   // shared system -> its requests for the tiles
     for (Req* r : act) {
         if (r->large) large.push_back(r);
+        else if (r->shared_id >= 0 && shs[r->shared_id].tile && !r->inst.resume) by_sys[r->shared_id].push_back(r);
         else grp[(r->dtype == DUQ_F64 ? 0 : 2) + (batch_short_class(r->dtype, r->n) ? 1 : 0)].r.push_back(r);
     }
     size_t off = 0;
@@ -382,7 +399,37 @@ int round(duq_server* s) {
         gr.o_res = plan(sizeof(BatchResultDev) * B);
         gr.o_queue = plan(sizeof(unsigned));
     }
+    // tile groups: the request table, results and queue with the metadata;
+    // gathered q, g, the outputs and the tile state in the tile workspace
+    std::vector<TileGroup> tgs;
+    size_t woff = 0;
+    auto wplan = [&](size_t b) { size_t o = woff; woff += up(b); return o; };
+    for (auto& kv : by_sys) {
+        TileGroup tg;
+        tg.sid = kv.first;
+        tg.r = kv.second;
+        const Shared& sh = shs[tg.sid];
+        const size_t B = tg.r.size(), n = (size_t)sh.n, pp = (size_t)std::max(sh.p, 1);
+        tg.o_inst = plan(sizeof(ServeInst) * B);
+        tg.o_res = plan(sizeof(BatchResultDev) * B);
+        tg.o_queue = plan(sizeof(unsigned));
+        tg.w_q = wplan(8 * B * n);
+        tg.w_g = wplan(8 * B * pp);
+        tg.w_x = wplan(8 * B * n);
+        tg.w_l = wplan(8 * B * pp);
+        tg.w_dual = wplan(8 * 3 * B * pp);
+        tg.w_prim = wplan(8 * 4 * B * n);
+        tgs.push_back(tg);
+    }
     if (int rc = ensure_meta(s, std::max<size_t>(off, kAlign))) return set_error(rc, "serving metadata");
+    if (woff > s->tile_ws_cap) {
+        if (s->tile_ws) (void)hipFree(s->tile_ws);
+        s->tile_ws = nullptr;
+        s->tile_ws_cap = 0;
+        const size_t cap = std::max(woff, 2 * s->tile_ws_cap);
+        if (hipMalloc(&s->tile_ws, cap) != hipSuccess) return set_error(DUQ_ENOMEM, "serving tile workspace");
+        s->tile_ws_cap = cap;
+    }
     hipError_t e = hipSuccess;
     DevParams par{};
     par.method = s->opts.method;
@@ -434,6 +481,47 @@ int round(duq_server* s) {
         const int nblocks = std::max(1, std::min(B, s->cus * std::max(bpc, 1)));
         e = e ? e : launch_batch(gr.dtype, gr.sh, nblocks, shmem, s->stream, L);
         e = e ? e : hipMemcpyAsync(s->hmeta + gr.o_res, d + gr.o_res, sizeof(BatchResultDev) * B,
+                                   hipMemcpyDeviceToHost, s->stream);
+    }
+    for (TileGroup& tg : tgs) {
+        const Shared& sh = shs[tg.sid];
+        const int B = (int)tg.r.size();
+        ServeInst* hi = (ServeInst*)(s->hmeta + tg.o_inst);
+        for (int j = 0; j < B; ++j) hi[j] = tg.r[j]->inst;
+        std::memset(s->hmeta + tg.o_queue, 0, sizeof(unsigned));
+        char* d = (char*)s->meta;
+        char* w = (char*)s->tile_ws;
+        const ServeInst* di = (const ServeInst*)(d + tg.o_inst);
+        e = e ? e : hipMemcpyAsync(d + tg.o_inst, hi, sizeof(ServeInst) * B, hipMemcpyHostToDevice, s->stream);
+        e = e ? e : hipMemcpyAsync(d + tg.o_queue, s->hmeta + tg.o_queue, sizeof(unsigned), hipMemcpyHostToDevice,
+                                   s->stream);
+        e = e ? e : launch_serve_gather(di, B, sh.n, sh.p, (double*)(w + tg.w_q), (double*)(w + tg.w_g), s->stream);
+        TileLaunch t{};
+        t.B = B;
+        t.n = sh.n;
+        t.p = sh.p;
+        t.Q = sh.Q;
+        t.G = sh.G;
+        t.q = (const double*)(w + tg.w_q);
+        t.g = (const double*)(w + tg.w_g);
+        t.lb = sh.lb;
+        t.ub = sh.ub;
+        t.X = (double*)(w + tg.w_x);
+        t.Lam = (double*)(w + tg.w_l);
+        t.res = d + tg.o_res;
+        t.dual = (double*)(w + tg.w_dual);
+        t.prim = (double*)(w + tg.w_prim);
+        t.par = sh.par;
+        t.lam_min = sh.lam_min;
+        t.lam_max = sh.lam_max;
+        t.g2 = sh.p ? sh.g2 : 0.0;
+        t.queue = (unsigned*)(d + tg.o_queue);
+        int bpc = 0;
+        e = e ? e : tile_occupancy(sh.dtype, tile_lds_bytes(sh.n), &bpc);
+        const int nblocks = std::max(1, std::min((B + 15) / 16, s->cus * std::max(bpc, 1)));
+        e = e ? e : launch_tile(sh.dtype, nblocks, tile_lds_bytes(sh.n), s->stream, t);
+        e = e ? e : launch_serve_scatter(di, B, sh.n, sh.p, t.X, t.Lam, s->stream);
+        e = e ? e : hipMemcpyAsync(s->hmeta + tg.o_res, d + tg.o_res, sizeof(BatchResultDev) * B,
                                    hipMemcpyDeviceToHost, s->stream);
     }
     if (e != hipSuccess) return set_error(DUQ_EDEVICE, std::string("serving launch: ") + hipGetErrorString(e));
@@ -497,6 +585,32 @@ int round(duq_server* s) {
             r->code = to_code(x.status);
             if (x.status == 4)
                 r->err = "the constants of the request (estimated or given) are not finite and positive";
+        }
+    }
+    for (TileGroup& tg : tgs) {   // tile requests end in their round
+        const BatchResultDev* rr = (const BatchResultDev*)(s->hmeta + tg.o_res);
+        for (size_t j = 0; j < tg.r.size(); ++j) {
+            Req* r = tg.r[j];
+            const BatchResultDev& x = rr[j];
+            r->res.outer_iters = x.outer;
+            r->res.inner_iters = x.inner;
+            r->res.gt_rows = x.gt_rows;
+            r->res.f = x.F;
+            r->res.lb_dual = x.LB;
+            r->res.gap = x.F - x.LB;
+            r->res.feas = x.feas;
+            r->res.f64_outer_iters = x.outer;
+            r->res.engine = DUQ_ENGINE_TILE;
+            r->res.lam_min = x.lam_min;
+            r->res.lam_max = x.lam_max;
+            r->res.G_norm2 = x.G2;
+            r->x.resize(r->n);
+            r->lam.resize(r->p);
+            e = hipMemcpy(r->x.data(), r->inst.x, 8 * r->n, hipMemcpyDeviceToHost);
+            if (r->p > 0 && e == hipSuccess) e = hipMemcpy(r->lam.data(), r->inst.lam, 8 * r->p, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return set_error(DUQ_EDEVICE, "result copy");
+            r->code = to_code(x.status);
+            done.push_back(r);
         }
     }
     for (Req* r : large) {
@@ -670,7 +784,13 @@ int duq_register_shared(duq_server* s, const duq_problem* pr, int32_t* id) {
     Shared sh{n, p, pr->dtype, mem, bytes, Q, G, lb, ub, 0, 0, 0};
     int eng;
     handle_info(h, &sh.lam_min, &sh.lam_max, &sh.g2, &eng);
+    handle_params(h, &sh.par);
     duq_destroy(h);
+    // requests against a system the tile kernel can hold run there, 16 to a
+    // tile, each to completion within one round
+    int bpc = 0;
+    sh.tile = s->opts.rho == 0.0 && n <= kTileMaxN &&
+              tile_occupancy(pr->dtype, tile_lds_bytes(n), &bpc) == hipSuccess && bpc >= 1;
     std::lock_guard<std::mutex> lk(s->mu);
     s->shared.push_back(sh);
     *id = (int32_t)s->shared.size() - 1;
@@ -768,6 +888,7 @@ void duq_server_destroy(duq_server* s) {
     for (auto& kv : s->reqs)
         if (kv.second->st) (void)hipHostFree(kv.second->st);
     if (s->meta) (void)hipFree(s->meta);
+    if (s->tile_ws) (void)hipFree(s->tile_ws);
     if (s->hmeta) (void)hipHostFree(s->hmeta);
     if (s->arena_mem) (void)hipFree(s->arena_mem);
     if (s->stream) (void)hipStreamDestroy(s->stream);

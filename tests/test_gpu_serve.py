@@ -70,6 +70,7 @@ def test_served_requests_match_oracle():
         ref = dfom.dfom_solve(qp, dfom.Options(method=dfom.DFGM, eps_out=1e-4, eps_in=1e-8, max_outer=20000,
                                                lam_min=r["lam_min"], lam_max=r["lam_max"], G_norm2=r["G_norm2"]))
         assert rc == duq.DUQ_OK
+        assert r["engine"] == duq.ENGINE_TILE, (b, r)   # a shared system with n <= 128: the MFMA tiles
         assert r["outer_iters"] == ref.outer_iters and r["inner_iters"] == ref.inner_iters, (b, r)
         np.testing.assert_allclose(x, ref.x, rtol=0, atol=1e-7)
 
