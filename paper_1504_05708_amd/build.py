@@ -16,8 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libduq.so")
 
-SOURCES = ["kernels.hip", "batch_kernels.hip", "static_api.hip", "duq_api.cpp", "batch_api.cpp",
-           "serve_api.cpp"]
+SOURCES = ["kernels.hip", "batch_kernels.hip", "serve_kernels.hip", "static_api.hip", "duq_api.cpp",
+           "batch_api.cpp", "serve_api.cpp"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.
 HIP_FLAGS = [
