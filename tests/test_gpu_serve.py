@@ -169,3 +169,25 @@ def test_infeasible_request_is_certified():
     assert rc == duq.DUQ_EINFEASIBLE and r["outer_iters"] < 300
     w = G.T @ lam
     assert np.all(lam >= 0.0) and lam @ g + np.sum(np.minimum(qp.lb * w, qp.ub * w)) > 0.0
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_served_tile_requests_equal_the_shared_batch_bitwise(dt):
+    """Requests against a registered system run on the MFMA tiles: the same
+    bits as duq_solve_batch on the same system with the same constants (one
+    tile there, tiles of the round's requests here)."""
+    print(f"[case] serve tiles vs shared batch dtype={np.dtype(dt).name}", flush=True)
+    sysm = gen.mpc_system(seed=5, N=12)
+    X0, Qlin, Glin = gen.mpc_batch(sysm, 19, seed=55)
+    H, G = sysm.H.astype(dt), sysm.G.astype(dt)
+    with duq.Server(1 << 28, **OPTS) as s:
+        sid = s.register_shared(H, G, sysm.lb, sysm.ub)
+        out = [s.wait(s.submit(q=Qlin[b], g=Glin[b], shared_id=sid)) for b in range(len(Qlin))]
+    c = (out[0][3]["lam_min"], out[0][3]["lam_max"], out[0][3]["G_norm2"])
+    X, Lam, res = duq.solve_batch_shared(H, G, sysm.lb, sysm.ub, Qlin, Glin, constants=c, engine=duq.ENGINE_TILE,
+                                         **{k: v for k, v in OPTS.items() if k != "serve_slice"})
+    for b, (rc, x, lam, r) in enumerate(out):
+        assert rc == duq.DUQ_OK and r["engine"] == duq.ENGINE_TILE, (b, r)
+        assert (r["lam_min"], r["lam_max"], r["G_norm2"]) == c
+        assert r["outer_iters"] == res[b]["outer_iters"] and r["inner_iters"] == res[b]["inner_iters"], b
+        assert np.array_equal(x, X[b]) and np.array_equal(lam, Lam[b]), b
