@@ -139,6 +139,7 @@ struct duq_handle {
     DevWork W{};
     double* xstage = nullptr;
     double* lstage = nullptr;
+    bool ws_borrowed = false;      // ws lent by the caller (not freed here)
     int trace_cap = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int last_records = 0;
@@ -190,7 +191,7 @@ const char* duq_strerror(int code) {
 
 void duq_destroy(duq_handle* h) {
     if (!h) return;
-    if (h->ws) (void)hipFree(h->ws);
+    if (h->ws && !h->ws_borrowed) (void)hipFree(h->ws);
     if (h->dH) (void)hipFree(h->dH);
     if (h->owned_data) (void)hipFree(h->owned_data);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
@@ -335,7 +336,7 @@ extern "C" int duq_max_n(int32_t p, int32_t engine, int32_t* n_max) {
 // duq_setup (Qs null: dense Q and G in `pr`) and duq_setup_csr (compressed-row
 // Q and G, already checked).
 static int setup_impl(const duq_problem* pr, const duq_csr* Qs, const duq_csr* Gs, const duq_options* opts,
-                      void* stream, duq_handle** out) {
+                      void* stream, duq_handle** out, void* lent_ws = nullptr, size_t lent_bytes = 0) {
     if (!out) return fail(DUQ_EINVAL, "null output handle");
     *out = nullptr;
     const bool sparse = Qs != nullptr;
@@ -554,7 +555,15 @@ static int setup_impl(const duq_problem* pr, const duq_csr* Qs, const duq_csr* G
     auto carve = [&](Carve& c) { carve_solver(c, n, p, nb, trace, &h->W, &h->xstage, &h->lstage, sparse); };
     Carve c0;
     carve(c0);
-    if (hipMalloc(&h->ws, c0.off) != hipSuccess) {
+    if (lent_ws) {
+        if (lent_bytes < c0.off) {
+            duq_destroy(h);
+            return fail(DUQ_ENOMEM, "lent workspace of " + std::to_string(lent_bytes) + " bytes, " +
+                                        std::to_string(c0.off) + " needed");
+        }
+        h->ws = lent_ws;
+        h->ws_borrowed = true;
+    } else if (hipMalloc(&h->ws, c0.off) != hipSuccess) {
         duq_destroy(h);
         return fail(DUQ_ENOMEM, "device workspace (" + std::to_string(c0.off) + " bytes)");
     }
@@ -617,6 +626,25 @@ static int setup_impl(const duq_problem* pr, const duq_csr* Qs, const duq_csr* G
 
 extern "C" int duq_setup(const duq_problem* pr, const duq_options* opts, void* stream, duq_handle** out) {
     return setup_impl(pr, nullptr, nullptr, opts, stream, out);
+}
+
+// Internal (serving): bytes of the solver workspace of a dense QP with
+// tracing off on `nblocks` workgroups, and duq_setup on a workspace the
+// caller lends (a block of its arena, at least that many bytes, 256-byte
+// aligned, not freed by duq_destroy).  The constant estimate's Krylov basis
+// is still a temporary allocation of the setup.
+size_t solver_workspace_bytes(int n, int p, int nblocks) {
+    DevWork W;
+    double* xs = nullptr;
+    double* ls = nullptr;
+    Carve c;
+    carve_solver(c, n, p, nblocks, 0, &W, &xs, &ls, false);
+    return c.off;
+}
+
+int setup_lent(const duq_problem* pr, const duq_options* opts, void* stream, void* ws, size_t ws_bytes,
+               duq_handle** out) {
+    return setup_impl(pr, nullptr, nullptr, opts, stream, out, ws, ws_bytes);
 }
 
 extern "C" int duq_setup_csr(const duq_problem* pr, const duq_csr* Q, const duq_csr* G, const duq_options* opts,

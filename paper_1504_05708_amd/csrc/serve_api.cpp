@@ -36,6 +36,9 @@ int resolve_lb_cert(int opt);
 void handle_info(duq_handle* h, double* lam_min, double* lam_max, double* g2, int* engine);
 void handle_params(duq_handle* h, DevParams* par);
 }  // namespace duq
+size_t solver_workspace_bytes(int n, int p, int nblocks);
+int setup_lent(const duq_problem* pr, const duq_options* opts, void* stream, void* ws, size_t ws_bytes,
+               duq_handle** out);
 
 namespace {
 
@@ -188,10 +191,10 @@ size_t footprint(const duq_server* s, int n, int p, int dtype, bool own, bool la
     const int k = (!own || given) ? 0 : std::min(s->k_req, n);
     if (k_out) *k_out = k;
     if (large) {
-        // workspace of the single-QP engine (allocated by duq_setup): vectors,
-        // partial columns of the grid engine and the Lanczos basis
-        const size_t nb = n > DUQ_SERVE_BATCH_NMAX ? (size_t)s->cus : 1;
-        b += up(8 * (20 * (size_t)n + 12 * (size_t)pp + nb * (size_t)n + (size_t)(s->k_req + 1) * n)) + (1u << 20);
+        // the single-QP engine's workspace, lent to its setup from this block
+        // (grid engine above DUQ_SERVE_BATCH_NMAX: one workgroup per CU)
+        const int nb = n > DUQ_SERVE_BATCH_NMAX ? std::min(s->cus, n) : 1;
+        b += up(solver_workspace_bytes(n, p, nb));
     } else {
         b += up(8 * (size_t)n) + up(8 * (size_t)pp);                                            // x lam
         b += up((size_t)batch_slot_bytes(n, p, k));
@@ -260,7 +263,8 @@ int place(duq_server* s, Req* r) {
         duq_options o = s->opts;
         o.trace_outer = 0;
         o.engine = DUQ_ENGINE_AUTO;
-        int rc = duq_setup(&pr, &o, s->stream, &r->h);
+        // the solver workspace is the rest of the request's block
+        int rc = setup_lent(&pr, &o, s->stream, c, r->bytes - (size_t)(c - r->mem), &r->h);
         if (rc) return rc;
         if (hipHostMalloc((void**)&r->st, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
             return set_error(DUQ_ENOMEM, "pinned state");
