@@ -69,17 +69,17 @@ __device__ __forceinline__ void gemv_rows(const T* A, long ld, int rlo, int rhi,
                 const int v = lane + kk * kWave;
                 if (v < nv) {
                     const double* xv = xl + (long)v * V;
+                    // element loads whatever the alignment: in the batch
+                    // kernels they measured faster than 16-byte loads (the
+                    // eight rows' quads constrain register allocation), and
+                    // the same entries are summed in the same order
                     VT a[R];
 #pragma unroll
                     for (int q = 0; q < R; ++q) {
                         if (r0 + q < rhi) {
                             const T* row = A + (long)(r0 + q) * ld;
-                            if (vec) {
-                                a[q] = vload<T, NT>(reinterpret_cast<const VT*>(row) + v);
-                            } else {
 #pragma unroll
-                                for (int e = 0; e < V; ++e) a[q][e] = row[(long)v * V + e];
-                            }
+                            for (int e = 0; e < V; ++e) a[q][e] = row[(long)v * V + e];
                         }
                     }
 #pragma unroll
