@@ -122,33 +122,6 @@ struct Tile {
         }
     }
 
-    // colsum in two halves: publish (wave partials to LDS, then the barrier)
-    // and finish (every lane sums its column), so that independent work can
-    // be issued between the barrier and the reads.
-    template <int K>
-    __device__ __forceinline__ void colsum_publish(double (&v)[K], double* buf) const {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            v[k] += __shfl_xor(v[k], 16, 64);
-            v[k] += __shfl_xor(v[k], 32, 64);
-        }
-        if (grp == 0) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) buf[(w * kTile + col) * K + k] = v[k];
-        }
-        __syncthreads();
-    }
-    template <int K>
-    __device__ __forceinline__ void colsum_finish(double (&v)[K], const double* buf) const {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            double t = buf[col * K + k];
-#pragma unroll
-            for (int ww = 1; ww < kTileWaves; ++ww) t += buf[(ww * kTile + col) * K + k];
-            v[k] = t;
-        }
-    }
-
     // colsum for records longer than the outer buffer: chunks of kTileK with
     // a barrier after each read, so the buffer can be reused at once.
     template <int K>
