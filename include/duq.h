@@ -334,7 +334,10 @@ typedef struct duq_batch {
  * Lam_out (sum p_i, or B x p) are host buffers laid out like q and g; res has
  * B entries (time_ms is the batch's device time).  Returns DUQ_OK when every
  * instance passed its outer test, DUQ_EMAXITER / DUQ_ENUMERIC /
- * DUQ_EINFEASIBLE when one did not (see res[i].status), or an error code.   */
+ * DUQ_EINFEASIBLE when one did not (see res[i].status), or an error code.
+ * The device workspace of a call is kept for the next one on the same device
+ * (a larger call replaces it, a concurrent call allocates its own); it is
+ * held until the process ends.                                              */
 int duq_solve_batch(const duq_batch *batch, const duq_options *opts, void *stream,
                     double *X_out, double *Lam_out, duq_result *res);
 

@@ -41,10 +41,59 @@ int tuned_wpc(int dtype, bool sh, int n_max) {
     return it == g_tune.end() ? 0 : it->second;
 }
 
+// Device workspace of the batched solves, kept per device between calls: a
+// call takes the kept block when it is free and large enough (a larger
+// request replaces it), a call that finds it in use allocates its own.  The
+// block goes back only after the call's stream has drained, so the next call
+// never sees it in use.  It is held until the process ends.
+struct KeptWs {
+    void* p = nullptr;
+    size_t bytes = 0;
+    bool busy = false;
+};
+std::mutex g_ws_mu;
+std::map<int, KeptWs> g_ws;
+
 struct DevBuf {
     void* p = nullptr;
+    int dev = -1;                 // >= 0: the kept block of this device
+    hipStream_t stream = nullptr;
+    hipError_t alloc(size_t bytes, hipStream_t s) {
+        stream = s;
+        int d = 0;
+        hipError_t e = hipGetDevice(&d);
+        if (e != hipSuccess) return e;
+        {
+            std::lock_guard<std::mutex> lk(g_ws_mu);
+            KeptWs& k = g_ws[d];
+            if (!k.busy) {
+                if (k.bytes < bytes) {
+                    if (k.p) (void)hipFree(k.p);
+                    k.p = nullptr;
+                    k.bytes = 0;
+                    if ((e = hipMalloc(&k.p, bytes)) != hipSuccess) {
+                        k.p = nullptr;
+                        return e;
+                    }
+                    k.bytes = bytes;
+                }
+                k.busy = true;
+                p = k.p;
+                dev = d;
+                return hipSuccess;
+            }
+        }
+        return hipMalloc(&p, bytes);
+    }
     ~DevBuf() {
-        if (p) (void)hipFree(p);
+        if (!p) return;
+        if (dev >= 0) {
+            (void)hipStreamSynchronize(stream);
+            std::lock_guard<std::mutex> lk(g_ws_mu);
+            g_ws[dev].busy = false;
+        } else {
+            (void)hipFree(p);
+        }
     }
 };
 
@@ -142,7 +191,7 @@ int solve_shared_tiles(const duq_batch* b, const duq_options* o, hipStream_t s, 
     const size_t o_dual = plan(8 * 3 * (size_t)B * pp);
     const size_t o_prim = plan(8 * 4 * (size_t)B * n);
     const size_t o_q = plan(256);
-    BTRY(hipMalloc(&ws.p, off));
+    BTRY(ws.alloc(off, s));
     char* w = (char*)ws.p;
     BTRY(hipMemsetAsync(w + o_q, 0, 256, s));
     t.B = B;
@@ -398,7 +447,7 @@ extern "C" int duq_solve_batch(const duq_batch* b, const duq_options* o, void* s
     const size_t o_meta = plan((sizeof(int) * 3 + sizeof(long long) * 4) * B);
     const size_t o_c = plan(8 * 3 * nc);
     const size_t o_q = plan(256);
-    BTRY(hipMalloc(&ws.p, off));
+    BTRY(ws.alloc(off, s));
     char* w = (char*)ws.p;
     int* d_order = (int*)(w + o_meta);
     int* d_n = d_order + B;
