@@ -204,3 +204,29 @@ def test_tuned_launch_shape_leaves_results_unchanged(tmp_path):
         assert [r["inner_iters"] for r in res] == [r["inner_iters"] for r in rw]
     duq.tune_save(str(tmp_path / "tune.txt"))
     assert (tmp_path / "tune.txt").read_text().strip()
+
+
+def test_concurrent_batches_give_the_same_bits():
+    """duq_solve_batch keeps its device workspace between calls: calls from
+    two host threads at once (one takes the kept block, the other allocates
+    its own) give the bits of a call made alone."""
+    import threading
+    print("[case] batch calls from two threads", flush=True)
+    ub = gen.uneven_batch(B=24, seed=77, n_lo=20, n_hi=300, dtype=np.float64)
+    kw = dict(method=duq.DFGM, eps_out=1e-4, eps_in=1e-8, max_outer=20000)
+    X0, L0, r0 = duq.solve_batch_uneven(ub, **kw)
+    out = [None, None, None]
+
+    def run(i):
+        out[i] = duq.solve_batch_uneven(ub, **kw)
+
+    th = [threading.Thread(target=run, args=(i,)) for i in range(3)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=120)
+    for i, o in enumerate(out):
+        assert o is not None, i
+        X, L, r = o
+        assert np.array_equal(X, X0) and np.array_equal(L, L0), i
+        assert [q["inner_iters"] for q in r] == [q["inner_iters"] for q in r0], i
